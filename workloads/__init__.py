@@ -1,0 +1,244 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the bench.
+
+This module describes problems (block layout, face coordinates, boundary
+conditions, the homogeneous z direction) and draws right-hand sides.  It holds
+none of the solver's arithmetic: no operator, transform, projection or solve.
+Both the oracle and the HIP path receive exactly the arrays built here.
+
+Problem model (the paper's problem statement, Sec. 3.1 and Table 2):
+  * the x-y cross-section is a set of logically rectangular blocks given in
+    index space by inclusive corners ``lo``/``hi`` (cells = hi - lo + 1), with
+    physical face coordinates ``xf`` (nx+1) and ``yf`` (ny+1) per block;
+  * every block face is Dirichlet, Neumann, connected to the block that touches
+    it in index space, or periodic (cyclic connection);
+  * z is uniform with ``nz`` cells on ``[0, lz)`` and a boundary-condition pair
+    at its two ends (Table 1 rows, plus Dirichlet-Neumann).
+Unknowns are cell-centred; the packed field stores block after block, each in
+C order ``(nz, ny, nx)`` (x fastest).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+# Face / end conditions.  Values are part of the C ABI as well.
+DIRICHLET = 1
+NEUMANN = 2
+CONNECT = 3
+PERIODIC = 4
+
+BC_NAMES = {DIRICHLET: "D", NEUMANN: "N", CONNECT: "C", PERIODIC: "P"}
+
+# The five valid conditions pairs along a direction (lower end, upper end).
+PAIRS = {
+    "PP": (PERIODIC, PERIODIC),
+    "NN": (NEUMANN, NEUMANN),
+    "DD": (DIRICHLET, DIRICHLET),
+    "ND": (NEUMANN, DIRICHLET),
+    "DN": (DIRICHLET, NEUMANN),
+}
+PAIR_CYCLE = ["PP", "NN", "DD", "ND", "DN"]
+
+
+@dataclasses.dataclass
+class Block:
+    lo: Tuple[int, int]
+    hi: Tuple[int, int]
+    xf: np.ndarray
+    yf: np.ndarray
+    bc: Tuple[int, int, int, int]  # (-x, +x, -y, +y)
+
+    @property
+    def nx(self) -> int:
+        return self.hi[0] - self.lo[0] + 1
+
+    @property
+    def ny(self) -> int:
+        return self.hi[1] - self.lo[1] + 1
+
+
+@dataclasses.dataclass
+class Problem:
+    blocks: List[Block]
+    nz: int
+    lz: float
+    zbc: Tuple[int, int]
+    name: str = ""
+
+    @property
+    def ncells(self) -> int:
+        return self.nz * sum(b.nx * b.ny for b in self.blocks)
+
+    def block_offsets(self) -> List[int]:
+        off = [0]
+        for b in self.blocks:
+            off.append(off[-1] + self.nz * b.nx * b.ny)
+        return off
+
+    def split(self, flat: np.ndarray) -> List[np.ndarray]:
+        """Views of a packed field as one (nz, ny, nx) array per block."""
+        off = self.block_offsets()
+        return [flat[off[i]:off[i + 1]].reshape(self.nz, b.ny, b.nx)
+                for i, b in enumerate(self.blocks)]
+
+
+# ---------------------------------------------------------------------------
+# Face coordinates.  Hyperbolic-tangent clustering (Sec. 3.1, Table 2 caption:
+# type 0 clusters at both ends, -1 / +1 at the lower / upper end, factor 0 is
+# uniform).  The paper does not print the mapping; the profile used here is
+# x(s) = (1 + tanh(a (s - 1/2)) / tanh(a / 2)) / 2 for two-sided clustering.
+# ---------------------------------------------------------------------------
+
+def faces(n: int, lmin: float, lmax: float, gtype: int = 0, factor: float = 0.0) -> np.ndarray:
+    s = np.arange(n + 1, dtype=np.float64) / n
+    a = float(factor)
+    if a == 0.0:
+        x = s
+    elif gtype == 0:
+        x = 0.5 * (1.0 + np.tanh(a * (s - 0.5)) / math.tanh(0.5 * a))
+    elif gtype == -1:
+        x = 1.0 + np.tanh(a * (s - 1.0)) / math.tanh(a)
+    elif gtype == 1:
+        x = np.tanh(a * s) / math.tanh(a)
+    else:
+        raise ValueError("grid type must be 0, -1 or +1")
+    x[0], x[-1] = 0.0, 1.0
+    return lmin + (lmax - lmin) * x
+
+
+def box(nx: int, ny: int, nz: int, lx: float, ly: float, lz: float,
+        xpair: str, ypair: str, zpair: str,
+        xfactor: float = 0.0, yfactor: float = 0.0, name: str = "") -> Problem:
+    """One block on [0,lx] x [0,ly] x [0,lz) with the given condition pairs."""
+    bx, by = PAIRS[xpair], PAIRS[ypair]
+    blk = Block(lo=(1, 1), hi=(nx, ny),
+                xf=faces(nx, 0.0, lx, 0, xfactor if xpair != "PP" else 0.0),
+                yf=faces(ny, 0.0, ly, 0, yfactor if ypair != "PP" else 0.0),
+                bc=(bx[0], bx[1], by[0], by[1]))
+    return Problem(blocks=[blk], nz=nz, lz=lz, zbc=PAIRS[zpair], name=name)
+
+
+# ---------------------------------------------------------------------------
+# Workloads.  Shapes follow the paper's cases: the single-box cavity (Sec. 4),
+# the three-block L-shaped duct (Sec. 4.2) and batches / streams of boxes.
+# ---------------------------------------------------------------------------
+
+def config1() -> Problem:
+    """32^3 box on [0,1]^3: Dirichlet x, Neumann y, periodic z."""
+    return box(32, 32, 32, 1.0, 1.0, 1.0, "DD", "NN", "PP", name="box32_DD_NN_PP")
+
+
+def lshape(n: int = 256, nz: int = 512, factor: float = 1.5, lz: float = 2.0) -> Problem:
+    """Three-block L-shaped cross-section: A=[0,1]^2, B=[1,2]x[0,1], C=[0,1]x[1,2].
+
+    n x n cells per block, y clustered two-sided (tanh) toward the walls of
+    each block, x uniform, Neumann on every outer wall, periodic z.
+    """
+    N, C = NEUMANN, CONNECT
+    xa = faces(n, 0.0, 1.0)
+    xb = faces(n, 1.0, 2.0)
+    ya = faces(n, 0.0, 1.0, 0, factor)
+    yc = faces(n, 1.0, 2.0, 0, factor)
+    A = Block((1, 1), (n, n), xa, ya, (N, C, N, C))
+    B = Block((n + 1, 1), (2 * n, n), xb, ya.copy(), (C, N, N, N))
+    Cb = Block((1, n + 1), (n, 2 * n), xa.copy(), yc, (N, N, C, N))
+    return Problem(blocks=[A, B, Cb], nz=nz, lz=lz, zbc=PAIRS["PP"],
+                   name=f"lshape3x{n}^2x{nz}_stretch{factor}")
+
+
+def config2() -> Problem:
+    return lshape(256, 512, 1.5, 2.0)
+
+
+def config3() -> Problem:
+    """512 x 512 x 1024 box on [0,1]x[0,1]x[0,2]: Dirichlet x, Neumann y, Neumann z."""
+    return box(512, 512, 1024, 1.0, 1.0, 2.0, "DD", "NN", "NN", name="box512x512x1024_DD_NN_NN")
+
+
+H_ISO = 1.0 / 128.0  # isotropic base spacing of the batched and served boxes
+
+
+def config4(count: int = 64) -> List[Problem]:
+    """Batch of boxes of uneven size with the condition pairs cycled per axis."""
+    seeds = np.random.SeedSequence(4).spawn(count)
+    out = []
+    xy_choices = np.arange(64, 385, 32)
+    z_choices = np.arange(64, 257, 32)
+    for i, ss in enumerate(seeds):
+        rng = np.random.default_rng(ss)
+        nx = int(rng.choice(xy_choices))
+        ny = int(rng.choice(xy_choices))
+        nz = int(rng.choice(z_choices))
+        zp = PAIR_CYCLE[i % 5]
+        xp = PAIR_CYCLE[(i // 5) % 5]
+        yp = PAIR_CYCLE[(i // 25 + i) % 5]
+        out.append(box(nx, ny, nz, nx * H_ISO, ny * H_ISO, nz * H_ISO, xp, yp, zp,
+                       name=f"batch{i}_{nx}x{ny}x{nz}_{xp}{yp}{zp}"))
+    return out
+
+
+def _log_uniform16(rng, lo=32, hi=512) -> int:
+    v = math.exp(rng.uniform(math.log(lo), math.log(hi)))
+    return int(min(hi, max(lo, 16 * round(v / 16))))
+
+
+@dataclasses.dataclass
+class Request:
+    problem: Problem
+    arrival_s: float
+    seed: int
+
+
+def config5(count: int = 1000, rate_per_s: float = 100.0, seed: int = 5,
+            max_cells: int | None = None) -> List[Request]:
+    """Poisson-process stream of solve requests (exponential gaps at ``rate_per_s``).
+
+    Each of nx, ny, nz is log-uniform in [32, 512] rounded to a multiple of 16,
+    every axis draws its condition pair uniformly from the five kinds, and
+    non-periodic x / y axes are clustered two-sided with a factor in [1, 2].
+    ``max_cells`` (optional) redraws requests larger than that many cells.
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    i = 0
+    while len(out) < count:
+        t += rng.exponential(1.0 / rate_per_s)
+        nx, ny, nz = (_log_uniform16(rng) for _ in range(3))
+        xp, yp, zp = (PAIR_CYCLE[int(rng.integers(5))] for _ in range(3))
+        a = float(rng.uniform(1.0, 2.0))
+        b = float(rng.uniform(1.0, 2.0))
+        req_seed = int(rng.integers(2**31 - 1))
+        if max_cells is not None and nx * ny * nz > max_cells:
+            continue
+        p = box(nx, ny, nz, nx * H_ISO, ny * H_ISO, nz * H_ISO, xp, yp, zp,
+                xfactor=a, yfactor=b, name=f"req{i}_{nx}x{ny}x{nz}_{xp}{yp}{zp}")
+        out.append(Request(problem=p, arrival_s=t, seed=req_seed))
+        i += 1
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Right-hand sides: raw samples only (no compatibility projection here).
+# ---------------------------------------------------------------------------
+
+def rhs(problem: Problem, seed: int, dist: str = "uniform") -> np.ndarray:
+    """Packed float64 rhs, block after block in block order, each (nz, ny, nx)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for b in problem.blocks:
+        shape = (problem.nz, b.ny, b.nx)
+        if dist == "uniform":
+            parts.append(rng.uniform(-1.0, 1.0, size=shape).ravel())
+        elif dist == "normal":
+            parts.append(rng.standard_normal(size=shape).ravel())
+        else:
+            raise ValueError(dist)
+    return np.concatenate(parts)
+
+
+CONFIG_SEEDS = {1: 1, 2: 2, 3: 3, 4: 4, 5: 5}
+CONFIG_DIST = {1: "uniform", 2: "normal", 3: "uniform", 4: "uniform", 5: "uniform"}
