@@ -1,0 +1,243 @@
+/*
+ * mbp.h -- C ABI of the multi-block FFT-accelerated Poisson solver (gfx950).
+ *
+ * Problem (paper Sec. 2, Eqs. (8)-(9); Sec. 3.1, Table 2): the cell-centred
+ * second-order finite-volume Laplacian L_h p = f on a multi-block x-y
+ * cross-section (logically rectangular blocks, spacing free to vary in x and
+ * y) extruded along a uniform z direction with nz cells.  Along z the field is
+ * expanded in the eigenfunctions of Table 1 (periodic, Neumann-Neumann,
+ * Dirichlet-Dirichlet, Neumann-Dirichlet, plus Dirichlet-Neumann), which
+ * splits the 3D system into nz independent 2D Helmholtz systems
+ *     (A_2D + lambda_q / dz^2) phat_q = fhat_q          (Eq. (9))
+ * solved here by geometric-multigrid V-cycles, then transformed back
+ * (Algorithm 1).
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns an int status: MBP_OK (0) or a negative MBP_ERR_*.
+ *     Nothing throws across this interface.  mbp_status_string() names codes.
+ *   - Fields (rhs, p) are ONE packed float64 buffer: block after block in the
+ *     order given to mbp_plan_create, each block in C order (nz, ny, nx), x
+ *     fastest.  mbp_plan_layout() returns the offsets.
+ *   - Pointers named *_dev are device pointers on the plan's HIP device; all
+ *     other pointers are host pointers.  Descriptors are copied at plan
+ *     creation; the caller may free them afterwards.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Homogeneous boundary conditions only (inhomogeneous data belongs in the
+ *     rhs).  Unknowns are cell centred; a Dirichlet / Neumann face holds p = 0 /
+ *     dp/dn = 0 on the face (staggered conditions of Table 1).
+ */
+#ifndef MBP_H
+#define MBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define MBP_OK                 0
+#define MBP_PENDING            1   /* server ticket not finished yet */
+#define MBP_ERR_INVALID       -1   /* bad descriptor / argument */
+#define MBP_ERR_NOMEM         -2   /* device or host allocation failed */
+#define MBP_ERR_HIP           -3   /* a HIP runtime call failed */
+#define MBP_ERR_NOT_CONVERGED -4   /* max_cycles reached; p holds the last iterate */
+#define MBP_ERR_NONFINITE     -5   /* rhs holds NaN or Inf */
+#define MBP_ERR_INCOMPATIBLE  -6   /* singular problem, rhs not compatible, no projection asked */
+#define MBP_ERR_BUSY          -7   /* plan already has a solve in flight */
+#define MBP_ERR_TOO_LARGE     -8   /* request footprint exceeds the server budget */
+#define MBP_ERR_NO_DEVICE     -9   /* no HIP device available */
+
+/* ---- face / end conditions (Sec. 3.1: Dirichlet, Neumann, block-block
+ *      connectivity; periodic = cyclic connectivity) ---------------------- */
+#define MBP_DIRICHLET 1
+#define MBP_NEUMANN   2
+#define MBP_CONNECT   3   /* joined to the block touching this face in index space */
+#define MBP_PERIODIC  4   /* joined cyclically to the opposite PERIODIC face */
+
+/* ---- options ------------------------------------------------------------ */
+#define MBP_FP64  0       /* every V-cycle in float64 */
+#define MBP_MIXED 1       /* float32 V-cycles inside float64 iterative refinement */
+
+#define MBP_PROJECT_RHS 1 /* singular problems: remove the volume-weighted mean of rhs */
+#define MBP_WARM_START  2 /* p_dev holds the initial guess (Sec. 3.3.1: latest solution) */
+#define MBP_RETIRE      4 /* retire each z mode as soon as it converges (else lockstep) */
+
+/* One block of the x-y cross-section (Table 2: lo / hi in index space,
+ * inclusive, cells = hi - lo + 1; physical face coordinates).
+ *   lo, hi : index-space corners (x, y).
+ *   xf, yf : host arrays of nx+1 / ny+1 increasing face coordinates.
+ *   bc     : condition of the faces -x, +x, -y, +y (MBP_DIRICHLET ...).
+ * A CONNECT face must touch exactly one block over exactly the same
+ * tangential index range, and both sides must carry the same face
+ * coordinates (the congruence rule of Sec. 3.1).  A PERIODIC face on the
+ * lower side joins the PERIODIC upper face of the block with the same
+ * tangential range (itself for a single block). */
+typedef struct {
+    int32_t lo[2];
+    int32_t hi[2];
+    const double* xf;
+    const double* yf;
+    int32_t bc[4];
+} mbp_block_desc;
+
+/* The homogeneous (synthesis) direction: nz uniform cells on [0, lz) (the
+ * grid must be uniform along it, Sec. 2).  nz must be even (Table 1).
+ * (bc_lo, bc_hi) is one of (P,P), (N,N), (D,D), (N,D), (D,N). */
+typedef struct {
+    int32_t nz;
+    double lz;
+    int32_t bc_lo;
+    int32_t bc_hi;
+} mbp_synth_desc;
+
+/* Solver options.  Pass NULL for the defaults in brackets.
+ *   precision  MBP_FP64 | MBP_MIXED                              [MBP_FP64]
+ *   nu1, nu2   red-black Gauss-Seidel sweeps before / after the
+ *              coarse-grid correction                            [1, 1]
+ *   max_cycles cap on V-cycles (or refinement steps)             [60]
+ *   flags      default solve flags OR-ed into each solve          [0] */
+typedef struct {
+    int32_t precision;
+    int32_t nu1, nu2;
+    int32_t max_cycles;
+    int32_t flags;
+} mbp_options;
+
+/* Per-solve report (caller-owned).
+ *   status          MBP_OK or the asynchronous error of this solve
+ *   cycles          V-cycles (refinement steps) taken by the slowest mode
+ *   rel_residual    max over modes of ||rhat_q|| / ||fhat_q|| at exit; since
+ *                   the transforms are orthonormal this bounds the 3D
+ *                   relative residual ||f - L_h p|| / ||f||
+ *   removed_mean    volume-weighted mean removed from rhs (singular, projected)
+ *   cycles_per_mode optional caller array of nz ints, or NULL
+ *   t_ms            [0] forward transform, [1] multigrid, [2] inverse, [3] total
+ *                   (filled only when the solve is timed, else 0) */
+typedef struct {
+    int32_t status;
+    int32_t cycles;
+    double rel_residual;
+    double removed_mean;
+    int32_t* cycles_per_mode;
+    double t_ms[4];
+} mbp_solve_info;
+
+/* Host-side summary of a validated problem (mbp_plan_check). */
+typedef struct {
+    int64_t ncells;          /* total cells nz * sum(nx*ny) */
+    int32_t nlevels;         /* multigrid levels of the x-y plane */
+    int32_t coarse_cells;    /* cells of the coarsest plane (dense solve) */
+    int32_t singular;        /* 1 if no Dirichlet condition anywhere */
+    int32_t nblocks;
+    int64_t workspace_bytes; /* device bytes the plan allocates (FP64 + FP32 work) */
+    int32_t nbr[64][4];      /* neighbour block per face (first 64 blocks; -1 = wall) */
+} mbp_plan_summary;
+
+typedef struct mbp_plan mbp_plan;
+typedef struct mbp_server mbp_server;
+
+/* Static text for a status code. */
+const char* mbp_status_string(int status);
+
+/* ABI version (major*100 + minor). */
+int mbp_version(void);
+
+/* Face coordinates of a hyperbolic-tangent clustered 1D grid (Sec. 3.1,
+ * Table 2 caption: type 0 clusters at both ends, -1 / +1 at the lower /
+ * upper end, factor 0 is uniform).  Writes n+1 faces into faces_out (host,
+ * caller-owned) from lmin to lmax.  MBP_ERR_INVALID for n < 1, lmax <= lmin,
+ * an unknown type or a negative factor. */
+int mbp_grid_tanh(int n, double lmin, double lmax, int type, double factor, double* faces_out);
+
+/* Validate a problem and describe the plan it would build, on the host only
+ * (no HIP call, no allocation on the device).  Same errors as
+ * mbp_plan_create's validation; out may be NULL. */
+int mbp_plan_check(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* z,
+                   const mbp_options* opt, mbp_plan_summary* out);
+
+/* Build a plan on the current HIP device: validation, connectivity, grid
+ * metrics per multigrid level, modal shifts lambda_q / dz^2, transform
+ * tables, the coarsest-level eigen-decomposition, device workspace.
+ * Blocking.  The plan owns its device memory.  Errors: MBP_ERR_INVALID
+ * (odd or < 2 nz, invalid pair, non-congruent or partial interface, a face
+ * with two neighbours, overlapping blocks, bad faces), MBP_ERR_NOMEM,
+ * MBP_ERR_HIP, MBP_ERR_NO_DEVICE. */
+int mbp_plan_create(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* z,
+                    const mbp_options* opt, mbp_plan** out);
+
+/* Layout query.  block_offsets (nblocks+1 int64, may be NULL): element
+ * offsets of each block in the packed field; workspace_bytes and singular
+ * may be NULL. */
+int mbp_plan_layout(const mbp_plan* plan, int64_t* block_offsets, size_t* workspace_bytes,
+                    int* singular);
+
+/* Solve L_h p = rhs (Algorithm 1) to a relative residual rtol.
+ *   rhs_dev  packed float64 device field, read only.
+ *   p_dev    packed float64 device field, written (read first if
+ *            MBP_WARM_START).  May not alias rhs_dev.
+ *   rtol     per-mode stopping rule ||rhat_q|| <= rtol * ||fhat_q||, which
+ *            implies ||f - L_h p|| <= rtol * ||f||.  Must be > 0.
+ *   flags    MBP_PROJECT_RHS | MBP_WARM_START | MBP_RETIRE, OR-ed with the
+ *            plan's default flags.
+ * The work is ordered on `stream`; the call returns when the solve has
+ * finished (it reads convergence data back to decide when to stop) and
+ * info (optional) is then valid.  One solve at a time per plan
+ * (MBP_ERR_BUSY otherwise).  Returns the same status as info->status. */
+int mbp_solve(mbp_plan* plan, const double* rhs_dev, double* p_dev, double rtol, int flags,
+              void* stream, mbp_solve_info* info);
+
+/* Many independent solves in one call.  All z modes of all problems are put
+ * on one device work list; converged modes are retired on the device and the
+ * whole multigrid loop is replayed from one captured HIP graph per call
+ * signature.  Plans may differ in size and conditions and must be distinct.
+ * Returns MBP_OK if every item converged, else the first failing item's
+ * status; infos (optional, count entries) hold the per-item reports. */
+int mbp_solve_batch(mbp_plan* const* plans, const double* const* rhs_dev, double* const* p_dev,
+                    int count, double rtol, int flags, void* stream, mbp_solve_info* infos);
+
+/* Building blocks of the solve, exposed for checking and for callers that
+ * compose their own pipelines.  All are stream-ordered and asynchronous.
+ *   mbp_forward_transform: fhat = T^T f along z for every x-y cell; modal
+ *     layout is plane-major: mode q occupies [q*P, (q+1)*P) with P the cells
+ *     of one x-y plane, blocks packed inside a plane in block order, each
+ *     (ny, nx).  Orthonormal transforms (Table 1 kinds, scaled to theta = 1).
+ *   mbp_inverse_transform: the inverse map, modal -> packed field.
+ *   mbp_apply_operator: out = L_h p on the packed field (float64).
+ *   mbp_modal_shift: writes the nz shifts lambda_q / dz^2 (host array). */
+int mbp_forward_transform(mbp_plan* plan, const double* f_dev, double* fhat_dev, void* stream);
+int mbp_inverse_transform(mbp_plan* plan, const double* phat_dev, double* p_dev, void* stream);
+int mbp_apply_operator(mbp_plan* plan, const double* p_dev, double* out_dev, void* stream);
+int mbp_modal_shift(const mbp_plan* plan, double* shift_host);
+
+/* Release the plan's device memory.  The caller ensures no work is in
+ * flight on it.  NULL is ignored. */
+void mbp_plan_destroy(mbp_plan* plan);
+
+/* ---- serving loop ------------------------------------------------------- */
+/* A server admits solve requests of any size and conditions, keeps plans
+ * (hierarchies, tables, workspaces) resident in an LRU cache keyed by the
+ * descriptor, and runs up to `slots` requests concurrently on their own HIP
+ * streams: a request that arrives while others run starts as soon as a slot
+ * and `hbm_budget` bytes of plan memory are free (continuous batching).
+ *   mbp_server_create: opt may be NULL.  slots in [1, 64].
+ *   mbp_server_submit: rhs_dev / p_dev stay owned by the caller and must stay
+ *     valid until the ticket completes; returns MBP_ERR_TOO_LARGE when the
+ *     request alone exceeds the budget, MBP_ERR_INVALID for a bad problem.
+ *   mbp_server_poll: MBP_PENDING, or the request's final status with info
+ *     filled; latency_ms (optional) = completion - submission, wall clock.
+ *   mbp_server_wait: blocks until the ticket completes, then as poll.
+ *   mbp_server_destroy: waits for all work, frees every cached plan. */
+int mbp_server_create(size_t hbm_budget, int slots, const mbp_options* opt, mbp_server** out);
+int mbp_server_submit(mbp_server* s, const mbp_block_desc* blocks, int nblocks,
+                      const mbp_synth_desc* z, const double* rhs_dev, double* p_dev,
+                      double rtol, int flags, uint64_t* ticket);
+int mbp_server_poll(mbp_server* s, uint64_t ticket, mbp_solve_info* info, double* latency_ms);
+int mbp_server_wait(mbp_server* s, uint64_t ticket, mbp_solve_info* info, double* latency_ms);
+void mbp_server_destroy(mbp_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBP_H */

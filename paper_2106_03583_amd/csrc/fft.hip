@@ -1,0 +1,380 @@
+// Real-to-real transforms along the homogeneous z direction (Algorithm 1,
+// first and last loops; Table 1 kinds).  Every kind is reduced to one
+// complex FFT of length m = n/2 per z column:
+//   periodic  -> discrete Hartley transform from the half-length real DFT;
+//   N-N       -> DCT-II by Makhoul's even/odd reordering (inverse DCT-III);
+//   D-D       -> DST-II as the DCT-II of (-1)^j x read backwards (DST-III);
+//   N-D       -> DCT-IV with the quarter-wave pre/post twiddles (self-inverse);
+//   D-N       -> DST-IV as (-1)^q DCT-IV of x reversed (self-inverse).
+// All transforms are orthonormal.  The complex FFT is a mixed-radix Stockham
+// autosort held in LDS; a workgroup transforms W neighbouring columns, whose
+// z rows are read and written as contiguous W-element segments.
+#include "internal.h"
+
+namespace mbp {
+
+struct FFTArgs {
+    int n, m, kind, W, cs;
+    int nstage;
+    int radix[16];
+    const double* tw;     // e^{-2 pi i t / m}, t < m
+    const double* twn;    // e^{-2 pi i k / n}, k <= m
+    const double* post;   // e^{-i pi k / (2n)}, k <= n
+    const double* pre4;   // e^{-i pi (4k+1) / (4n)}, k < m
+    const double* post4;  // e^{-i pi k / n}, k < m
+};
+
+struct FTile {
+    long long in_base, out_base;  // element offsets of column 0 of the tile
+    int in_stride, out_stride;    // distance between consecutive z rows
+    int ncol;                     // valid columns (<= W)
+    int pad;
+};
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 ld2(const double* t, int k) { return make_double2(t[2 * k], t[2 * k + 1]); }
+
+// XCD-aware mapping: workgroups are dispatched round-robin over the 8 XCDs;
+// give each XCD one contiguous range of tiles so neighbouring tiles share an L2.
+__device__ __forceinline__ int xcd_remap(int g, int n) {
+    int x = g & 7, l = g >> 3;
+    int per = n >> 3, rem = n & 7;
+    return x * per + min(x, rem) + l;
+}
+
+// One Stockham stage of radix R over W columns held column-major in LDS
+// (column stride cs complex values).  Reads all inputs into registers before
+// a barrier, then writes the outputs, so the stage runs in place.
+template <int R, int BPT>
+__device__ void stage(double2* z, int cs, int m, int W, int Ns, const double* tw) {
+    const int nbf = m / R;
+    const int total = W * nbf;
+    double2 v[BPT][R];
+    int dst[BPT];
+#pragma unroll
+    for (int t = 0; t < BPT; ++t) {
+        int b = threadIdx.x + t * blockDim.x;
+        dst[t] = -1;
+        if (b < total) {
+            int w = b / nbf, j = b - w * nbf;
+            int k = j % Ns;
+            const double2* col = z + w * cs;
+            int step = m / (Ns * R);  // twiddle index stride
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double2 x = col[j + r * nbf];
+                if (r > 0 && k > 0) x = cmul(x, ld2(tw, (k * r * step) % m));
+                v[t][r] = x;
+            }
+            // DFT of length R with the roots e^{-2 pi i r s / R} = tw[(r s mod R) * m / R]
+            double2 y[R];
+#pragma unroll
+            for (int s = 0; s < R; ++s) {
+                double2 acc = v[t][0];
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    int e = (r * s) % R;
+                    double2 rt = ld2(tw, e * (m / R));
+                    double2 pr = cmul(v[t][r], rt);
+                    acc.x += pr.x;
+                    acc.y += pr.y;
+                }
+                y[s] = acc;
+            }
+#pragma unroll
+            for (int s = 0; s < R; ++s) v[t][s] = y[s];
+            dst[t] = w * cs + (j / Ns) * Ns * R + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < BPT; ++t) {
+        if (dst[t] < 0) continue;
+#pragma unroll
+        for (int r = 0; r < R; ++r) z[dst[t] + r * Ns] = v[t][r];
+    }
+    __syncthreads();
+}
+
+template <int R>
+__device__ void stage_dispatch(double2* z, int cs, int m, int W, int Ns, const double* tw) {
+    const int total = W * (m / R);
+    const int bpt = (total + blockDim.x - 1) / blockDim.x;
+    if constexpr (R > 8) {
+        stage<R, 1>(z, cs, m, W, Ns, tw);  // the host keeps W * m / R <= 256 here
+    } else {
+        if (bpt <= 1) stage<R, 1>(z, cs, m, W, Ns, tw);
+        else if (bpt <= 2) stage<R, 2>(z, cs, m, W, Ns, tw);
+        else stage<R, 4>(z, cs, m, W, Ns, tw);
+    }
+}
+
+__device__ void fft_columns(double2* z, int cs, const FFTArgs& a) {
+    int Ns = 1;
+    for (int s = 0; s < a.nstage; ++s) {
+        int R = a.radix[s];
+        switch (R) {
+            case 2: stage_dispatch<2>(z, cs, a.m, a.W, Ns, a.tw); break;
+            case 3: stage_dispatch<3>(z, cs, a.m, a.W, Ns, a.tw); break;
+            case 4: stage_dispatch<4>(z, cs, a.m, a.W, Ns, a.tw); break;
+            case 5: stage_dispatch<5>(z, cs, a.m, a.W, Ns, a.tw); break;
+            case 7: stage_dispatch<7>(z, cs, a.m, a.W, Ns, a.tw); break;
+            case 8: stage_dispatch<8>(z, cs, a.m, a.W, Ns, a.tw); break;
+            case 11: stage_dispatch<11>(z, cs, a.m, a.W, Ns, a.tw); break;
+            case 13: stage_dispatch<13>(z, cs, a.m, a.W, Ns, a.tw); break;
+            case 17: stage_dispatch<17>(z, cs, a.m, a.W, Ns, a.tw); break;
+            case 19: stage_dispatch<19>(z, cs, a.m, a.W, Ns, a.tw); break;
+            case 23: stage_dispatch<23>(z, cs, a.m, a.W, Ns, a.tw); break;
+            case 29: stage_dispatch<29>(z, cs, a.m, a.W, Ns, a.tw); break;
+            case 31: stage_dispatch<31>(z, cs, a.m, a.W, Ns, a.tw); break;
+            default: break;  // rejected on the host
+        }
+        Ns *= R;
+    }
+}
+
+// Forward (dir = 0) or inverse (dir = 1) transform of W columns per workgroup.
+__global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict__ tiles, int ntiles,
+                                             int dir, const double* __restrict__ in,
+                                             double* __restrict__ out, int* nonfinite) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    double2* z = reinterpret_cast<double2*>(lds_raw);
+    const int tix = xcd_remap(blockIdx.x, ntiles);
+    const FTile T = tiles[tix];
+    const int n = a.n, m = a.m, W = a.W, cs = a.cs;
+    const int kind = a.kind;
+    const double sc2 = sqrt(2.0 / n), sc1 = sqrt(1.0 / n);
+    // which algorithm runs: forward kinds, and the inverse of N-N / D-D
+    const bool inv_cos = dir == 1 && (kind == Z_NN || kind == Z_DD);
+
+    // ---------------- load + pre-processing ----------------
+    if (!inv_cos) {
+        bool bad = false;
+        for (int idx = threadIdx.x; idx < n * W; idx += blockDim.x) {
+            int k = idx / W, w = idx - k * W;
+            double x = 0.0;
+            if (w < T.ncol) x = in[T.in_base + (long long)k * T.in_stride + w];
+            if (!isfinite(x)) bad = true;
+            double* zc = reinterpret_cast<double*>(z + w * cs);
+            int u;  // position in the length-n real sequence fed to the FFT
+            switch (kind) {
+                case Z_PP: u = k; break;
+                case Z_DD:
+                    if (k & 1) x = -x;
+                    [[fallthrough]];
+                case Z_NN: u = (k & 1) ? n - 1 - (k >> 1) : (k >> 1); break;
+                case Z_DN: {
+                    int j = n - 1 - k;  // reversed input, then the DCT-IV packing
+                    u = (j & 1) ? ((n - 1 - j) >> 1) * 2 + 1 : (j >> 1) * 2;
+                    break;
+                }
+                default:  // Z_ND
+                    u = (k & 1) ? ((n - 1 - k) >> 1) * 2 + 1 : (k >> 1) * 2;
+                    break;
+            }
+            zc[u] = x;  // real part at even u, imaginary part at odd u
+        }
+        if (bad && nonfinite) atomicOr(nonfinite, 1);
+        __syncthreads();
+        if (kind == Z_ND || kind == Z_DN) {
+            for (int idx = threadIdx.x; idx < m * W; idx += blockDim.x) {
+                int w = idx / m, k = idx - w * m;
+                z[w * cs + k] = cmul(z[w * cs + k], ld2(a.pre4, k));
+            }
+            __syncthreads();
+        }
+    } else {
+        // inverse of the cosine kinds: V_q = e^{i pi q/(2n)} (y'_q - i y'_{n-q}),
+        // Z_k = (V_k + conj V_{m-k}) + i (V_k - conj V_{m-k}) e^{2 pi i k/n};
+        // the FFT below then computes conj(IFFT) of conj(Z).
+        const int half = m / 2;
+        for (int idx = threadIdx.x; idx < (half + 1) * W; idx += blockDim.x) {
+            int k = idx / W, w = idx - k * W;
+            auto Y = [&](int q) -> double {  // y'_q = y_q / c_q, y'_n = 0
+                if (q >= n || w >= T.ncol) return 0.0;
+                int row = kind == Z_DD ? n - 1 - q : q;
+                double y = in[T.in_base + (long long)row * T.in_stride + w];
+                return y / (q == 0 ? sc1 : sc2);
+            };
+            auto V = [&](int q) -> double2 {
+                double2 c = cconj(ld2(a.post, q));
+                double2 t = make_double2(Y(q), -Y(n - q));
+                return cmul(c, t);
+            };
+            double2 Vk = V(k), Vmk = V(m - k);
+            auto Zk = [&](double2 A, double2 B, int kk) -> double2 {
+                double2 Bc = cconj(B);
+                double2 s = make_double2(A.x + Bc.x, A.y + Bc.y);
+                double2 d = make_double2(A.x - Bc.x, A.y - Bc.y);
+                double2 e = cconj(ld2(a.twn, kk));  // e^{+2 pi i kk / n}
+                double2 id = cmul(make_double2(-d.y, d.x), e);
+                return make_double2(s.x + id.x, s.y + id.y);
+            };
+            if (k < m) z[w * cs + k] = cconj(Zk(Vk, Vmk, k));
+            if (k > 0 && m - k != k && m - k < m) z[w * cs + (m - k)] = cconj(Zk(Vmk, Vk, m - k));
+        }
+        __syncthreads();
+    }
+
+    // ---------------- complex FFT of length m ----------------
+    fft_columns(z, cs, a);
+
+    // ---------------- post-processing + store ----------------
+    if (inv_cos) {
+        const double inv_n = 1.0 / n;
+        for (int idx = threadIdx.x; idx < n * W; idx += blockDim.x) {
+            int j = idx / W, w = idx - j * W;
+            if (w >= T.ncol) continue;
+            int u = (j & 1) ? n - 1 - (j >> 1) : (j >> 1);
+            double2 Fz = z[w * cs + (u >> 1)];
+            double v = (u & 1) ? -Fz.y * inv_n : Fz.x * inv_n;
+            if (kind == Z_DD && (j & 1)) v = -v;
+            out[T.out_base + (long long)j * T.out_stride + w] = v;
+        }
+        return;
+    }
+    if (kind == Z_ND || kind == Z_DN) {
+        for (int idx = threadIdx.x; idx < m * W; idx += blockDim.x) {
+            int k = idx / W, w = idx - k * W;
+            if (w >= T.ncol) continue;
+            double2 u = cmul(z[w * cs + k], ld2(a.post4, k));
+            int q0 = 2 * k, q1 = n - 1 - 2 * k;
+            double y0 = sc2 * u.x, y1 = -sc2 * u.y;
+            if (kind == Z_DN) {
+                if (q0 & 1) y0 = -y0;
+                if (q1 & 1) y1 = -y1;
+            }
+            out[T.out_base + (long long)q0 * T.out_stride + w] = y0;
+            out[T.out_base + (long long)q1 * T.out_stride + w] = y1;
+        }
+        return;
+    }
+    // PP / NN / DD: real DFT X_k (k = 0..m) from the half-length FFT
+    for (int idx = threadIdx.x; idx < (m + 1) * W; idx += blockDim.x) {
+        int k = idx / W, w = idx - k * W;
+        if (w >= T.ncol) continue;
+        double2 Zk = z[w * cs + (k % m)];
+        double2 Zc = cconj(z[w * cs + ((m - k) % m)]);
+        double2 s = make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y + Zc.y));
+        double2 d = make_double2(0.5 * (Zk.x - Zc.x), 0.5 * (Zk.y - Zc.y));
+        double2 t = cmul(ld2(a.twn, k), d);  // e^{-2 pi i k/n} (Zk - Zc) / 2
+        double2 X = make_double2(s.x + t.y, s.y - t.x);  // s - i t
+        double* o = out + T.out_base + w;
+        const long long st = T.out_stride;
+        if (kind == Z_PP) {
+            o[k * st] = sc1 * (X.x - X.y);
+            if (k > 0 && k < m) o[(n - k) * st] = sc1 * (X.x + X.y);
+        } else {
+            // DCT-II: y_q = c_q Re(e^{-i pi q/(2n)} X_q), X_{n-k} = conj X_k
+            double yk = (k == 0 ? sc1 : sc2) * (ld2(a.post, k).x * X.x - ld2(a.post, k).y * X.y);
+            int rk = kind == Z_DD ? n - 1 - k : k;
+            o[rk * st] = yk;
+            if (k > 0 && k < m) {
+                double2 pc = ld2(a.post, n - k);
+                double yn = sc2 * (pc.x * X.x + pc.y * X.y);  // Re(pc * conj X)
+                int rn = kind == Z_DD ? k - 1 : n - k;
+                o[rn * st] = yn;
+            }
+        }
+    }
+}
+
+int fft_col_stride(const mbp_plan* P);
+
+// Columns per workgroup: at most 16, the LDS image W * cs complex values must
+// fit the budget, and every stage must fit 256 threads x (4 butterflies for
+// radices <= 8, 1 butterfly for the larger odd radices).
+int fft_columns_per_wg(const mbp_plan* P) {
+    const int m = P->fft.m;
+    int W = 16;
+    while (W > 1 && int64_t(W) * fft_col_stride(P) * 16 > P->lds_limit) W >>= 1;
+    for (int R : P->fft.radices)
+        while (W > 1 && W * (m / R) > (R > 8 ? 256 : 4 * 256)) W >>= 1;
+    return W;
+}
+
+// Column stride in complex values: one padding slot breaks the power-of-two
+// bank pattern when the padded image still fits.
+int fft_col_stride(const mbp_plan* P) {
+    const int m = P->fft.m;
+    return (int64_t(8) * (m + 1) * 16 <= P->lds_limit) ? m + 1 : m;
+}
+
+void fft_build_tiles(const mbp_plan* P, std::vector<unsigned char>& fwd, std::vector<unsigned char>& inv,
+                     int* ntiles) {
+    const int W = fft_columns_per_wg(P);
+    std::vector<FTile> f, iv;
+    for (int b = 0; b < P->g.nb; ++b) {
+        long long cols = (long long)P->g.nx[b] * P->g.ny[b];
+        long long off2 = P->levels[0].off[b];
+        for (long long c0 = 0; c0 < cols; c0 += W) {
+            FTile t{};
+            t.ncol = int(std::min<long long>(W, cols - c0));
+            t.in_base = P->block_off[b] + c0;
+            t.in_stride = int(cols);
+            t.out_base = off2 + c0;
+            t.out_stride = int(P->plane0);
+            f.push_back(t);
+            FTile u{};
+            u.ncol = t.ncol;
+            u.in_base = off2 + c0;
+            u.in_stride = int(P->plane0);
+            u.out_base = P->block_off[b] + c0;
+            u.out_stride = int(cols);
+            iv.push_back(u);
+        }
+    }
+    *ntiles = int(f.size());
+    fwd.assign(reinterpret_cast<unsigned char*>(f.data()),
+               reinterpret_cast<unsigned char*>(f.data()) + f.size() * sizeof(FTile));
+    inv.assign(reinterpret_cast<unsigned char*>(iv.data()),
+               reinterpret_cast<unsigned char*>(iv.data()) + iv.size() * sizeof(FTile));
+}
+
+static FFTArgs make_args(const mbp_plan* P) {
+    FFTArgs a{};
+    a.n = P->fft.n;
+    a.m = P->fft.m;
+    a.kind = P->g.zkind;
+    a.W = fft_columns_per_wg(P);
+    a.cs = fft_col_stride(P);
+    a.nstage = int(P->fft.radices.size());
+    for (int s = 0; s < a.nstage && s < 16; ++s) a.radix[s] = P->fft.radices[s];
+    a.tw = P->d_dbl + P->fft_tw;
+    a.twn = P->d_dbl + P->fft_twn;
+    a.post = P->d_dbl + P->fft_post;
+    a.pre4 = P->d_dbl + P->fft_pre4;
+    a.post4 = P->d_dbl + P->fft_post4;
+    return a;
+}
+
+static size_t lds_bytes(const mbp_plan* P) {
+    return size_t(fft_columns_per_wg(P)) * fft_col_stride(P) * sizeof(double2);
+}
+
+static void set_lds_fft(size_t bytes) {
+    if (bytes > 64 * 1024)
+        hipFuncSetAttribute(reinterpret_cast<const void*>(k_r2r), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            int(bytes));
+}
+
+void launch_forward(const mbp_plan* P, const double* f, double* fhat, int* nonfinite, hipStream_t s) {
+    FFTArgs a = make_args(P);
+    set_lds_fft(lds_bytes(P));
+    hipLaunchKernelGGL(k_r2r, dim3(P->fft_ntiles), dim3(256), lds_bytes(P), s, a,
+                       reinterpret_cast<const FTile*>(P->d_ftiles_fwd), P->fft_ntiles, 0, f, fhat,
+                       nonfinite);
+}
+
+void launch_inverse(const mbp_plan* P, const double* phat, double* p, hipStream_t s) {
+    FFTArgs a = make_args(P);
+    set_lds_fft(lds_bytes(P));
+    hipLaunchKernelGGL(k_r2r, dim3(P->fft_ntiles), dim3(256), lds_bytes(P), s, a,
+                       reinterpret_cast<const FTile*>(P->d_ftiles_inv), P->fft_ntiles, 1, phat, p,
+                       nullptr);
+}
+
+}  // namespace mbp

@@ -1,0 +1,190 @@
+// Internal structures of the multi-block Poisson library (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mbp.h"
+
+namespace mbp {
+
+// Kinds of the z expansion (Table 1 rows; DN is the sine counterpart of ND).
+enum ZKind { Z_PP = 0, Z_NN = 1, Z_DD = 2, Z_ND = 3, Z_DN = 4 };
+
+enum Face { XM = 0, XP = 1, YM = 2, YP = 3 };
+
+// Tile of the global-memory multigrid kernels: 64 cells along x (one wave),
+// kTileY rows, 256 threads.
+constexpr int kTileX = 64;
+constexpr int kTileY = 16;
+constexpr int kRowsPerPass = 4;  // threadIdx.y extent (256 threads = 64 x 4)
+
+// One block of one multigrid level, as the kernels read it.
+struct DBlock {
+    int nx, ny;   // cells
+    int off;      // first cell of this block inside a packed plane
+    int nbr[4];   // neighbour block per face (-1 = wall)
+    int bc[4];    // face condition (MBP_DIRICHLET / MBP_NEUMANN / joined)
+    int par;      // colour parity offset (red-black ordering across blocks)
+    int oddwrap;  // bit 0: odd periodic x wrap, bit 1: odd periodic y wrap (extra colours)
+    int cx, cy;   // coefficient pool offsets: x -> [wm(nx) | wp(nx) | d(nx)], y alike
+    // transfer from this level to the next coarser one
+    int rsx, rsy;  // int pool: coarse -> first fine index (nc + 1 entries)
+    int rwx, rwy;  // double pool: per fine index dc_fine / dc_coarse(parent)
+    int pcx, pcy;  // int pool: per fine index coarse lower neighbour (-1 .. nc-1)
+    int pwx, pwy;  // double pool: per fine index weight of that lower neighbour
+};
+
+// Host view of one multigrid level.
+struct Level {
+    int nb = 0;
+    int64_t plane = 0;            // cells per plane
+    std::vector<int> nx, ny, off;
+    std::vector<std::vector<double>> xf, yf;  // face coordinates per block
+    int blk_off = 0;              // first DBlock of this level in the block table
+    int ntiles = 0;               // global-kernel tiles covering the plane
+    int tile_off = 0;             // first tile in the tile table
+    int64_t lds_off = 0;          // element offset of this level in the LDS image
+    bool oddwrap = false;         // some block needs the two extra smoothing colours
+};
+
+struct Geometry {
+    int nb = 0;
+    std::vector<int> lo0, lo1, hi0, hi1, nx, ny;
+    std::vector<std::vector<double>> xf, yf;
+    std::vector<std::array<int, 4>> bc, nbr;
+    int nz = 0;
+    double lz = 0.0, dz = 0.0;
+    int zlo = 0, zhi = 0;
+    ZKind zkind = Z_PP;
+    bool dirichlet_xy = false;
+    bool singular = false;
+};
+
+// The per-mode work description of one solve (batched launches list many).
+struct Item {
+    int plan;   // index into the batch's plan table
+    int mode;   // z mode q
+};
+
+struct DevPlan;  // device pointers of one plan (see below)
+
+struct FFTPlan {
+    int n = 0, m = 0;              // real length, complex length n/2
+    std::vector<int> radices;      // Stockham stages, product = m
+};
+
+}  // namespace mbp
+
+struct mbp_plan {
+    mbp::Geometry g;
+    mbp_options opt{};
+    std::vector<mbp::Level> levels;
+    int nlev = 0;
+    int lds_level = 0;            // first level handled by the LDS-resident kernel (FP64)
+    int lds_level32 = 0;          // same for FP32 V-cycles
+    int64_t lds_bytes64 = 0, lds_bytes32 = 0;
+    int coarse_n = 0;             // cells of the coarsest plane
+    std::vector<double> lambda;   // Table-1 eigenvalues
+    std::vector<double> shift;    // lambda_q / dz^2
+    mbp::FFTPlan fft;
+    int fft_tw = 0, fft_twn = 0, fft_post = 0, fft_pre4 = 0, fft_post4 = 0;  // double-pool offsets
+    int fft_ntiles = 0;
+    void* d_ftiles_fwd = nullptr;
+    void* d_ftiles_inv = nullptr;
+    int64_t lds_limit = 64 * 1024;  // LDS bytes one workgroup may use
+    int lvinfo = 0;               // int-pool offset: per level {plane, blk_off, tile_off, ntiles}
+    // host tables (uploaded into one device allocation)
+    std::vector<mbp::DBlock> hblk;
+    std::vector<int> hint;
+    std::vector<double> hdbl;
+    std::vector<int4> htiles;
+    std::vector<double> coarse_wl, coarse_wr, coarse_mu;  // nc x nc, nc x nc, nc
+    std::vector<double> areas0;   // cell areas of the finest plane
+    double area_sum = 0.0;
+    int64_t ncells = 0;
+    int64_t plane0 = 0;
+    std::vector<int64_t> block_off;  // packed-field element offsets, nb + 1
+    // ---- device state ----
+    int device = -1;
+    bool busy = false;
+    void* dmem = nullptr;         // one allocation holding everything below
+    size_t dbytes = 0;
+    mbp::DBlock* d_blk = nullptr;
+    int* d_int = nullptr;
+    double* d_dbl = nullptr;
+    int4* d_tiles = nullptr;
+    double* d_shift = nullptr;    // nz
+    float* d_shift32 = nullptr;   // nz
+    double* d_cwl = nullptr;      // coarse eigen tables
+    double* d_cwr = nullptr;
+    double* d_cmu = nullptr;
+    double* d_area0 = nullptr;    // finest plane areas
+    double* fhat = nullptr;       // nz * plane0 modal rhs
+    double* phat = nullptr;       // nz * plane0 modal solution
+    std::vector<double*> p64, f64;  // levels >= 1, FP64
+    std::vector<float*> p32, f32;   // levels >= 0, FP32 (mixed precision)
+    double* d_part = nullptr;     // per-mode partial sums (nz * nparts * 2)
+    int nparts = 0;
+    double* d_fnorm = nullptr;    // nz: ||fhat_q||^2
+    double* d_rnorm = nullptr;    // nz: ||rhat_q||^2
+    int* d_act = nullptr;         // active mode list (nz)
+    int* d_nact = nullptr;        // 1 int
+    int* d_cyc = nullptr;         // nz: cycles per mode
+    int* d_flag = nullptr;        // 4 ints: [0] non-finite rhs
+    double* d_scal = nullptr;     // 8 doubles of scratch scalars
+    void* graph_exec = nullptr;   // cached batched replay (hipGraphExec_t)
+    void* host_pinned = nullptr;  // small pinned buffer for convergence readback
+};
+
+namespace mbp {
+
+// plan.cpp
+int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* z,
+                           const mbp_options* opt, int64_t lds_limit, mbp_plan* P, std::string* err);
+int build_plan_host(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* z,
+                    const mbp_options* opt, mbp_plan* P, std::string* err);
+void options_default(mbp_options* o);
+int grid_tanh(int n, double lmin, double lmax, int type, double factor, double* out);
+
+// fft.hip (host helpers)
+int fft_columns_per_wg(const mbp_plan* P);
+int fft_col_stride(const mbp_plan* P);
+void fft_build_tiles(const mbp_plan* P, std::vector<unsigned char>& fwd, std::vector<unsigned char>& inv,
+                     int* ntiles);
+
+// device launchers (fft.hip, mg.hip)
+void launch_forward(const mbp_plan* P, const double* f, double* fhat, int* nonfinite_flag,
+                    hipStream_t s);
+void launch_inverse(const mbp_plan* P, const double* phat, double* p, hipStream_t s);
+void launch_apply3d(const mbp_plan* P, const double* p, double* out, hipStream_t s);
+
+template <typename T>
+void launch_vcycle(const mbp_plan* P, T* p0, T* f0, const int* act, const int* nact, int nitems,
+                   hipStream_t s);
+void launch_residual_norm(const mbp_plan* P, const double* p, const double* f, double* rnorm,
+                          const int* act, const int* nact, int nitems, hipStream_t s);
+void launch_residual_to32(const mbp_plan* P, const double* p, const double* f, float* r32,
+                          float* e32, double* rnorm, const int* act, const int* nact, int nitems,
+                          hipStream_t s);
+void launch_add_correction(const mbp_plan* P, double* p, const float* e32, const int* act,
+                           const int* nact, int nitems, hipStream_t s);
+void launch_plane_norm(const mbp_plan* P, const double* f, double* out, hipStream_t s);
+void launch_update_active(const mbp_plan* P, double rtol2, int retire, int cycle, hipStream_t s);
+void launch_zero(double* p, size_t n, hipStream_t s);
+void launch_zero32(float* p, size_t n, hipStream_t s);
+void launch_singular_fix(const mbp_plan* P, double* plane, double* out_mean, hipStream_t s);
+
+// solve.cpp
+size_t plan_device_bytes(const mbp_plan* P);
+int plan_device_init(mbp_plan* P);
+void plan_device_free(mbp_plan* P);
+int solve_one(mbp_plan* P, const double* rhs, double* p, double rtol, int flags, hipStream_t s,
+              mbp_solve_info* info);
+
+}  // namespace mbp

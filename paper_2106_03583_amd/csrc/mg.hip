@@ -1,0 +1,871 @@
+// Geometric multigrid for the shifted 2D systems of Eq. (9),
+//     (A_2D + sigma_q) phat_q = fhat_q,   sigma_q = lambda_q / dz^2,
+// one system per z mode, on a multi-block x-y plane with possibly stretched
+// spacing.  A_2D is the cell-centred finite-volume Laplacian; joined faces
+// couple blocks directly (the halo is read from the neighbour block), walls
+// enter through the coefficients (Neumann: no coupling, Dirichlet: a mirrored
+// ghost folded into the diagonal).
+//
+// Components: red-black Gauss-Seidel smoothing, residual + area-weighted
+// restriction (fused), bilinear prolongation in physical coordinates +
+// correction (fused), and an exact coarsest solve from a precomputed
+// eigen-decomposition.  Fine levels stream through HBM with tiled kernels;
+// the levels whose hierarchy fits in LDS run inside one workgroup per mode.
+#include "internal.h"
+
+namespace mbp {
+
+__device__ __forceinline__ int xcd_remap_mg(int g, int n) {
+    int x = g & 7, l = g >> 3;
+    int per = n >> 3, rem = n & 7;
+    return x * per + min(x, rem) + l;
+}
+
+// Values of the four stencil neighbours of cell (i, j) of block b.  A
+// neighbour beyond a joined face comes from the partner block (same
+// tangential index); beyond a wall the coefficient is zero and 0 is returned.
+template <typename T>
+__device__ __forceinline__ void neighbours(const T* __restrict__ pl, const DBlock* __restrict__ B,
+                                           const DBlock& b, int i, int j, T& xm, T& xp, T& ym,
+                                           T& yp) {
+    const T* row = pl + b.off + j * b.nx;
+    if (i > 0) xm = row[i - 1];
+    else if (b.nbr[XM] >= 0) { const DBlock& k = B[b.nbr[XM]]; xm = pl[k.off + j * k.nx + k.nx - 1]; }
+    else xm = T(0);
+    if (i < b.nx - 1) xp = row[i + 1];
+    else if (b.nbr[XP] >= 0) { const DBlock& k = B[b.nbr[XP]]; xp = pl[k.off + j * k.nx]; }
+    else xp = T(0);
+    if (j > 0) ym = row[i - b.nx];
+    else if (b.nbr[YM] >= 0) { const DBlock& k = B[b.nbr[YM]]; ym = pl[k.off + (k.ny - 1) * k.nx + i]; }
+    else ym = T(0);
+    if (j < b.ny - 1) yp = row[i + b.nx];
+    else if (b.nbr[YP] >= 0) { const DBlock& k = B[b.nbr[YP]]; yp = pl[k.off + i]; }
+    else yp = T(0);
+}
+
+// (A_2D + sigma) p at cell (i, j).
+template <typename T>
+__device__ __forceinline__ T apply_at(const T* __restrict__ pl, const DBlock* __restrict__ B,
+                                      const DBlock& b, const double* __restrict__ dp, int i, int j,
+                                      T sig) {
+    T xm, xp, ym, yp;
+    neighbours(pl, B, b, i, j, xm, xp, ym, yp);
+    const T c = pl[b.off + j * b.nx + i];
+    const T d = T(dp[b.cx + 2 * b.nx + i]) + T(dp[b.cy + 2 * b.ny + j]) + sig;
+    return T(dp[b.cx + i]) * xm + T(dp[b.cx + b.nx + i]) * xp + T(dp[b.cy + j]) * ym +
+           T(dp[b.cy + b.ny + j]) * yp + d * c;
+}
+
+// Smoothing colour of cell (i, j): red / black by index parity (0 / 1); on an
+// odd periodic wrap the last column / row gets colours 2 / 3 so that no two
+// neighbours are ever relaxed in the same pass.
+__device__ __forceinline__ int colour_of(const DBlock& b, int i, int j) {
+    int c = (i + j + b.par) & 1;
+    if (((b.oddwrap & 1) && i == b.nx - 1) || ((b.oddwrap & 2) && j == b.ny - 1)) c += 2;
+    return c;
+}
+
+// Red-black Gauss-Seidel update of one cell: solve its own equation with the
+// current neighbour values.
+template <typename T>
+__device__ __forceinline__ T gs_value(const T* __restrict__ pl, const T* __restrict__ fl,
+                                      const DBlock* __restrict__ B, const DBlock& b,
+                                      const double* __restrict__ dp, int i, int j, T sig) {
+    T xm, xp, ym, yp;
+    neighbours(pl, B, b, i, j, xm, xp, ym, yp);
+    const T d = T(dp[b.cx + 2 * b.nx + i]) + T(dp[b.cy + 2 * b.ny + j]) + sig;
+    const T off = T(dp[b.cx + i]) * xm + T(dp[b.cx + b.nx + i]) * xp + T(dp[b.cy + j]) * ym +
+                  T(dp[b.cy + b.ny + j]) * yp;
+    return (fl[b.off + j * b.nx + i] - off) / d;
+}
+
+// Coarse value at (I, J) of block b, I in [-1, nx], J in [-1, ny]: beyond a
+// joined face it is the partner's cell, beyond a wall the mirror image
+// (Neumann +, Dirichlet -).  A corner is reached through the y face first.
+template <typename T>
+__device__ __forceinline__ T coarse_value(const T* __restrict__ pl, const DBlock* __restrict__ B,
+                                          int b, int I, int J) {
+    T s = T(1);
+    const DBlock* bb = &B[b];
+    if (J < 0) {
+        if (bb->nbr[YM] >= 0) { bb = &B[bb->nbr[YM]]; J = bb->ny - 1; }
+        else { if (bb->bc[YM] == MBP_DIRICHLET) s = -s; J = 0; }
+    } else if (J >= bb->ny) {
+        if (bb->nbr[YP] >= 0) { bb = &B[bb->nbr[YP]]; J = 0; }
+        else { if (bb->bc[YP] == MBP_DIRICHLET) s = -s; J = bb->ny - 1; }
+    }
+    if (I < 0) {
+        if (bb->nbr[XM] >= 0) { bb = &B[bb->nbr[XM]]; I = bb->nx - 1; }
+        else { if (bb->bc[XM] == MBP_DIRICHLET) s = -s; I = 0; }
+    } else if (I >= bb->nx) {
+        if (bb->nbr[XP] >= 0) { bb = &B[bb->nbr[XP]]; I = 0; }
+        else { if (bb->bc[XP] == MBP_DIRICHLET) s = -s; I = bb->nx - 1; }
+    }
+    return s * pl[bb->off + J * bb->nx + I];
+}
+
+// Area-weighted restriction of the residual for coarse cell (I, J).
+template <typename T>
+__device__ __forceinline__ T restrict_at(const T* __restrict__ pf, const T* __restrict__ ff,
+                                         const DBlock* __restrict__ Bf, const DBlock& bf,
+                                         const double* __restrict__ dp, const int* __restrict__ ip,
+                                         int I, int J, T sig) {
+    const int i0 = ip[bf.rsx + I], i1 = ip[bf.rsx + I + 1];
+    const int j0 = ip[bf.rsy + J], j1 = ip[bf.rsy + J + 1];
+    T acc = T(0);
+    for (int j = j0; j < j1; ++j) {
+        const T wy = T(dp[bf.rwy + j]);
+        T row = T(0);
+        for (int i = i0; i < i1; ++i) {
+            const T r = ff[bf.off + j * bf.nx + i] - apply_at(pf, Bf, bf, dp, i, j, sig);
+            row += T(dp[bf.rwx + i]) * r;
+        }
+        acc += wy * row;
+    }
+    return acc;
+}
+
+// Bilinear interpolation (physical-coordinate weights) of the coarse
+// correction at fine cell (i, j).
+template <typename T>
+__device__ __forceinline__ T prolong_at(const T* __restrict__ pc, const DBlock* __restrict__ Bc,
+                                        const DBlock& bf, int b, const double* __restrict__ dp,
+                                        const int* __restrict__ ip, int i, int j) {
+    const int cx = ip[bf.pcx + i], cy = ip[bf.pcy + j];
+    const T wx = T(dp[bf.pwx + i]), wy = T(dp[bf.pwy + j]);
+    const T e00 = coarse_value(pc, Bc, b, cx, cy), e10 = coarse_value(pc, Bc, b, cx + 1, cy);
+    const T e01 = coarse_value(pc, Bc, b, cx, cy + 1), e11 = coarse_value(pc, Bc, b, cx + 1, cy + 1);
+    return wy * (wx * e00 + (T(1) - wx) * e10) + (T(1) - wy) * (wx * e01 + (T(1) - wx) * e11);
+}
+
+// =========================== global-memory kernels ===========================
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_rbgs(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntiles,
+       const double* __restrict__ dp, T* __restrict__ p, const T* __restrict__ f, long long plane,
+       const double* __restrict__ shift, const int* __restrict__ act, const int* __restrict__ nact,
+       int colour) {
+    const int item = blockIdx.y;
+    if (item >= *nact) return;
+    const int q = act[item];
+    const int4 t = tiles[xcd_remap_mg(blockIdx.x, ntiles)];
+    const DBlock b = B[t.x];
+    T* pq = p + q * plane;
+    const T* fq = f + q * plane;
+    const T sig = T(shift[q]);
+    const int i = t.y + threadIdx.x;
+    if (i >= b.nx) return;
+    for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
+        const int j = t.z + r;
+        if (j >= b.ny) break;
+        if (colour_of(b, i, j) != colour) continue;
+        pq[b.off + j * b.nx + i] = gs_value(pq, fq, B, b, dp, i, j, sig);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_restrict(const DBlock* __restrict__ Bf, const DBlock* __restrict__ Bc,
+           const int4* __restrict__ tiles_c, int ntiles_c, const double* __restrict__ dp,
+           const int* __restrict__ ip, const T* __restrict__ pf, const T* __restrict__ ff,
+           T* __restrict__ fc, T* __restrict__ pc, long long plane_f, long long plane_c,
+           const double* __restrict__ shift, const int* __restrict__ act,
+           const int* __restrict__ nact) {
+    const int item = blockIdx.y;
+    if (item >= *nact) return;
+    const int q = act[item];
+    const int4 t = tiles_c[xcd_remap_mg(blockIdx.x, ntiles_c)];
+    const DBlock bc = Bc[t.x];
+    const DBlock bf = Bf[t.x];
+    const T* pq = pf + q * plane_f;
+    const T* fq = ff + q * plane_f;
+    const T sig = T(shift[q]);
+    const int I = t.y + threadIdx.x;
+    if (I >= bc.nx) return;
+    for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
+        const int J = t.z + r;
+        if (J >= bc.ny) break;
+        const long long o = q * plane_c + bc.off + J * bc.nx + I;
+        fc[o] = restrict_at(pq, fq, Bf, bf, dp, ip, I, J, sig);
+        pc[o] = T(0);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_prolong(const DBlock* __restrict__ Bf, const DBlock* __restrict__ Bc,
+          const int4* __restrict__ tiles_f, int ntiles_f, const double* __restrict__ dp,
+          const int* __restrict__ ip, const T* __restrict__ pc, T* __restrict__ pf,
+          long long plane_f, long long plane_c, const int* __restrict__ act,
+          const int* __restrict__ nact) {
+    const int item = blockIdx.y;
+    if (item >= *nact) return;
+    const int q = act[item];
+    const int4 t = tiles_f[xcd_remap_mg(blockIdx.x, ntiles_f)];
+    const DBlock bf = Bf[t.x];
+    const T* cq = pc + q * plane_c;
+    T* fq = pf + q * plane_f;
+    const int i = t.y + threadIdx.x;
+    if (i >= bf.nx) return;
+    for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
+        const int j = t.z + r;
+        if (j >= bf.ny) break;
+        fq[bf.off + j * bf.nx + i] += prolong_at(cq, Bc, bf, t.x, dp, ip, i, j);
+    }
+}
+
+// Wave + workgroup sum of a double; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x + threadIdx.y * blockDim.x;
+    const int wid = lane >> 6, nw = (blockDim.x * blockDim.y + 63) >> 6;
+    __syncthreads();
+    if ((lane & 63) == 0) scratch[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (lane == 0)
+        for (int w = 0; w < nw; ++w) s += scratch[w];
+    return s;
+}
+
+// Per-tile partial sums of the squared finest-level residual of each mode;
+// mode == 1 also writes r as float32 (the refinement rhs) and zeroes e32.
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_residual(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntiles,
+           const double* __restrict__ dp, const double* __restrict__ p,
+           const double* __restrict__ f, long long plane, const double* __restrict__ shift,
+           const int* __restrict__ act, const int* __restrict__ nact, double* __restrict__ part,
+           float* __restrict__ r32, float* __restrict__ e32) {
+    __shared__ double scratch[8];
+    const int item = blockIdx.y;
+    if (item >= *nact) return;
+    const int q = act[item];
+    const int tix = xcd_remap_mg(blockIdx.x, ntiles);
+    const int4 t = tiles[tix];
+    const DBlock b = B[t.x];
+    const double* pq = p + q * plane;
+    const double* fq = f + q * plane;
+    const double sig = shift[q];
+    const int i = t.y + threadIdx.x;
+    double acc = 0.0;
+    if (i < b.nx) {
+        for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
+            const int j = t.z + r;
+            if (j >= b.ny) break;
+            const long long c = b.off + j * b.nx + i;
+            const double res = fq[c] - apply_at(pq, B, b, dp, i, j, sig);
+            acc += res * res;
+            if (MODE == 1) {
+                r32[q * plane + c] = float(res);
+                e32[q * plane + c] = 0.0f;
+            }
+        }
+    }
+    const double s = block_sum(acc, scratch);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[(long long)q * ntiles + tix] = s;
+}
+
+// Per-tile partial sums of fhat_q^2.
+__global__ void __launch_bounds__(256)
+k_sumsq(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntiles,
+        const double* __restrict__ f, long long plane, double* __restrict__ part) {
+    __shared__ double scratch[8];
+    const int q = blockIdx.y;
+    const int tix = xcd_remap_mg(blockIdx.x, ntiles);
+    const int4 t = tiles[tix];
+    const DBlock b = B[t.x];
+    const double* fq = f + q * plane;
+    const int i = t.y + threadIdx.x;
+    double acc = 0.0;
+    if (i < b.nx)
+        for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
+            const int j = t.z + r;
+            if (j >= b.ny) break;
+            const double v = fq[b.off + j * b.nx + i];
+            acc += v * v;
+        }
+    const double s = block_sum(acc, scratch);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[(long long)q * ntiles + tix] = s;
+}
+
+// Deterministic per-mode reduction of the tile partials (one workgroup per item).
+__global__ void __launch_bounds__(256)
+k_finish(const double* __restrict__ part, int ntiles, const int* __restrict__ act,
+         const int* __restrict__ nact, double* __restrict__ out) {
+    __shared__ double scratch[8];
+    const int item = blockIdx.x;
+    if (act && item >= *nact) return;
+    const int q = act ? act[item] : item;
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) acc += part[(long long)q * ntiles + t];
+    const double s = block_sum(acc, scratch);
+    if (threadIdx.x == 0) out[q] = s;
+}
+
+__global__ void __launch_bounds__(256)
+k_addcorr(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntiles,
+          double* __restrict__ p, const float* __restrict__ e, long long plane,
+          const int* __restrict__ act, const int* __restrict__ nact) {
+    const int item = blockIdx.y;
+    if (item >= *nact) return;
+    const int q = act[item];
+    const int4 t = tiles[xcd_remap_mg(blockIdx.x, ntiles)];
+    const DBlock b = B[t.x];
+    const int i = t.y + threadIdx.x;
+    if (i >= b.nx) return;
+    for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
+        const int j = t.z + r;
+        if (j >= b.ny) break;
+        const long long c = q * plane + b.off + j * b.nx + i;
+        p[c] += double(e[c]);
+    }
+}
+
+// Convergence bookkeeping after a residual evaluation (single workgroup):
+// ratio_q = ||r_q||^2 / ||f_q||^2.  scal[0] = max ratio over the active list.
+// With retirement, converged modes record the cycle count and leave the list.
+__global__ void __launch_bounds__(1024)
+k_update(int nz, const double* __restrict__ rnorm, const double* __restrict__ fnorm, double rtol2,
+         int retire, int cycle, int* __restrict__ act, int* __restrict__ nact, int* __restrict__ cyc,
+         double* __restrict__ scal) {
+    __shared__ int keep[4096];
+    __shared__ int cnt;
+    __shared__ double mx[16];
+    const int n = *nact;
+    double m = 0.0;
+    for (int it = threadIdx.x; it < n; it += blockDim.x) {
+        const int q = act[it];
+        const double fn = fnorm[q];
+        const double ratio = fn > 0.0 ? rnorm[q] / fn : (rnorm[q] > 0.0 ? 1e300 : 0.0);
+        m = fmax(m, ratio);
+        const bool done = ratio <= rtol2;
+        keep[it] = done ? -1 : q;
+        if (done || !retire) cyc[q] = cycle;
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double g = 0.0;
+        for (int w = 0; w < int(blockDim.x >> 6); ++w) g = fmax(g, mx[w]);
+        scal[0] = g;
+        if (retire) {
+            int c = 0;
+            for (int it = 0; it < n; ++it)
+                if (keep[it] >= 0) act[c++] = keep[it];
+            cnt = c;
+            *nact = c;
+        }
+    }
+    (void)cnt;
+}
+
+__global__ void k_zero64(double* p, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+__global__ void k_fill_int(int* p, int n, int v) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
+}
+
+__global__ void k_iota(int* act, int n, int* nact) {
+    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) act[i] = i;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nact = n;
+}
+
+// sum(a x) over one plane (single workgroup, fixed order).
+__global__ void __launch_bounds__(1024)
+k_area_dot(const double* __restrict__ x, const double* __restrict__ a, long long n,
+           double* __restrict__ out) {
+    __shared__ double scratch[16];
+    double acc = 0.0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) acc += a[i] * x[i];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < int(blockDim.x >> 6); ++w) s += scratch[w];
+        out[0] = s;
+    }
+}
+
+__global__ void k_sub(double* __restrict__ x, long long n, const double* __restrict__ num, double den) {
+    const double m = num[0] / den;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        x[i] -= m;
+}
+
+// L_h p on the packed 3D field: x-y part from the level-0 tables, z part
+// with the ghost rules of the pair (N: g = p0, D: g = -p0, P: wrap).
+__global__ void __launch_bounds__(256)
+k_apply3d(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntiles,
+          const double* __restrict__ dp, const double* __restrict__ p, double* __restrict__ out,
+          int nz, double idz2, int zkind) {
+    const int k = blockIdx.y;
+    const int4 t = tiles[xcd_remap_mg(blockIdx.x, ntiles)];
+    const DBlock b = B[t.x];
+    const long long cols = (long long)b.nx * b.ny;
+    const long long base = (long long)b.off * nz;  // block start in the packed field
+    const int i = t.y + threadIdx.x;
+    if (i >= b.nx) return;
+    for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
+        const int j = t.z + r;
+        if (j >= b.ny) break;
+        const long long c = base + k * cols + j * b.nx + i;
+        const double v = p[c];
+        // x-y neighbours (other blocks addressed through their own base)
+        auto at = [&](const DBlock& bb, int ii, int jj) {
+            return p[(long long)bb.off * nz + k * (long long)bb.nx * bb.ny + jj * bb.nx + ii];
+        };
+        double xm = 0, xp = 0, ym = 0, yp = 0;
+        if (i > 0) xm = p[c - 1];
+        else if (b.nbr[XM] >= 0) { const DBlock& kk = B[b.nbr[XM]]; xm = at(kk, kk.nx - 1, j); }
+        if (i < b.nx - 1) xp = p[c + 1];
+        else if (b.nbr[XP] >= 0) { const DBlock& kk = B[b.nbr[XP]]; xp = at(kk, 0, j); }
+        if (j > 0) ym = p[c - b.nx];
+        else if (b.nbr[YM] >= 0) { const DBlock& kk = B[b.nbr[YM]]; ym = at(kk, i, kk.ny - 1); }
+        if (j < b.ny - 1) yp = p[c + b.nx];
+        else if (b.nbr[YP] >= 0) { const DBlock& kk = B[b.nbr[YP]]; yp = at(kk, i, 0); }
+        double zm, zp;
+        if (k > 0) zm = p[c - cols];
+        else zm = zkind == Z_PP ? p[c + (nz - 1) * cols] : ((zkind == Z_NN || zkind == Z_ND) ? v : -v);
+        if (k < nz - 1) zp = p[c + cols];
+        else zp = zkind == Z_PP ? p[c - (nz - 1) * cols] : ((zkind == Z_NN || zkind == Z_DN) ? v : -v);
+        const double d = dp[b.cx + 2 * b.nx + i] + dp[b.cy + 2 * b.ny + j];
+        out[c] = dp[b.cx + i] * xm + dp[b.cx + b.nx + i] * xp + dp[b.cy + j] * ym +
+                 dp[b.cy + b.ny + j] * yp + d * v + (zm - 2.0 * v + zp) * idz2;
+    }
+}
+
+// ============================ LDS-resident levels ============================
+
+struct LdsArgs {
+    const DBlock* Ball;  // every level's blocks
+    const double* dp;
+    const int* ip;
+    int lvinfo;          // int-pool offset of {plane, blk_off, tile_off, ntiles} per level
+    int nlev, L, nb;
+    int nu1, nu2;
+    const double* cwl;   // coarsest eigen tables
+    const double* cwr;
+    const double* cmu;
+    int nc;
+};
+
+template <typename T>
+struct LdsView {
+    T* base;             // LDS image: per level l >= L: p (plane) then f (plane)
+    double* ctmp;        // coarse temp (nc doubles)
+    double* red;         // reduction scratch
+};
+
+template <typename T>
+__device__ __forceinline__ T* lds_p(const LdsArgs& a, const LdsView<T>& v, int l) {
+    long long o = 0;
+    for (int k = a.L; k < l; ++k) o += 2LL * a.ip[a.lvinfo + 4 * k];
+    return v.base + o;
+}
+
+template <typename T>
+__device__ void lds_smooth(const LdsArgs& a, T* p, const T* f, const DBlock* B, T sig, int colour) {
+    bool any_odd = false;
+    for (int bi = 0; bi < a.nb; ++bi) {
+        const DBlock b = B[bi];
+        any_odd |= b.oddwrap != 0;
+        if (b.oddwrap == 0) {
+            const int hx = (b.nx + 1) >> 1;
+            const int cnt = hx * b.ny;
+            for (int h = threadIdx.x; h < cnt; h += blockDim.x) {
+                const int j = h / hx;
+                const int i = 2 * (h - j * hx) + ((colour + j + b.par) & 1);
+                if (i >= b.nx) continue;
+                p[b.off + j * b.nx + i] = gs_value(p, f, B, b, a.dp, i, j, sig);
+            }
+        } else {
+            const int cnt = b.nx * b.ny;
+            for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+                const int j = c / b.nx, i = c - j * b.nx;
+                if (colour_of(b, i, j) != colour) continue;
+                p[b.off + c] = gs_value(p, f, B, b, a.dp, i, j, sig);
+            }
+        }
+        // cells of one colour are never neighbours, also across blocks
+    }
+    __syncthreads();
+    if (any_odd && colour == 1) {  // the two extra colours of odd periodic wraps
+        for (int extra = 2; extra < 4; ++extra) {
+            for (int bi = 0; bi < a.nb; ++bi) {
+                const DBlock b = B[bi];
+                if (b.oddwrap == 0) continue;
+                const int cnt = b.nx * b.ny;
+                for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+                    const int j = c / b.nx, i = c - j * b.nx;
+                    if (colour_of(b, i, j) != extra) continue;
+                    p[b.off + c] = gs_value(p, f, B, b, a.dp, i, j, sig);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <typename T>
+__device__ void lds_restrict(const LdsArgs& a, const T* pf, const T* ff, T* pc, T* fc,
+                             const DBlock* Bf, const DBlock* Bc, T sig) {
+    for (int bi = 0; bi < a.nb; ++bi) {
+        const DBlock bc = Bc[bi];
+        const DBlock bf = Bf[bi];
+        const int cnt = bc.nx * bc.ny;
+        for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+            const int J = c / bc.nx, I = c - J * bc.nx;
+            fc[bc.off + c] = restrict_at(pf, ff, Bf, bf, a.dp, a.ip, I, J, sig);
+            pc[bc.off + c] = T(0);
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void lds_prolong(const LdsArgs& a, const T* pc, T* pf, const DBlock* Bf, const DBlock* Bc) {
+    for (int bi = 0; bi < a.nb; ++bi) {
+        const DBlock bf = Bf[bi];
+        const int cnt = bf.nx * bf.ny;
+        for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+            const int j = c / bf.nx, i = c - j * bf.nx;
+            pf[bf.off + c] += prolong_at(pc, Bc, bf, bi, a.dp, a.ip, i, j);
+        }
+    }
+    __syncthreads();
+}
+
+// Exact coarsest solve in float64: x = Wl diag(1/(mu + sigma)) Wr b, with the
+// null mode (mu + sigma = 0, singular plane) dropped.
+template <typename T>
+__device__ void lds_coarse(const LdsArgs& a, const LdsView<T>& v, T* p, const T* f, double sig) {
+    const int nc = a.nc;
+    double mumax = 0.0;
+    for (int k = 0; k < nc; ++k) mumax = fmax(mumax, fabs(a.cmu[k]));
+    for (int k = threadIdx.x; k < nc; k += blockDim.x) {
+        double acc = 0.0;
+        const double* row = a.cwr + (long long)k * nc;
+        for (int j = 0; j < nc; ++j) acc += row[j] * double(f[j]);
+        const double d = a.cmu[k] + sig;
+        v.ctmp[k] = fabs(d) > 1e-11 * (mumax + fabs(sig)) ? acc / d : 0.0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+        double acc = 0.0;
+        const double* row = a.cwl + (long long)i * nc;
+        for (int k = 0; k < nc; ++k) acc += row[k] * v.ctmp[k];
+        p[i] = T(acc);
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ void lds_vcycle(const LdsArgs& a, const LdsView<T>& v, double sigd) {
+    const T sig = T(sigd);
+    for (int l = a.L; l < a.nlev - 1; ++l) {
+        const DBlock* Bf = a.Ball + a.ip[a.lvinfo + 4 * l + 1];
+        const DBlock* Bc = a.Ball + a.ip[a.lvinfo + 4 * (l + 1) + 1];
+        T* pf = lds_p(a, v, l);
+        T* ff = pf + a.ip[a.lvinfo + 4 * l];
+        T* pc = lds_p(a, v, l + 1);
+        T* fc = pc + a.ip[a.lvinfo + 4 * (l + 1)];
+        for (int s = 0; s < a.nu1; ++s) {
+            lds_smooth(a, pf, ff, Bf, sig, 0);
+            lds_smooth(a, pf, ff, Bf, sig, 1);
+        }
+        lds_restrict(a, pf, ff, pc, fc, Bf, Bc, sig);
+    }
+    {
+        T* pc = lds_p(a, v, a.nlev - 1);
+        T* fc = pc + a.ip[a.lvinfo + 4 * (a.nlev - 1)];
+        lds_coarse(a, v, pc, fc, sigd);
+    }
+    for (int l = a.nlev - 2; l >= a.L; --l) {
+        const DBlock* Bf = a.Ball + a.ip[a.lvinfo + 4 * l + 1];
+        const DBlock* Bc = a.Ball + a.ip[a.lvinfo + 4 * (l + 1) + 1];
+        T* pf = lds_p(a, v, l);
+        T* ff = pf + a.ip[a.lvinfo + 4 * l];
+        const T* pc = lds_p(a, v, l + 1);
+        lds_prolong(a, pc, pf, Bf, Bc);
+        for (int s = 0; s < a.nu2; ++s) {
+            lds_smooth(a, pf, ff, Bf, sig, 0);
+            lds_smooth(a, pf, ff, Bf, sig, 1);
+        }
+    }
+}
+
+template <typename T>
+__device__ LdsView<T> lds_view(const LdsArgs& a, unsigned char* raw) {
+    LdsView<T> v;
+    v.base = reinterpret_cast<T*>(raw);
+    long long e = 0;
+    for (int l = a.L; l < a.nlev; ++l) e += 2LL * a.ip[a.lvinfo + 4 * l];
+    long long bytes = (e * (long long)sizeof(T) + 15) & ~15LL;
+    v.ctmp = reinterpret_cast<double*>(raw + bytes);
+    v.red = v.ctmp + ((a.nc + 1) & ~1);
+    return v;
+}
+
+// One V-cycle on levels L.. of every active mode: f_L in, p_L out (from 0).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_lds_vcycle(LdsArgs a, T* __restrict__ pL, const T* __restrict__ fL, long long planeL,
+             const double* __restrict__ shift, const int* __restrict__ act,
+             const int* __restrict__ nact) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int item = blockIdx.x;
+    if (item >= *nact) return;
+    const int q = act[item];
+    LdsView<T> v = lds_view<T>(a, lds_raw);
+    T* p = lds_p(a, v, a.L);
+    T* f = p + planeL;
+    for (long long c = threadIdx.x; c < planeL; c += blockDim.x) {
+        f[c] = fL[q * planeL + c];
+        p[c] = T(0);
+    }
+    __syncthreads();
+    lds_vcycle(a, v, shift[q]);
+    for (long long c = threadIdx.x; c < planeL; c += blockDim.x) pL[q * planeL + c] = p[c];
+}
+
+__device__ double lds_block_sum(double x, double* red) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < int(blockDim.x >> 6); ++w) s += red[w];
+    __syncthreads();
+    return s;  // every thread holds the same sum
+}
+
+// Whole solve of one mode in LDS (the plane's full hierarchy fits): iterate
+// V-cycles until ||r_q||^2 <= rtol2 ||f_q||^2 or maxc cycles; each mode stops
+// on its own (early retirement).
+__global__ void __launch_bounds__(256)
+k_lds_full(LdsArgs a, double* __restrict__ p0, const double* __restrict__ f0, long long plane,
+           const double* __restrict__ shift, const int* __restrict__ act,
+           const int* __restrict__ nact, int maxc, double rtol2, int* __restrict__ cyc,
+           double* __restrict__ rnorm, double* __restrict__ fnorm) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int item = blockIdx.x;
+    if (item >= *nact) return;
+    const int q = act[item];
+    LdsView<double> v = lds_view<double>(a, lds_raw);
+    double* p = v.base;
+    double* f = p + plane;
+    const DBlock* B = a.Ball + a.ip[a.lvinfo + 1];
+    double fs = 0.0;
+    for (long long c = threadIdx.x; c < plane; c += blockDim.x) {
+        const double x = f0[q * plane + c];
+        f[c] = x;
+        p[c] = p0[q * plane + c];
+        fs += x * x;
+    }
+    const double fn = lds_block_sum(fs, v.red);
+    const double sig = shift[q];
+    int c = 0;
+    double rn = 0.0;
+    for (;; ++c) {
+        double rs = 0.0;
+        for (int bi = 0; bi < a.nb; ++bi) {
+            const DBlock b = B[bi];
+            const int cnt = b.nx * b.ny;
+            for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+                const int j = k / b.nx, i = k - j * b.nx;
+                const double r = f[b.off + k] - apply_at(p, B, b, a.dp, i, j, sig);
+                rs += r * r;
+            }
+        }
+        rn = lds_block_sum(rs, v.red);
+        if (rn <= rtol2 * fn || c >= maxc) break;
+        lds_vcycle(a, v, sig);
+    }
+    for (long long k = threadIdx.x; k < plane; k += blockDim.x) p0[q * plane + k] = p[k];
+    if (threadIdx.x == 0) {
+        cyc[q] = c;
+        rnorm[q] = rn;
+        fnorm[q] = fn;
+    }
+}
+
+// ================================ launchers ================================
+
+static LdsArgs lds_args(const mbp_plan* P, int L) {
+    LdsArgs a{};
+    a.Ball = P->d_blk;
+    a.dp = P->d_dbl;
+    a.ip = P->d_int;
+    a.lvinfo = P->lvinfo;
+    a.nlev = P->nlev;
+    a.L = L;
+    a.nb = P->g.nb;
+    a.nu1 = P->opt.nu1;
+    a.nu2 = P->opt.nu2;
+    a.cwl = P->d_cwl;
+    a.cwr = P->d_cwr;
+    a.cmu = P->d_cmu;
+    a.nc = P->coarse_n;
+    return a;
+}
+
+template <typename T>
+static T* level_p(const mbp_plan* P, int l);
+template <>
+double* level_p<double>(const mbp_plan* P, int l) { return P->p64[l]; }
+template <>
+float* level_p<float>(const mbp_plan* P, int l) { return P->p32[l]; }
+template <typename T>
+static T* level_f(const mbp_plan* P, int l);
+template <>
+double* level_f<double>(const mbp_plan* P, int l) { return P->f64[l]; }
+template <>
+float* level_f<float>(const mbp_plan* P, int l) { return P->f32[l]; }
+
+static void set_lds(const void* fn, size_t bytes) {
+    if (bytes > 64 * 1024) hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
+template <typename T>
+void launch_vcycle(const mbp_plan* P, T* p0, T* f0, const int* act, const int* nact, int nitems,
+                   hipStream_t s) {
+    const bool is32 = sizeof(T) == 4;
+    const int L = is32 ? P->lds_level32 : P->lds_level;
+    const dim3 blk(kTileX, kRowsPerPass);
+    auto P_ = [&](int l) -> T* { return l == 0 ? p0 : level_p<T>(P, l); };
+    auto F_ = [&](int l) -> T* { return l == 0 ? f0 : level_f<T>(P, l); };
+    for (int l = 0; l < L; ++l) {
+        const Level& Lf = P->levels[l];
+        const Level& Lc = P->levels[l + 1];
+        const DBlock* Bf = P->d_blk + Lf.blk_off;
+        const DBlock* Bc = P->d_blk + Lc.blk_off;
+        for (int it = 0; it < P->opt.nu1; ++it)
+            for (int colour = 0; colour < (Lf.oddwrap ? 4 : 2); ++colour)
+                hipLaunchKernelGGL(k_rbgs<T>, dim3(Lf.ntiles, nitems), blk, 0, s, Bf,
+                                   P->d_tiles + Lf.tile_off, Lf.ntiles, P->d_dbl, P_(l), F_(l),
+                                   (long long)Lf.plane, P->d_shift, act, nact, colour);
+        hipLaunchKernelGGL(k_restrict<T>, dim3(Lc.ntiles, nitems), blk, 0, s, Bf, Bc,
+                           P->d_tiles + Lc.tile_off, Lc.ntiles, P->d_dbl, P->d_int, P_(l), F_(l),
+                           F_(l + 1), P_(l + 1), (long long)Lf.plane, (long long)Lc.plane,
+                           P->d_shift, act, nact);
+    }
+    {
+        LdsArgs a = lds_args(P, L);
+        const size_t bytes = size_t(is32 ? P->lds_bytes32 : P->lds_bytes64);
+        set_lds(reinterpret_cast<const void*>(k_lds_vcycle<T>), bytes);
+        hipLaunchKernelGGL(k_lds_vcycle<T>, dim3(nitems), dim3(256), bytes, s, a, P_(L), F_(L),
+                           (long long)P->levels[L].plane, P->d_shift, act, nact);
+    }
+    for (int l = L - 1; l >= 0; --l) {
+        const Level& Lf = P->levels[l];
+        const Level& Lc = P->levels[l + 1];
+        const DBlock* Bf = P->d_blk + Lf.blk_off;
+        const DBlock* Bc = P->d_blk + Lc.blk_off;
+        hipLaunchKernelGGL(k_prolong<T>, dim3(Lf.ntiles, nitems), blk, 0, s, Bf, Bc,
+                           P->d_tiles + Lf.tile_off, Lf.ntiles, P->d_dbl, P->d_int, P_(l + 1),
+                           P_(l), (long long)Lf.plane, (long long)Lc.plane, act, nact);
+        for (int it = 0; it < P->opt.nu2; ++it)
+            for (int colour = 0; colour < (Lf.oddwrap ? 4 : 2); ++colour)
+                hipLaunchKernelGGL(k_rbgs<T>, dim3(Lf.ntiles, nitems), blk, 0, s, Bf,
+                                   P->d_tiles + Lf.tile_off, Lf.ntiles, P->d_dbl, P_(l), F_(l),
+                                   (long long)Lf.plane, P->d_shift, act, nact, colour);
+    }
+}
+
+template void launch_vcycle<double>(const mbp_plan*, double*, double*, const int*, const int*, int,
+                                    hipStream_t);
+template void launch_vcycle<float>(const mbp_plan*, float*, float*, const int*, const int*, int,
+                                   hipStream_t);
+
+void launch_lds_full(const mbp_plan* P, double* p, const double* f, const int* act, const int* nact,
+                     int nitems, int maxc, double rtol2, int* cyc, double* rnorm, double* fnorm,
+                     hipStream_t s) {
+    LdsArgs a = lds_args(P, 0);
+    const size_t bytes = size_t(P->lds_bytes64);
+    set_lds(reinterpret_cast<const void*>(k_lds_full), bytes);
+    hipLaunchKernelGGL(k_lds_full, dim3(nitems), dim3(256), bytes, s, a, p, f,
+                       (long long)P->plane0, P->d_shift, act, nact, maxc, rtol2, cyc, rnorm, fnorm);
+}
+
+void launch_residual_norm(const mbp_plan* P, const double* p, const double* f, double* rnorm,
+                          const int* act, const int* nact, int nitems, hipStream_t s) {
+    const Level& L = P->levels[0];
+    hipLaunchKernelGGL(k_residual<0>, dim3(L.ntiles, nitems), dim3(kTileX, kRowsPerPass), 0, s,
+                       P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, f,
+                       (long long)L.plane, P->d_shift, act, nact, P->d_part, nullptr, nullptr);
+    hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, P->d_part, L.ntiles, act, nact, rnorm);
+}
+
+void launch_residual_to32(const mbp_plan* P, const double* p, const double* f, float* r32, float* e32,
+                          double* rnorm, const int* act, const int* nact, int nitems, hipStream_t s) {
+    const Level& L = P->levels[0];
+    hipLaunchKernelGGL(k_residual<1>, dim3(L.ntiles, nitems), dim3(kTileX, kRowsPerPass), 0, s,
+                       P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, f,
+                       (long long)L.plane, P->d_shift, act, nact, P->d_part, r32, e32);
+    hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, P->d_part, L.ntiles, act, nact, rnorm);
+}
+
+void launch_add_correction(const mbp_plan* P, double* p, const float* e32, const int* act,
+                           const int* nact, int nitems, hipStream_t s) {
+    const Level& L = P->levels[0];
+    hipLaunchKernelGGL(k_addcorr, dim3(L.ntiles, nitems), dim3(kTileX, kRowsPerPass), 0, s,
+                       P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, p, e32,
+                       (long long)L.plane, act, nact);
+}
+
+void launch_plane_norm(const mbp_plan* P, const double* f, double* out, hipStream_t s) {
+    const Level& L = P->levels[0];
+    hipLaunchKernelGGL(k_sumsq, dim3(L.ntiles, P->g.nz), dim3(kTileX, kRowsPerPass), 0, s,
+                       P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, f, (long long)L.plane,
+                       P->d_part);
+    hipLaunchKernelGGL(k_finish, dim3(P->g.nz), dim3(256), 0, s, P->d_part, L.ntiles, nullptr, nullptr,
+                       out);
+}
+
+void launch_update_active(const mbp_plan* P, double rtol2, int retire, int cycle, hipStream_t s) {
+    hipLaunchKernelGGL(k_update, dim3(1), dim3(1024), 0, s, P->g.nz, P->d_rnorm, P->d_fnorm, rtol2,
+                       retire, cycle, P->d_act, P->d_nact, P->d_cyc, P->d_scal);
+}
+
+void launch_reset_active(const mbp_plan* P, hipStream_t s) {
+    hipLaunchKernelGGL(k_iota, dim3(1), dim3(1024), 0, s, P->d_act, P->g.nz, P->d_nact);
+}
+
+void launch_fill_int(int* p, int n, int v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(256), 0, s, p, n, v);
+}
+
+void launch_zero(double* p, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero64, dim3(1024), dim3(256), 0, s, p, (long long)n);
+}
+
+// Remove the area-weighted mean of one plane; the removed sum(a x) goes to out.
+void launch_singular_fix(const mbp_plan* P, double* plane, double* out_sum, hipStream_t s) {
+    hipLaunchKernelGGL(k_area_dot, dim3(1), dim3(1024), 0, s, plane, P->d_area0, (long long)P->plane0,
+                       out_sum);
+    hipLaunchKernelGGL(k_sub, dim3(256), dim3(256), 0, s, plane, (long long)P->plane0, out_sum,
+                       P->area_sum);
+}
+
+void launch_area_dot(const mbp_plan* P, const double* plane, double* out_sum, hipStream_t s) {
+    hipLaunchKernelGGL(k_area_dot, dim3(1), dim3(1024), 0, s, plane, P->d_area0, (long long)P->plane0,
+                       out_sum);
+}
+
+void launch_apply3d(const mbp_plan* P, const double* p, double* out, hipStream_t s) {
+    const Level& L = P->levels[0];
+    hipLaunchKernelGGL(k_apply3d, dim3(L.ntiles, P->g.nz), dim3(kTileX, kRowsPerPass), 0, s,
+                       P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, out,
+                       P->g.nz, 1.0 / (P->g.dz * P->g.dz), int(P->g.zkind));
+}
+
+}  // namespace mbp

@@ -1,0 +1,636 @@
+// Host-side plan construction: validation, connectivity, multigrid levels,
+// coefficient and transfer tables, colour parities, the coarsest-level
+// eigen-decomposition and the z-transform tables.  No HIP call is made here,
+// so mbp_plan_check works without a GPU.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "internal.h"
+
+namespace mbp {
+
+void options_default(mbp_options* o) {
+    o->precision = MBP_FP64;
+    o->nu1 = 1;
+    o->nu2 = 1;
+    o->max_cycles = 60;
+    o->flags = 0;
+}
+
+// Hyperbolic-tangent face clustering (Sec. 3.1, Table 2 caption).  Two-sided:
+// x(s) = (1 + tanh(a (s - 1/2)) / tanh(a/2)) / 2; lower-end clustering:
+// x(s) = 1 + tanh(a (s - 1)) / tanh(a); upper-end: x(s) = tanh(a s) / tanh(a).
+int grid_tanh(int n, double lmin, double lmax, int type, double factor, double* out) {
+    if (n < 1 || !out || !(lmax > lmin) || !std::isfinite(lmin) || !std::isfinite(lmax) ||
+        !(factor >= 0.0) || !std::isfinite(factor) || type < -1 || type > 1)
+        return MBP_ERR_INVALID;
+    for (int i = 0; i <= n; ++i) {
+        double s = double(i) / n, x;
+        if (factor == 0.0)
+            x = s;
+        else if (type == 0)
+            x = 0.5 * (1.0 + std::tanh(factor * (s - 0.5)) / std::tanh(0.5 * factor));
+        else if (type == -1)
+            x = 1.0 + std::tanh(factor * (s - 1.0)) / std::tanh(factor);
+        else
+            x = std::tanh(factor * s) / std::tanh(factor);
+        if (i == 0) x = 0.0;
+        if (i == n) x = 1.0;
+        out[i] = lmin + (lmax - lmin) * x;
+    }
+    return MBP_OK;
+}
+
+namespace {
+
+bool fail(std::string* err, const std::string& msg) {
+    if (err) *err = msg;
+    return false;
+}
+
+bool increasing(const double* f, int n1) {
+    if (!f) return false;
+    for (int i = 0; i < n1; ++i)
+        if (!std::isfinite(f[i])) return false;
+    for (int i = 1; i < n1; ++i)
+        if (!(f[i] > f[i - 1])) return false;
+    return true;
+}
+
+bool validate(const mbp_block_desc* blocks, int nb, const mbp_synth_desc* z, Geometry& g,
+              std::string* err) {
+    if (!blocks || nb < 1 || nb > 4096) return fail(err, "need 1..4096 blocks");
+    if (!z) return fail(err, "missing z descriptor");
+    if (z->nz < 2 || (z->nz & 1) || z->nz > 4096) return fail(err, "nz must be even, 2..4096");
+    if (!(z->lz > 0.0) || !std::isfinite(z->lz)) return fail(err, "lz must be positive");
+    int lo = z->bc_lo, hi = z->bc_hi;
+    if (lo == MBP_PERIODIC && hi == MBP_PERIODIC)
+        g.zkind = Z_PP;
+    else if (lo == MBP_NEUMANN && hi == MBP_NEUMANN)
+        g.zkind = Z_NN;
+    else if (lo == MBP_DIRICHLET && hi == MBP_DIRICHLET)
+        g.zkind = Z_DD;
+    else if (lo == MBP_NEUMANN && hi == MBP_DIRICHLET)
+        g.zkind = Z_ND;
+    else if (lo == MBP_DIRICHLET && hi == MBP_NEUMANN)
+        g.zkind = Z_DN;
+    else
+        return fail(err, "invalid z condition pair");
+    g.nz = z->nz;
+    g.lz = z->lz;
+    g.dz = z->lz / z->nz;
+    g.zlo = lo;
+    g.zhi = hi;
+    g.nb = nb;
+    g.lo0.resize(nb); g.lo1.resize(nb); g.hi0.resize(nb); g.hi1.resize(nb);
+    g.nx.resize(nb); g.ny.resize(nb); g.xf.resize(nb); g.yf.resize(nb);
+    g.bc.resize(nb); g.nbr.resize(nb);
+    for (int i = 0; i < nb; ++i) {
+        const mbp_block_desc& b = blocks[i];
+        if (b.hi[0] < b.lo[0] || b.hi[1] < b.lo[1]) return fail(err, "block with hi < lo");
+        int64_t nx = int64_t(b.hi[0]) - b.lo[0] + 1, ny = int64_t(b.hi[1]) - b.lo[1] + 1;
+        if (nx > (1 << 16) || ny > (1 << 16)) return fail(err, "block too large");
+        g.lo0[i] = b.lo[0]; g.lo1[i] = b.lo[1]; g.hi0[i] = b.hi[0]; g.hi1[i] = b.hi[1];
+        g.nx[i] = int(nx);
+        g.ny[i] = int(ny);
+        if (!increasing(b.xf, int(nx) + 1) || !increasing(b.yf, int(ny) + 1))
+            return fail(err, "face coordinates must be finite and increasing");
+        if ((b.bc[XM] == MBP_PERIODIC && (nx & 1)) || (b.bc[YM] == MBP_PERIODIC && (ny & 1)))
+            return fail(err, "a periodic direction needs an even cell count");
+        g.xf[i].assign(b.xf, b.xf + nx + 1);
+        g.yf[i].assign(b.yf, b.yf + ny + 1);
+        for (int f = 0; f < 4; ++f) {
+            if (b.bc[f] < MBP_DIRICHLET || b.bc[f] > MBP_PERIODIC)
+                return fail(err, "unknown face condition");
+            g.bc[i][f] = b.bc[f];
+            g.nbr[i][f] = -1;
+        }
+    }
+    // overlapping blocks in index space
+    for (int i = 0; i < nb; ++i)
+        for (int k = i + 1; k < nb; ++k) {
+            bool ox = g.lo0[i] <= g.hi0[k] && g.lo0[k] <= g.hi0[i];
+            bool oy = g.lo1[i] <= g.hi1[k] && g.lo1[k] <= g.hi1[i];
+            if (ox && oy) return fail(err, "blocks overlap in index space");
+        }
+    // connectivity: each joined face has exactly one partner over the same
+    // tangential range (Sec. 3.1)
+    for (int i = 0; i < nb; ++i)
+        for (int f = 0; f < 4; ++f) {
+            int kind = g.bc[i][f];
+            if (kind != MBP_CONNECT && kind != MBP_PERIODIC) continue;
+            int axis = f / 2;
+            int tlo_i = axis == 0 ? g.lo1[i] : g.lo0[i];
+            int thi_i = axis == 0 ? g.hi1[i] : g.hi0[i];
+            int found = -1, count = 0;
+            for (int k = 0; k < nb; ++k) {
+                int tlo_k = axis == 0 ? g.lo1[k] : g.lo0[k];
+                int thi_k = axis == 0 ? g.hi1[k] : g.hi0[k];
+                if (tlo_k != tlo_i || thi_k != thi_i) continue;
+                if (g.bc[k][f ^ 1] != kind) continue;
+                if (kind == MBP_CONNECT) {
+                    if (k == i) continue;
+                    int alo_i = axis == 0 ? g.lo0[i] : g.lo1[i];
+                    int ahi_i = axis == 0 ? g.hi0[i] : g.hi1[i];
+                    int alo_k = axis == 0 ? g.lo0[k] : g.lo1[k];
+                    int ahi_k = axis == 0 ? g.hi0[k] : g.hi1[k];
+                    bool lower = (f & 1) == 0;
+                    if (lower ? (ahi_k + 1 != alo_i) : (ahi_i + 1 != alo_k)) continue;
+                }
+                found = k;
+                ++count;
+            }
+            if (count != 1)
+                return fail(err, "block " + std::to_string(i) + " face " + std::to_string(f) +
+                                     ": needs exactly one partner, found " + std::to_string(count));
+            g.nbr[i][f] = found;
+        }
+    for (int i = 0; i < nb; ++i)
+        for (int f = 0; f < 4; ++f) {
+            int k = g.nbr[i][f];
+            if (k >= 0 && g.nbr[k][f ^ 1] != i) return fail(err, "connectivity not symmetric");
+            if (k < 0) continue;
+            const std::vector<double>& a = f < 2 ? g.yf[i] : g.xf[i];
+            const std::vector<double>& c = f < 2 ? g.yf[k] : g.xf[k];
+            if (a.size() != c.size()) return fail(err, "joined faces differ in cell count");
+            if (g.bc[i][f] == MBP_CONNECT) {
+                double scale = std::max(std::fabs(a.front()), std::fabs(a.back())) + (a.back() - a.front());
+                for (size_t t = 0; t < a.size(); ++t)
+                    if (std::fabs(a[t] - c[t]) > 1e-12 * scale)
+                        return fail(err, "joined faces are not congruent");
+            }
+        }
+    g.dirichlet_xy = false;
+    for (int i = 0; i < nb; ++i)
+        for (int f = 0; f < 4; ++f)
+            if (g.bc[i][f] == MBP_DIRICHLET) g.dirichlet_xy = true;
+    bool zd = g.zlo == MBP_DIRICHLET || g.zhi == MBP_DIRICHLET;
+    g.singular = !g.dirichlet_xy && !zd;
+    return true;
+}
+
+std::vector<double> coarsen_faces(const std::vector<double>& f) {
+    int n = int(f.size()) - 1, nc = n / 2;
+    std::vector<double> c(nc + 1);
+    for (int I = 0; I < nc; ++I) c[I] = f[2 * I];
+    c[nc] = f[n];
+    return c;
+}
+
+// Symmetric eigen-decomposition by cyclic Jacobi rotations (A is overwritten;
+// V receives the eigenvectors as columns, row-major n x n).
+void jacobi_eig(std::vector<double>& A, int n, std::vector<double>& V, std::vector<double>& w) {
+    V.assign(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) V[size_t(i) * n + i] = 1.0;
+    auto a = [&](int i, int j) -> double& { return A[size_t(i) * n + j]; };
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                tot += a(i, j) * a(i, j);
+                if (i != j) off += a(i, j) * a(i, j);
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double apq = a(p, q);
+                if (std::fabs(apq) < 1e-300) continue;
+                double app = a(p, p), aqq = a(q, q);
+                double theta = (aqq - app) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    double akp = a(k, p), akq = a(k, q);
+                    a(k, p) = c * akp - s * akq;
+                    a(k, q) = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double apk = a(p, k), aqk = a(q, k);
+                    a(p, k) = c * apk - s * aqk;
+                    a(q, k) = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double vkp = V[size_t(k) * n + p], vkq = V[size_t(k) * n + q];
+                    V[size_t(k) * n + p] = c * vkp - s * vkq;
+                    V[size_t(k) * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    w.resize(n);
+    for (int i = 0; i < n; ++i) w[i] = a(i, i);
+}
+
+std::vector<int> fft_radices(int m) {
+    std::vector<int> r;
+    while (m % 8 == 0) { r.push_back(8); m /= 8; }
+    while (m % 4 == 0) { r.push_back(4); m /= 4; }
+    while (m % 2 == 0) { r.push_back(2); m /= 2; }
+    for (int p = 3; m > 1; p += 2)
+        while (m % p == 0) { r.push_back(p); m /= p; }
+    return r;
+}
+
+}  // namespace
+
+int build_plan_host(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* z,
+                    const mbp_options* opt, mbp_plan* P, std::string* err) {
+    return build_plan_host_limits(blocks, nblocks, z, opt, 64 * 1024, P, err);
+}
+
+int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* z,
+                           const mbp_options* opt, int64_t lds_limit, mbp_plan* P, std::string* err) {
+    P->lds_limit = lds_limit;
+    if (!validate(blocks, nblocks, z, P->g, err)) return MBP_ERR_INVALID;
+    Geometry& g = P->g;
+    if (opt) {
+        P->opt = *opt;
+        if (P->opt.precision != MBP_FP64 && P->opt.precision != MBP_MIXED) {
+            if (err) *err = "unknown precision";
+            return MBP_ERR_INVALID;
+        }
+        if (P->opt.nu1 < 0 || P->opt.nu2 < 0 || P->opt.nu1 + P->opt.nu2 < 1 || P->opt.nu1 > 8 ||
+            P->opt.nu2 > 8 || P->opt.max_cycles < 1) {
+            if (err) *err = "bad smoothing counts or max_cycles";
+            return MBP_ERR_INVALID;
+        }
+    } else {
+        options_default(&P->opt);
+    }
+    const int nb = g.nb;
+    const int nz = g.nz;
+
+    // ---- modal shifts (Table 1): lambda_q = 2 (cos(2 pi k_q / n) - 1) ----
+    P->lambda.resize(nz);
+    P->shift.resize(nz);
+    for (int q = 0; q < nz; ++q) {
+        long double k;
+        switch (g.zkind) {
+            case Z_PP: k = q; break;
+            case Z_NN: k = 0.5L * q; break;
+            case Z_DD: k = 0.5L * (q + 1); break;
+            default: k = 0.25L * (2 * q + 1); break;
+        }
+        long double lam = 2.0L * (std::cos(2.0L * 3.14159265358979323846264338327950288L * k / nz) - 1.0L);
+        if (g.zkind == Z_PP && q == 0) lam = 0.0L;
+        if (g.zkind == Z_NN && q == 0) lam = 0.0L;
+        P->lambda[q] = double(lam);
+        P->shift[q] = double(lam / ((long double)g.dz * g.dz));
+    }
+
+    // ---- multigrid levels: full coarsening while every block has >= 4 cells
+    //      per direction; odd counts merge their last three cells ----
+    P->levels.clear();
+    {
+        Level L;
+        L.nb = nb;
+        L.nx = g.nx;
+        L.ny = g.ny;
+        L.xf = g.xf;
+        L.yf = g.yf;
+        P->levels.push_back(L);
+    }
+    while (P->levels.size() < 24) {
+        const Level& F = P->levels.back();
+        bool ok = true;
+        for (int b = 0; b < nb; ++b)
+            if (F.nx[b] < 4 || F.ny[b] < 4) ok = false;
+        if (!ok) break;
+        Level C;
+        C.nb = nb;
+        C.nx.resize(nb);
+        C.ny.resize(nb);
+        C.xf.resize(nb);
+        C.yf.resize(nb);
+        for (int b = 0; b < nb; ++b) {
+            C.xf[b] = coarsen_faces(F.xf[b]);
+            C.yf[b] = coarsen_faces(F.yf[b]);
+            C.nx[b] = int(C.xf[b].size()) - 1;
+            C.ny[b] = int(C.yf[b].size()) - 1;
+        }
+        P->levels.push_back(C);
+    }
+    P->nlev = int(P->levels.size());
+    for (Level& L : P->levels) {
+        L.off.resize(nb + 1);
+        L.off[0] = 0;
+        for (int b = 0; b < nb; ++b) L.off[b + 1] = L.off[b] + L.nx[b] * L.ny[b];
+        L.plane = L.off[nb];
+    }
+    P->plane0 = P->levels[0].plane;
+    if (P->plane0 > (int64_t(1) << 30)) {
+        if (err) *err = "plane too large";
+        return MBP_ERR_INVALID;
+    }
+    P->ncells = P->plane0 * nz;
+    P->coarse_n = int(P->levels.back().plane);
+    if (P->coarse_n > 2048) {
+        if (err) *err = "coarsest plane exceeds 2048 cells (block sizes too disparate)";
+        return MBP_ERR_INVALID;
+    }
+    P->block_off.resize(nb + 1);
+    P->block_off[0] = 0;
+    for (int b = 0; b < nb; ++b)
+        P->block_off[b + 1] = P->block_off[b] + int64_t(nz) * g.nx[b] * g.ny[b];
+
+    // ---- tables ----
+    P->hblk.clear();
+    P->hint.clear();
+    P->hdbl.clear();
+    P->htiles.clear();
+    auto push_d = [&](const std::vector<double>& v) {
+        int o = int(P->hdbl.size());
+        P->hdbl.insert(P->hdbl.end(), v.begin(), v.end());
+        return o;
+    };
+    auto push_i = [&](const std::vector<int>& v) {
+        int o = int(P->hint.size());
+        P->hint.insert(P->hint.end(), v.begin(), v.end());
+        return o;
+    };
+    for (int l = 0; l < P->nlev; ++l) {
+        Level& L = P->levels[l];
+        L.blk_off = int(P->hblk.size());
+        // colour parity: a breadth-first walk makes joined neighbours differ
+        std::vector<int> par(nb, -1);
+        for (int s = 0; s < nb; ++s) {
+            if (par[s] >= 0) continue;
+            par[s] = 0;
+            std::vector<int> stack{s};
+            while (!stack.empty()) {
+                int b = stack.back();
+                stack.pop_back();
+                for (int f = 0; f < 4; ++f) {
+                    int k = g.nbr[b][f];
+                    if (k < 0 || par[k] >= 0) continue;
+                    int n;
+                    if (f == XP) n = L.nx[b];
+                    else if (f == XM) n = L.nx[k];
+                    else if (f == YP) n = L.ny[b];
+                    else n = L.ny[k];
+                    par[k] = (par[b] + n) & 1;
+                    stack.push_back(k);
+                }
+            }
+        }
+        for (int b = 0; b < nb; ++b) {
+            DBlock d{};
+            d.nx = L.nx[b];
+            d.ny = L.ny[b];
+            d.off = L.off[b];
+            for (int f = 0; f < 4; ++f) {
+                d.nbr[f] = g.nbr[b][f];
+                d.bc[f] = g.bc[b][f];
+            }
+            d.par = par[b];
+            // an odd cell count around a periodic wrap cannot be two-coloured:
+            // its last column / row is relaxed in two extra passes
+            d.oddwrap = 0;
+            if (g.bc[b][XP] == MBP_PERIODIC && g.nbr[b][XP] == b && (L.nx[b] & 1)) d.oddwrap |= 1;
+            if (g.bc[b][YP] == MBP_PERIODIC && g.nbr[b][YP] == b && (L.ny[b] & 1)) d.oddwrap |= 2;
+            if (d.oddwrap) L.oddwrap = true;
+            // coefficients along each axis
+            for (int axis = 0; axis < 2; ++axis) {
+                const std::vector<double>& F = axis == 0 ? L.xf[b] : L.yf[b];
+                int n = int(F.size()) - 1;
+                std::vector<double> dc(n), cc(n), co(3 * n, 0.0);
+                for (int i = 0; i < n; ++i) {
+                    dc[i] = F[i + 1] - F[i];
+                    cc[i] = 0.5 * (F[i + 1] + F[i]);
+                }
+                int fm = axis == 0 ? XM : YM, fp = axis == 0 ? XP : YP;
+                for (int i = 0; i < n; ++i) {
+                    double wm = 0.0, wp = 0.0, extra = 0.0;
+                    if (i > 0) wm = 1.0 / (dc[i] * (cc[i] - cc[i - 1]));
+                    else {
+                        int k = g.nbr[b][fm];
+                        if (k >= 0) {
+                            const std::vector<double>& Fk = axis == 0 ? L.xf[k] : L.yf[k];
+                            double dk = Fk[Fk.size() - 1] - Fk[Fk.size() - 2];
+                            wm = 1.0 / (dc[0] * 0.5 * (dc[0] + dk));
+                        } else if (g.bc[b][fm] == MBP_DIRICHLET) {
+                            extra += 2.0 / (dc[0] * dc[0]);
+                        }
+                    }
+                    if (i < n - 1) wp = 1.0 / (dc[i] * (cc[i + 1] - cc[i]));
+                    else {
+                        int k = g.nbr[b][fp];
+                        if (k >= 0) {
+                            const std::vector<double>& Fk = axis == 0 ? L.xf[k] : L.yf[k];
+                            double dk = Fk[1] - Fk[0];
+                            wp = 1.0 / (dc[n - 1] * 0.5 * (dc[n - 1] + dk));
+                        } else if (g.bc[b][fp] == MBP_DIRICHLET) {
+                            extra += 2.0 / (dc[n - 1] * dc[n - 1]);
+                        }
+                    }
+                    co[i] = wm;
+                    co[n + i] = wp;
+                    co[2 * n + i] = -(wm + wp) - extra;
+                }
+                if (axis == 0) d.cx = push_d(co);
+                else d.cy = push_d(co);
+            }
+            // transfer tables to the next level
+            d.rsx = d.rsy = d.rwx = d.rwy = d.pcx = d.pcy = d.pwx = d.pwy = -1;
+            if (l + 1 < P->nlev) {
+                const Level& C = P->levels[l + 1];
+                for (int axis = 0; axis < 2; ++axis) {
+                    const std::vector<double>& F = axis == 0 ? L.xf[b] : L.yf[b];
+                    const std::vector<double>& G = axis == 0 ? C.xf[b] : C.yf[b];
+                    int n = int(F.size()) - 1, nc = int(G.size()) - 1;
+                    std::vector<int> rs(nc + 1);
+                    for (int I = 0; I < nc; ++I) rs[I] = 2 * I;
+                    rs[nc] = n;
+                    std::vector<double> rw(n);
+                    for (int i = 0; i < n; ++i) {
+                        int I = std::min(i / 2, nc - 1);
+                        rw[i] = (F[i + 1] - F[i]) / (G[I + 1] - G[I]);
+                    }
+                    // prolongation: coarse centres with a ghost centre beyond each face
+                    std::vector<double> ext(nc + 2);
+                    for (int I = 0; I < nc; ++I) ext[I + 1] = 0.5 * (G[I] + G[I + 1]);
+                    int fm = axis == 0 ? XM : YM, fp = axis == 0 ? XP : YP;
+                    int k = g.nbr[b][fm];
+                    if (k >= 0) {
+                        const std::vector<double>& Gk = axis == 0 ? C.xf[k] : C.yf[k];
+                        ext[0] = G[0] - 0.5 * (Gk[Gk.size() - 1] - Gk[Gk.size() - 2]);
+                    } else {
+                        ext[0] = 2.0 * G[0] - ext[1];
+                    }
+                    k = g.nbr[b][fp];
+                    if (k >= 0) {
+                        const std::vector<double>& Gk = axis == 0 ? C.xf[k] : C.yf[k];
+                        ext[nc + 1] = G[nc] + 0.5 * (Gk[1] - Gk[0]);
+                    } else {
+                        ext[nc + 1] = 2.0 * G[nc] - ext[nc];
+                    }
+                    std::vector<int> pc(n);
+                    std::vector<double> pw(n);
+                    for (int i = 0; i < n; ++i) {
+                        double x = 0.5 * (F[i] + F[i + 1]);
+                        int t = 0;
+                        while (t < nc && ext[t + 1] <= x) ++t;
+                        pc[i] = t - 1;
+                        pw[i] = (ext[t + 1] - x) / (ext[t + 1] - ext[t]);
+                    }
+                    if (axis == 0) {
+                        d.rsx = push_i(rs); d.rwx = push_d(rw); d.pcx = push_i(pc); d.pwx = push_d(pw);
+                    } else {
+                        d.rsy = push_i(rs); d.rwy = push_d(rw); d.pcy = push_i(pc); d.pwy = push_d(pw);
+                    }
+                }
+            }
+            P->hblk.push_back(d);
+        }
+        // tiles of the global-memory kernels
+        L.tile_off = int(P->htiles.size());
+        for (int b = 0; b < nb; ++b)
+            for (int y0 = 0; y0 < L.ny[b]; y0 += kTileY)
+                for (int x0 = 0; x0 < L.nx[b]; x0 += kTileX) P->htiles.push_back(make_int4(b, x0, y0, 0));
+        L.ntiles = int(P->htiles.size()) - L.tile_off;
+    }
+
+    // ---- finest-plane areas (compatibility projection, gauge) ----
+    {
+        const Level& L = P->levels[0];
+        P->areas0.resize(L.plane);
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b)
+            for (int j = 0; j < L.ny[b]; ++j)
+                for (int i = 0; i < L.nx[b]; ++i) {
+                    double a = (L.xf[b][i + 1] - L.xf[b][i]) * (L.yf[b][j + 1] - L.yf[b][j]);
+                    P->areas0[L.off[b] + j * L.nx[b] + i] = a;
+                    s += a;
+                }
+        P->area_sum = s;
+    }
+
+    // ---- coarsest plane: eigen-decomposition of the symmetrised operator ----
+    {
+        const Level& L = P->levels.back();
+        const int nc = int(L.plane);
+        std::vector<double> A(size_t(nc) * nc, 0.0), area(nc);
+        for (int b = 0; b < nb; ++b) {
+            const DBlock& d = P->hblk[L.blk_off + b];
+            const double* cx = &P->hdbl[d.cx];
+            const double* cy = &P->hdbl[d.cy];
+            for (int j = 0; j < d.ny; ++j)
+                for (int i = 0; i < d.nx; ++i) {
+                    int c = d.off + j * d.nx + i;
+                    area[c] = (L.xf[b][i + 1] - L.xf[b][i]) * (L.yf[b][j + 1] - L.yf[b][j]);
+                    A[size_t(c) * nc + c] += cx[2 * d.nx + i] + cy[2 * d.ny + j];
+                    auto addnb = [&](int f, double w, int ii, int jj) {
+                        if (w == 0.0) return;
+                        int bb = b;
+                        if (ii < 0 || ii >= d.nx || jj < 0 || jj >= d.ny) {
+                            bb = g.nbr[b][f];
+                            const DBlock& e = P->hblk[L.blk_off + bb];
+                            if (ii < 0) ii = e.nx - 1;
+                            if (ii >= d.nx) ii = 0;
+                            if (jj < 0) jj = e.ny - 1;
+                            if (jj >= d.ny) jj = 0;
+                        }
+                        const DBlock& e = P->hblk[L.blk_off + bb];
+                        A[size_t(c) * nc + (e.off + jj * e.nx + ii)] += w;
+                    };
+                    addnb(XM, cx[i], i - 1, j);
+                    addnb(XP, cx[d.nx + i], i + 1, j);
+                    addnb(YM, cy[j], i, j - 1);
+                    addnb(YP, cy[d.ny + j], i, j + 1);
+                }
+        }
+        // S = diag(a)^(1/2) A diag(a)^(-1/2) is symmetric
+        std::vector<double> S(size_t(nc) * nc);
+        for (int r = 0; r < nc; ++r)
+            for (int c = 0; c < nc; ++c)
+                S[size_t(r) * nc + c] = std::sqrt(area[r]) * A[size_t(r) * nc + c] / std::sqrt(area[c]);
+        for (int r = 0; r < nc; ++r)
+            for (int c = r + 1; c < nc; ++c) {
+                double m = 0.5 * (S[size_t(r) * nc + c] + S[size_t(c) * nc + r]);
+                S[size_t(r) * nc + c] = S[size_t(c) * nc + r] = m;
+            }
+        std::vector<double> V, mu;
+        jacobi_eig(S, nc, V, mu);
+        P->coarse_mu = mu;
+        P->coarse_wl.resize(size_t(nc) * nc);
+        P->coarse_wr.resize(size_t(nc) * nc);
+        for (int r = 0; r < nc; ++r)
+            for (int k = 0; k < nc; ++k) {
+                P->coarse_wl[size_t(r) * nc + k] = V[size_t(r) * nc + k] / std::sqrt(area[r]);
+                P->coarse_wr[size_t(k) * nc + r] = V[size_t(r) * nc + k] * std::sqrt(area[r]);
+            }
+    }
+
+    // ---- LDS-resident levels: the smallest index whose remaining hierarchy
+    //      (p and rhs of every level) fits the LDS budget ----
+    {
+        const int64_t budget = P->lds_limit;
+        auto need = [&](int L0, int64_t elem) {
+            int64_t e = 0;
+            for (int l = L0; l < P->nlev; ++l) e += 2 * P->levels[l].plane;
+            return e * elem + int64_t(P->coarse_n) * 8 + 1024;
+        };
+        P->lds_level = P->nlev - 1;
+        for (int l = P->nlev - 1; l >= 0; --l)
+            if (need(l, 8) <= budget) P->lds_level = l;
+        P->lds_level32 = P->nlev - 1;
+        for (int l = P->nlev - 1; l >= 0; --l)
+            if (need(l, 4) <= budget) P->lds_level32 = l;
+        P->lds_bytes64 = need(P->lds_level, 8);
+        P->lds_bytes32 = need(P->lds_level32, 4);
+        if (P->lds_bytes64 > budget) {
+            if (err) *err = "coarsest plane does not fit the LDS budget";
+            return MBP_ERR_INVALID;
+        }
+        int64_t o = 0;
+        for (int l = 0; l < P->nlev; ++l) {
+            P->levels[l].lds_off = l >= P->lds_level ? o : -1;
+            if (l >= P->lds_level) o += 2 * P->levels[l].plane;
+        }
+    }
+
+    // ---- level summary for the kernels ----
+    {
+        std::vector<int> li;
+        for (const Level& L : P->levels) {
+            li.push_back(int(L.plane));
+            li.push_back(L.blk_off);
+            li.push_back(L.tile_off);
+            li.push_back(L.ntiles);
+        }
+        P->lvinfo = push_i(li);
+    }
+
+    // ---- z transform tables (twiddles in extended precision) ----
+    P->fft.n = nz;
+    P->fft.m = nz / 2;
+    P->fft.radices = fft_radices(P->fft.m);
+    for (int R : P->fft.radices)
+        if (R > 31 || R == 9) {
+            if (err) *err = "nz/2 has a prime factor above 31";
+            return MBP_ERR_INVALID;
+        }
+    {
+        const long double PI = 3.14159265358979323846264338327950288L;
+        const int n = nz, m = nz / 2;
+        auto cexp_table = [&](int count, auto angle) {
+            std::vector<double> t(2 * size_t(count));
+            for (int k = 0; k < count; ++k) {
+                long double a = angle(k);
+                t[2 * k] = double(std::cos(a));
+                t[2 * k + 1] = double(std::sin(a));
+            }
+            return t;
+        };
+        P->fft_tw = push_d(cexp_table(m, [&](int t) { return -2.0L * PI * t / m; }));
+        P->fft_twn = push_d(cexp_table(m + 1, [&](int k) { return -2.0L * PI * k / n; }));
+        P->fft_post = push_d(cexp_table(n + 1, [&](int k) { return -PI * k / (2.0L * n); }));
+        P->fft_pre4 = push_d(cexp_table(m, [&](int k) { return -PI * (4.0L * k + 1.0L) / (4.0L * n); }));
+        P->fft_post4 = push_d(cexp_table(m, [&](int k) { return -PI * k / (long double)n; }));
+    }
+    return MBP_OK;
+}
+
+}  // namespace mbp

@@ -1,0 +1,164 @@
+"""HIP path vs the CPU oracle, element by element, on small seeded problems.
+
+Sizes are chosen so the oracle finishes in seconds while the GPU kernels see
+several tiles, ragged tile tails, odd-size coarsening (three-cell merges),
+odd periodic wraps (extra smoothing colours), joined blocks and stretched
+faces.  Tolerances: transforms and the operator to ~1e-12 (FP64 rounding);
+solves to the stated bar, relative residual <= 1e-10 (checked with the
+oracle's own operator) and relative solution error <= 1e-9.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["PP", "NN", "DD", "ND", "DN"]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mbp():
+    import paper_2106_03583_amd as m
+    return m
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def two_block(nz, zpair, nx1=12, nx2=7, ny=9):
+    """Two joined blocks side by side, stretched y, ragged x sizes."""
+    yf = W.faces(ny, 0.0, 1.0, 0, 1.3)
+    A = W.Block((1, 1), (nx1, ny), W.faces(nx1, 0.0, 1.0), yf, (W.DIRICHLET, W.CONNECT, W.NEUMANN, W.NEUMANN))
+    B = W.Block((nx1 + 1, 1), (nx1 + nx2, ny), W.faces(nx2, 1.0, 1.6, 0, 0.8), yf.copy(),
+                (W.CONNECT, W.NEUMANN, W.NEUMANN, W.DIRICHLET))
+    return W.Problem([A, B], nz, 1.3, W.PAIRS[zpair], name=f"two_block_{zpair}_{nz}")
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("nz", [2, 4, 6, 8, 10, 14, 22, 26, 32, 48, 62, 64, 96, 160, 1024])
+def test_transforms(torch_cuda, mbp, kind, nz):
+    torch = torch_cuda
+    prob = two_block(nz, kind)
+    print(f"transform {kind} nz={nz}", flush=True)
+    plan = mbp.Plan(prob)
+    f = W.rhs(prob, 11 + nz)
+    fh = torch.empty(plan.ncells, dtype=torch.float64, device="cuda")
+    plan.forward(dev(torch, f), fh)
+    ref = oracle.modal_rhs(prob, f, range(nz))  # (nz, plane)
+    got = host(fh).reshape(nz, -1)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= 1e-12 * scale * max(1.0, np.sqrt(nz))
+    # inverse of random modal data
+    ph = np.random.default_rng(nz).standard_normal(plan.ncells)
+    p = torch.empty(plan.ncells, dtype=torch.float64, device="cuda")
+    plan.inverse(dev(torch, ph), p)
+    T = oracle.basis(kind, nz)
+    g = oracle.Geometry(prob)
+    phm = ph.reshape(nz, -1)
+    expect = np.concatenate([(T @ phm[:, g.off2[i]:g.off2[i + 1]]).ravel() for i in range(g.nb)])
+    assert np.abs(host(p) - expect).max() <= 1e-12 * np.abs(expect).max() * max(1.0, np.sqrt(nz))
+    plan.close()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_apply_operator(torch_cuda, mbp, kind):
+    torch = torch_cuda
+    prob = W.lshape(12, 6, 1.5, 1.0)
+    prob.zbc = W.PAIRS[kind]
+    plan = mbp.Plan(prob)
+    p = np.random.default_rng(3).standard_normal(plan.ncells)
+    out = torch.empty(plan.ncells, dtype=torch.float64, device="cuda")
+    plan.apply(dev(torch, p), out)
+    ref = oracle.apply_3d(oracle.Geometry(prob), p)
+    assert np.abs(host(out) - ref).max() <= 1e-12 * np.abs(ref).max()
+    plan.close()
+
+
+def _problems():
+    out = [
+        W.config1(),
+        W.lshape(32, 16, 1.5, 2.0),
+        W.box(96, 80, 12, 0.75, 0.625, 0.1, "DN", "NN", "ND", xfactor=1.7, yfactor=1.2, name="box96x80_DN_NN_ND"),
+        W.box(40, 36, 10, 40 / 128, 36 / 128, 10 / 128, "PP", "DD", "DD", name="box40x36_oddwrap"),
+        W.box(70, 130, 8, 70 / 128, 130 / 128, 8 / 128, "ND", "PP", "NN", xfactor=2.0, name="box70x130_ragged"),
+        two_block(6, "PP", 100, 36, 44),
+    ]
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("prob", _problems(), ids=lambda p: p.name)
+def test_solve_parity(torch_cuda, mbp, prob, precision):
+    torch = torch_cuda
+    print(f"solve {prob.name} {precision}", flush=True)
+    f = W.rhs(prob, 21)
+    ref = oracle.solve(prob, f)  # projects f when singular, gauge-fixed
+    fproj = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
+    plan = mbp.Plan(prob, precision=precision)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.PROJECT_RHS)
+    got = host(p)
+    res = oracle.rel_residual(prob, got, fproj)
+    err = oracle.rel_error(got, ref)
+    print(f"  {info} residual={res:.2e} error={err:.2e}", flush=True)
+    assert info.status == 0
+    assert info.rel_residual <= 1e-10
+    assert res <= 1e-10
+    assert err <= 1e-9
+    plan.close()
+
+
+@pytest.mark.parametrize("retire", [False, True])
+def test_retirement_same_answer(torch_cuda, mbp, retire):
+    torch = torch_cuda
+    prob = W.lshape(32, 16, 1.5, 2.0)
+    f = W.rhs(prob, 5, "normal")
+    ref = oracle.solve(prob, f)
+    plan = mbp.Plan(prob)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    flags = mbp.PROJECT_RHS | (mbp.RETIRE if retire else 0)
+    info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=flags)
+    assert oracle.rel_error(host(p), ref) <= 1e-9
+    cpm = info.cycles_per_mode
+    if retire:
+        # the slowest modes are the small-|lambda| ones (Appendix B trend)
+        assert cpm.max() > cpm.min()
+        assert cpm[0] == cpm.max()
+    plan.close()
+
+
+def test_status_codes(torch_cuda, mbp):
+    torch = torch_cuda
+    prob = W.lshape(8, 4, 1.5, 1.0)  # singular
+    plan = mbp.Plan(prob, max_cycles=60)
+    f = W.rhs(prob, 1)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, flags=0, raise_on_error=False)
+    assert info.status == mbp.ERR_INCOMPATIBLE
+    bad = f.copy()
+    bad[17] = np.nan
+    info = plan.solve(dev(torch, bad), p, flags=mbp.PROJECT_RHS, raise_on_error=False)
+    assert info.status == mbp.ERR_NONFINITE
+    plan.close()
+    plan = mbp.Plan(W.box(64, 64, 4, 1, 1, 1, "NN", "DD", "NN"), max_cycles=1)
+    f = W.rhs(plan.problem, 2)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, raise_on_error=False)
+    assert info.status == mbp.ERR_NOT_CONVERGED
+    with pytest.raises(ValueError):
+        plan.solve(dev(torch, f[:-1]), p)
+    plan.close()
