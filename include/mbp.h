@@ -97,12 +97,19 @@ typedef struct {
  *   nu1, nu2   red-black Gauss-Seidel sweeps before / after the
  *              coarse-grid correction                            [1, 1]
  *   max_cycles cap on V-cycles (or refinement steps)             [60]
- *   flags      default solve flags OR-ed into each solve          [0] */
+ *   flags      default solve flags OR-ed into each solve          [0]
+ *   etol       target of the estimated relative solution error of
+ *              each mode, ||rhat_q|| / (mu_0 + |sigma_q|) <= etol ||phat_q||
+ *              / 2, with mu_0 the smallest non-zero eigenvalue magnitude
+ *              of the coarsest plane operator (a lower bound of the fine
+ *              one, so the estimate is conservative); 0 = 10 * rtol,
+ *              negative = off                                    [0] */
 typedef struct {
     int32_t precision;
     int32_t nu1, nu2;
     int32_t max_cycles;
     int32_t flags;
+    double etol;
 } mbp_options;
 
 /* Per-solve report (caller-owned).

@@ -40,7 +40,7 @@ class SynthDesc(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
-                ("max_cycles", C.c_int32), ("flags", C.c_int32)]
+                ("max_cycles", C.c_int32), ("flags", C.c_int32), ("etol", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -147,9 +147,9 @@ class _Desc:
         self.z = SynthDesc(int(problem.nz), float(problem.lz), int(problem.zbc[0]), int(problem.zbc[1]))
 
 
-def _options(precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0) -> Options:
+def _options(precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0, etol=0.0) -> Options:
     prec = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}[precision]
-    return Options(prec, nu1, nu2, max_cycles, flags)
+    return Options(prec, nu1, nu2, max_cycles, flags, etol)
 
 
 def plan_check(problem, **opts) -> dict:
@@ -207,10 +207,10 @@ class Info:
 
 
 class Plan:
-    def __init__(self, problem, precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0):
+    def __init__(self, problem, precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0, etol=0.0):
         self.problem = problem
         self._desc = _Desc(problem)
-        self._opt = _options(precision, nu1, nu2, max_cycles, flags)
+        self._opt = _options(precision, nu1, nu2, max_cycles, flags, etol)
         self._h = C.c_void_p()
         _check(lib.mbp_plan_create(self._desc.blocks, self._desc.nblocks, C.byref(self._desc.z),
                                    C.byref(self._opt), C.byref(self._h)), "mbp_plan_create")
@@ -289,8 +289,8 @@ def solve_batch(plans: Sequence[Plan], rhs: Sequence, p: Sequence, rtol=1e-10, f
 
 class Server:
     def __init__(self, hbm_budget: int, slots: int = 4, precision="mixed", nu1=1, nu2=1, max_cycles=60,
-                 flags=0):
-        self._opt = _options(precision, nu1, nu2, max_cycles, flags)
+                 flags=0, etol=0.0):
+        self._opt = _options(precision, nu1, nu2, max_cycles, flags, etol)
         self._h = C.c_void_p()
         _check(lib.mbp_server_create(int(hbm_budget), int(slots), C.byref(self._opt), C.byref(self._h)),
                "mbp_server_create")

@@ -92,6 +92,8 @@ struct mbp_plan {
     int coarse_n = 0;             // cells of the coarsest plane
     std::vector<double> lambda;   // Table-1 eigenvalues
     std::vector<double> shift;    // lambda_q / dz^2
+    double mu0 = 0.0;             // smallest non-zero |eigenvalue| of the coarsest plane operator
+    std::vector<double> sabs;     // mu0 + |shift_q|: lower bound of |eigenvalues| of mode q
     mbp::FFTPlan fft;
     int fft_tw = 0, fft_twn = 0, fft_post = 0, fft_pre4 = 0, fft_post4 = 0;  // double-pool offsets
     int fft_ntiles = 0;
@@ -99,6 +101,10 @@ struct mbp_plan {
     void* d_ftiles_inv = nullptr;
     int64_t lds_limit = 64 * 1024;  // LDS bytes one workgroup may use
     int lvinfo = 0;               // int-pool offset: per level {plane, blk_off, tile_off, ntiles}
+    std::vector<int> mtile_off, mtile_cnt;  // fused-sweep strips per level
+    std::vector<char> march_ok;   // level runs the fused one-pass sweeps
+    void* d_mtiles = nullptr;
+    size_t mtile_bytes = 0;
     // host tables (uploaded into one device allocation)
     std::vector<mbp::DBlock> hblk;
     std::vector<int> hint;
@@ -129,10 +135,15 @@ struct mbp_plan {
     double* phat = nullptr;       // nz * plane0 modal solution
     std::vector<double*> p64, f64;  // levels >= 1, FP64
     std::vector<float*> p32, f32;   // levels >= 0, FP32 (mixed precision)
+    double* phatB = nullptr;        // second buffer of the finest level (out-of-place sweeps)
+    std::vector<double*> p64B;      // levels >= 1
+    std::vector<float*> p32B;       // levels >= 0
     double* d_part = nullptr;     // per-mode partial sums (nz * nparts * 2)
     int nparts = 0;
     double* d_fnorm = nullptr;    // nz: ||fhat_q||^2
     double* d_rnorm = nullptr;    // nz: ||rhat_q||^2
+    double* d_pnorm = nullptr;    // nz: ||phat_q||^2
+    double* d_sabs = nullptr;     // nz: mu0 + |shift_q|
     int* d_act = nullptr;         // active mode list (nz)
     int* d_nact = nullptr;        // 1 int
     int* d_cyc = nullptr;         // nz: cycles per mode
@@ -164,9 +175,30 @@ void launch_forward(const mbp_plan* P, const double* f, double* fhat, int* nonfi
 void launch_inverse(const mbp_plan* P, const double* phat, double* p, hipStream_t s);
 void launch_apply3d(const mbp_plan* P, const double* p, double* out, hipStream_t s);
 
+// One V-cycle on every active mode.  p0 / f0: finest-level iterate and rhs;
+// p0B: second finest buffer for the out-of-place sweeps (the result is
+// always left in p0).  With norm0 the finest post-smoothing sweep also
+// produces per-strip squared residuals; returns the strip count then (0 if
+// the caller must evaluate the residual itself).
 template <typename T>
-void launch_vcycle(const mbp_plan* P, T* p0, T* f0, const int* act, const int* nact, int nitems,
-                   hipStream_t s);
+int launch_vcycle(const mbp_plan* P, T* p0, T* p0B, T* f0, const int* act, const int* nact,
+                  int nitems, bool norm0, hipStream_t s);
+void launch_finish(const mbp_plan* P, int nparts, double* out, const int* act, const int* nact,
+                   int nitems, hipStream_t s);
+
+// march.hip
+struct MTile;
+bool march_level_ok(const mbp_plan* P, int l);
+void march_build_tiles_bytes(const mbp_plan* P, int l, int seg, std::vector<unsigned char>& out, int* count);
+template <typename T>
+void march_pre(const mbp_plan* P, int l, const T* pold, T* pnew, const T* f, T* fc, T* pc,
+               const int* act, const int* nact, int nitems, hipStream_t s);
+template <typename T>
+void march_sweep(const mbp_plan* P, int l, const T* pold, T* pnew, const T* f, const int* act,
+                 const int* nact, int nitems, hipStream_t s);
+template <typename T>
+void march_post(const mbp_plan* P, int l, const T* pold, T* pnew, const T* f, const T* ec, bool norm,
+                const int* act, const int* nact, int nitems, hipStream_t s);
 void launch_residual_norm(const mbp_plan* P, const double* p, const double* f, double* rnorm,
                           const int* act, const int* nact, int nitems, hipStream_t s);
 void launch_residual_to32(const mbp_plan* P, const double* p, const double* f, float* r32,
@@ -175,7 +207,8 @@ void launch_residual_to32(const mbp_plan* P, const double* p, const double* f, f
 void launch_add_correction(const mbp_plan* P, double* p, const float* e32, const int* act,
                            const int* nact, int nitems, hipStream_t s);
 void launch_plane_norm(const mbp_plan* P, const double* f, double* out, hipStream_t s);
-void launch_update_active(const mbp_plan* P, double rtol2, int retire, int cycle, hipStream_t s);
+void launch_update_active(const mbp_plan* P, double rtol2, double etol2, int retire, int cycle,
+                          hipStream_t s);
 void launch_zero(double* p, size_t n, hipStream_t s);
 void launch_zero32(float* p, size_t n, hipStream_t s);
 void launch_singular_fix(const mbp_plan* P, double* plane, double* out_mean, hipStream_t s);

@@ -249,7 +249,7 @@ k_residual(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int nti
     const double* fq = f + q * plane;
     const double sig = shift[q];
     const int i = t.y + threadIdx.x;
-    double acc = 0.0;
+    double acc = 0.0, pacc = 0.0;
     if (i < b.nx) {
         for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
             const int j = t.z + r;
@@ -257,6 +257,7 @@ k_residual(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int nti
             const long long c = b.off + j * b.nx + i;
             const double res = fq[c] - apply_at(pq, B, b, dp, i, j, sig);
             acc += res * res;
+            pacc += pq[c] * pq[c];
             if (MODE == 1) {
                 r32[q * plane + c] = float(res);
                 e32[q * plane + c] = 0.0f;
@@ -264,7 +265,11 @@ k_residual(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int nti
         }
     }
     const double s = block_sum(acc, scratch);
-    if (threadIdx.x == 0 && threadIdx.y == 0) part[(long long)q * ntiles + tix] = s;
+    const double sp = block_sum(pacc, scratch);
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        part[2 * ((long long)q * ntiles + tix)] = s;
+        part[2 * ((long long)q * ntiles + tix) + 1] = sp;
+    }
 }
 
 // Per-tile partial sums of fhat_q^2.
@@ -287,21 +292,32 @@ k_sumsq(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntiles
             acc += v * v;
         }
     const double s = block_sum(acc, scratch);
-    if (threadIdx.x == 0 && threadIdx.y == 0) part[(long long)q * ntiles + tix] = s;
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        part[2 * ((long long)q * ntiles + tix)] = s;
+        part[2 * ((long long)q * ntiles + tix) + 1] = 0.0;
+    }
 }
 
-// Deterministic per-mode reduction of the tile partials (one workgroup per item).
+// Deterministic per-mode reduction of the tile partial pairs (one workgroup
+// per item): out[q] = sum of first entries, out2[q] (optional) of seconds.
 __global__ void __launch_bounds__(256)
 k_finish(const double* __restrict__ part, int ntiles, const int* __restrict__ act,
-         const int* __restrict__ nact, double* __restrict__ out) {
+         const int* __restrict__ nact, double* __restrict__ out, double* __restrict__ out2) {
     __shared__ double scratch[8];
     const int item = blockIdx.x;
     if (act && item >= *nact) return;
     const int q = act ? act[item] : item;
-    double acc = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) acc += part[(long long)q * ntiles + t];
+    double acc = 0.0, acc2 = 0.0;
+    for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+        acc += part[2 * ((long long)q * ntiles + t)];
+        acc2 += part[2 * ((long long)q * ntiles + t) + 1];
+    }
     const double s = block_sum(acc, scratch);
-    if (threadIdx.x == 0) out[q] = s;
+    const double s2 = block_sum(acc2, scratch);
+    if (threadIdx.x == 0) {
+        out[q] = s;
+        if (out2) out2[q] = s2;
+    }
 }
 
 __global__ void __launch_bounds__(256)
@@ -327,7 +343,8 @@ k_addcorr(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntil
 // ratio_q = ||r_q||^2 / ||f_q||^2.  scal[0] = max ratio over the active list.
 // With retirement, converged modes record the cycle count and leave the list.
 __global__ void __launch_bounds__(1024)
-k_update(int nz, const double* __restrict__ rnorm, const double* __restrict__ fnorm, double rtol2,
+k_update(int nz, const double* __restrict__ rnorm, const double* __restrict__ fnorm,
+         const double* __restrict__ pnorm, const double* __restrict__ sabs, double rtol2, double etol2,
          int retire, int cycle, int* __restrict__ act, int* __restrict__ nact, int* __restrict__ cyc,
          double* __restrict__ scal) {
     __shared__ int keep[4096];
@@ -340,7 +357,9 @@ k_update(int nz, const double* __restrict__ rnorm, const double* __restrict__ fn
         const double fn = fnorm[q];
         const double ratio = fn > 0.0 ? rnorm[q] / fn : (rnorm[q] > 0.0 ? 1e300 : 0.0);
         m = fmax(m, ratio);
-        const bool done = ratio <= rtol2;
+        // estimated error ||r|| / (mu0 + |sigma|), doubled, against etol ||p||
+        const bool err_ok = etol2 < 0.0 || 4.0 * rnorm[q] <= etol2 * sabs[q] * sabs[q] * pnorm[q];
+        const bool done = ratio <= rtol2 && err_ok;
         keep[it] = done ? -1 : q;
         if (done || !retire) cyc[q] = cycle;
     }
@@ -351,6 +370,11 @@ k_update(int nz, const double* __restrict__ rnorm, const double* __restrict__ fn
         double g = 0.0;
         for (int w = 0; w < int(blockDim.x >> 6); ++w) g = fmax(g, mx[w]);
         scal[0] = g;
+        if (!retire) {  // lockstep: done when every mode passes both tests
+            int c = 0;
+            for (int it = 0; it < n; ++it) c += keep[it] >= 0 ? 1 : 0;
+            scal[1] = double(c);
+        }
         if (retire) {
             int c = 0;
             for (int it = 0; it < n; ++it)
@@ -653,9 +677,10 @@ __device__ double lds_block_sum(double x, double* red) {
 // on its own (early retirement).
 __global__ void __launch_bounds__(256)
 k_lds_full(LdsArgs a, double* __restrict__ p0, const double* __restrict__ f0, long long plane,
-           const double* __restrict__ shift, const int* __restrict__ act,
-           const int* __restrict__ nact, int maxc, double rtol2, int* __restrict__ cyc,
-           double* __restrict__ rnorm, double* __restrict__ fnorm) {
+           const double* __restrict__ shift, const double* __restrict__ sabs,
+           const int* __restrict__ act, const int* __restrict__ nact, int maxc, double rtol2,
+           double etol2, int* __restrict__ cyc, double* __restrict__ rnorm,
+           double* __restrict__ fnorm) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int item = blockIdx.x;
     if (item >= *nact) return;
@@ -675,8 +700,9 @@ k_lds_full(LdsArgs a, double* __restrict__ p0, const double* __restrict__ f0, lo
     const double sig = shift[q];
     int c = 0;
     double rn = 0.0;
+    const double sa = sabs[q];
     for (;; ++c) {
-        double rs = 0.0;
+        double rs = 0.0, ps = 0.0;
         for (int bi = 0; bi < a.nb; ++bi) {
             const DBlock b = B[bi];
             const int cnt = b.nx * b.ny;
@@ -684,10 +710,13 @@ k_lds_full(LdsArgs a, double* __restrict__ p0, const double* __restrict__ f0, lo
                 const int j = k / b.nx, i = k - j * b.nx;
                 const double r = f[b.off + k] - apply_at(p, B, b, a.dp, i, j, sig);
                 rs += r * r;
+                ps += p[b.off + k] * p[b.off + k];
             }
         }
         rn = lds_block_sum(rs, v.red);
-        if (rn <= rtol2 * fn || c >= maxc) break;
+        const double pn = lds_block_sum(ps, v.red);
+        const bool err_ok = etol2 < 0.0 || 4.0 * rn <= etol2 * sa * sa * pn;
+        if ((rn <= rtol2 * fn && err_ok) || c >= maxc) break;
         lds_vcycle(a, v, sig);
     }
     for (long long k = threadIdx.x; k < plane; k += blockDim.x) p0[q * plane + k] = p[k];
@@ -736,27 +765,50 @@ static void set_lds(const void* fn, size_t bytes) {
 }
 
 template <typename T>
-void launch_vcycle(const mbp_plan* P, T* p0, T* f0, const int* act, const int* nact, int nitems,
-                   hipStream_t s) {
+static T* level_pB(const mbp_plan* P, int l);
+template <>
+double* level_pB<double>(const mbp_plan* P, int l) { return P->p64B[l]; }
+template <>
+float* level_pB<float>(const mbp_plan* P, int l) { return P->p32B[l]; }
+
+template <typename T>
+int launch_vcycle(const mbp_plan* P, T* p0, T* p0B, T* f0, const int* act, const int* nact, int nitems,
+                  bool norm0, hipStream_t s) {
     const bool is32 = sizeof(T) == 4;
     const int L = is32 ? P->lds_level32 : P->lds_level;
     const dim3 blk(kTileX, kRowsPerPass);
+    const int nu1 = P->opt.nu1, nu2 = P->opt.nu2;
+    const bool fused_ok = ((nu1 + nu2) % 2 == 0) && nu1 >= 1 && nu2 >= 1;
     auto P_ = [&](int l) -> T* { return l == 0 ? p0 : level_p<T>(P, l); };
+    auto PB_ = [&](int l) -> T* { return l == 0 ? p0B : level_pB<T>(P, l); };
     auto F_ = [&](int l) -> T* { return l == 0 ? f0 : level_f<T>(P, l); };
+    auto use_march = [&](int l) { return fused_ok && P->march_ok[l] && PB_(l) != nullptr; };
+    auto rbgs = [&](int l) {
+        const Level& Lf = P->levels[l];
+        for (int colour = 0; colour < (Lf.oddwrap ? 4 : 2); ++colour)
+            hipLaunchKernelGGL(k_rbgs<T>, dim3(Lf.ntiles, nitems), blk, 0, s, P->d_blk + Lf.blk_off,
+                               P->d_tiles + Lf.tile_off, Lf.ntiles, P->d_dbl, P_(l), F_(l),
+                               (long long)Lf.plane, P->d_shift, act, nact, colour);
+    };
     for (int l = 0; l < L; ++l) {
         const Level& Lf = P->levels[l];
         const Level& Lc = P->levels[l + 1];
-        const DBlock* Bf = P->d_blk + Lf.blk_off;
-        const DBlock* Bc = P->d_blk + Lc.blk_off;
-        for (int it = 0; it < P->opt.nu1; ++it)
-            for (int colour = 0; colour < (Lf.oddwrap ? 4 : 2); ++colour)
-                hipLaunchKernelGGL(k_rbgs<T>, dim3(Lf.ntiles, nitems), blk, 0, s, Bf,
-                                   P->d_tiles + Lf.tile_off, Lf.ntiles, P->d_dbl, P_(l), F_(l),
-                                   (long long)Lf.plane, P->d_shift, act, nact, colour);
-        hipLaunchKernelGGL(k_restrict<T>, dim3(Lc.ntiles, nitems), blk, 0, s, Bf, Bc,
-                           P->d_tiles + Lc.tile_off, Lc.ntiles, P->d_dbl, P->d_int, P_(l), F_(l),
-                           F_(l + 1), P_(l + 1), (long long)Lf.plane, (long long)Lc.plane,
-                           P->d_shift, act, nact);
+        if (use_march(l)) {
+            // sweeps alternate A -> B -> A ...; the restricting sweep ends in B
+            T* a = P_(l);
+            T* b = PB_(l);
+            for (int it = 0; it + 1 < nu1; ++it) {
+                march_sweep<T>(P, l, a, b, F_(l), act, nact, nitems, s);
+                std::swap(a, b);
+            }
+            march_pre<T>(P, l, a, b, F_(l), F_(l + 1), P_(l + 1), act, nact, nitems, s);
+        } else {
+            for (int it = 0; it < nu1; ++it) rbgs(l);
+            hipLaunchKernelGGL(k_restrict<T>, dim3(Lc.ntiles, nitems), blk, 0, s, P->d_blk + Lf.blk_off,
+                               P->d_blk + Lc.blk_off, P->d_tiles + Lc.tile_off, Lc.ntiles, P->d_dbl,
+                               P->d_int, P_(l), F_(l), F_(l + 1), P_(l + 1), (long long)Lf.plane,
+                               (long long)Lc.plane, P->d_shift, act, nact);
+        }
     }
     {
         LdsArgs a = lds_args(P, L);
@@ -765,35 +817,59 @@ void launch_vcycle(const mbp_plan* P, T* p0, T* f0, const int* act, const int* n
         hipLaunchKernelGGL(k_lds_vcycle<T>, dim3(nitems), dim3(256), bytes, s, a, P_(L), F_(L),
                            (long long)P->levels[L].plane, P->d_shift, act, nact);
     }
+    int nparts = 0;
     for (int l = L - 1; l >= 0; --l) {
         const Level& Lf = P->levels[l];
         const Level& Lc = P->levels[l + 1];
-        const DBlock* Bf = P->d_blk + Lf.blk_off;
-        const DBlock* Bc = P->d_blk + Lc.blk_off;
-        hipLaunchKernelGGL(k_prolong<T>, dim3(Lf.ntiles, nitems), blk, 0, s, Bf, Bc,
-                           P->d_tiles + Lf.tile_off, Lf.ntiles, P->d_dbl, P->d_int, P_(l + 1),
-                           P_(l), (long long)Lf.plane, (long long)Lc.plane, act, nact);
-        for (int it = 0; it < P->opt.nu2; ++it)
-            for (int colour = 0; colour < (Lf.oddwrap ? 4 : 2); ++colour)
-                hipLaunchKernelGGL(k_rbgs<T>, dim3(Lf.ntiles, nitems), blk, 0, s, Bf,
-                                   P->d_tiles + Lf.tile_off, Lf.ntiles, P->d_dbl, P_(l), F_(l),
-                                   (long long)Lf.plane, P->d_shift, act, nact, colour);
+        if (use_march(l)) {
+            // the current iterate sits in A after nu1 - 1 swaps and one more sweep: B if nu1 odd
+            T* a = P_(l);
+            T* b = PB_(l);
+            T* cur = (nu1 % 2 == 1) ? b : a;
+            T* oth = (cur == a) ? b : a;
+            const bool nrm = norm0 && l == 0 && nu2 == 1;
+            march_post<T>(P, l, cur, oth, F_(l), P_(l + 1), nrm, act, nact, nitems, s);
+            std::swap(cur, oth);
+            for (int it = 1; it < nu2; ++it) {
+                const bool last = it == nu2 - 1;
+                if (norm0 && l == 0 && last) {
+                    // extra sweeps do not carry the norm; the caller evaluates it
+                }
+                march_sweep<T>(P, l, cur, oth, F_(l), act, nact, nitems, s);
+                std::swap(cur, oth);
+            }
+            if (nrm) nparts = P->mtile_cnt[0];
+        } else {
+            hipLaunchKernelGGL(k_prolong<T>, dim3(Lf.ntiles, nitems), blk, 0, s, P->d_blk + Lf.blk_off,
+                               P->d_blk + Lc.blk_off, P->d_tiles + Lf.tile_off, Lf.ntiles, P->d_dbl,
+                               P->d_int, P_(l + 1), P_(l), (long long)Lf.plane, (long long)Lc.plane, act,
+                               nact);
+            for (int it = 0; it < nu2; ++it) rbgs(l);
+        }
     }
+    return nparts;
 }
 
-template void launch_vcycle<double>(const mbp_plan*, double*, double*, const int*, const int*, int,
-                                    hipStream_t);
-template void launch_vcycle<float>(const mbp_plan*, float*, float*, const int*, const int*, int,
-                                   hipStream_t);
+template int launch_vcycle<double>(const mbp_plan*, double*, double*, double*, const int*, const int*,
+                                   int, bool, hipStream_t);
+template int launch_vcycle<float>(const mbp_plan*, float*, float*, float*, const int*, const int*, int,
+                                  bool, hipStream_t);
+
+void launch_finish(const mbp_plan* P, int nparts, double* out, const int* act, const int* nact,
+                   int nitems, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, P->d_part, nparts, act, nact, out,
+                       P->d_pnorm);
+}
 
 void launch_lds_full(const mbp_plan* P, double* p, const double* f, const int* act, const int* nact,
-                     int nitems, int maxc, double rtol2, int* cyc, double* rnorm, double* fnorm,
-                     hipStream_t s) {
+                     int nitems, int maxc, double rtol2, double etol2, int* cyc, double* rnorm,
+                     double* fnorm, hipStream_t s) {
     LdsArgs a = lds_args(P, 0);
     const size_t bytes = size_t(P->lds_bytes64);
     set_lds(reinterpret_cast<const void*>(k_lds_full), bytes);
     hipLaunchKernelGGL(k_lds_full, dim3(nitems), dim3(256), bytes, s, a, p, f,
-                       (long long)P->plane0, P->d_shift, act, nact, maxc, rtol2, cyc, rnorm, fnorm);
+                       (long long)P->plane0, P->d_shift, P->d_sabs, act, nact, maxc, rtol2, etol2, cyc,
+                       rnorm, fnorm);
 }
 
 void launch_residual_norm(const mbp_plan* P, const double* p, const double* f, double* rnorm,
@@ -802,7 +878,8 @@ void launch_residual_norm(const mbp_plan* P, const double* p, const double* f, d
     hipLaunchKernelGGL(k_residual<0>, dim3(L.ntiles, nitems), dim3(kTileX, kRowsPerPass), 0, s,
                        P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, f,
                        (long long)L.plane, P->d_shift, act, nact, P->d_part, nullptr, nullptr);
-    hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, P->d_part, L.ntiles, act, nact, rnorm);
+    hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, P->d_part, L.ntiles, act, nact, rnorm,
+                       P->d_pnorm);
 }
 
 void launch_residual_to32(const mbp_plan* P, const double* p, const double* f, float* r32, float* e32,
@@ -811,7 +888,8 @@ void launch_residual_to32(const mbp_plan* P, const double* p, const double* f, f
     hipLaunchKernelGGL(k_residual<1>, dim3(L.ntiles, nitems), dim3(kTileX, kRowsPerPass), 0, s,
                        P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, f,
                        (long long)L.plane, P->d_shift, act, nact, P->d_part, r32, e32);
-    hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, P->d_part, L.ntiles, act, nact, rnorm);
+    hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, P->d_part, L.ntiles, act, nact, rnorm,
+                       P->d_pnorm);
 }
 
 void launch_add_correction(const mbp_plan* P, double* p, const float* e32, const int* act,
@@ -828,12 +906,13 @@ void launch_plane_norm(const mbp_plan* P, const double* f, double* out, hipStrea
                        P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, f, (long long)L.plane,
                        P->d_part);
     hipLaunchKernelGGL(k_finish, dim3(P->g.nz), dim3(256), 0, s, P->d_part, L.ntiles, nullptr, nullptr,
-                       out);
+                       out, nullptr);
 }
 
-void launch_update_active(const mbp_plan* P, double rtol2, int retire, int cycle, hipStream_t s) {
-    hipLaunchKernelGGL(k_update, dim3(1), dim3(1024), 0, s, P->g.nz, P->d_rnorm, P->d_fnorm, rtol2,
-                       retire, cycle, P->d_act, P->d_nact, P->d_cyc, P->d_scal);
+void launch_update_active(const mbp_plan* P, double rtol2, double etol2, int retire, int cycle,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_update, dim3(1), dim3(1024), 0, s, P->g.nz, P->d_rnorm, P->d_fnorm, P->d_pnorm,
+                       P->d_sabs, rtol2, etol2, retire, cycle, P->d_act, P->d_nact, P->d_cyc, P->d_scal);
 }
 
 void launch_reset_active(const mbp_plan* P, hipStream_t s) {

@@ -18,6 +18,7 @@ void options_default(mbp_options* o) {
     o->nu2 = 1;
     o->max_cycles = 60;
     o->flags = 0;
+    o->etol = 0.0;
 }
 
 // Hyperbolic-tangent face clustering (Sec. 3.1, Table 2 caption).  Two-sided:
@@ -279,6 +280,7 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
         P->lambda[q] = double(lam);
         P->shift[q] = double(lam / ((long double)g.dz * g.dz));
     }
+    P->sabs.resize(nz);
 
     // ---- multigrid levels: full coarsening while every block has >= 4 cells
     //      per direction; odd counts merge their last three cells ----
@@ -554,6 +556,14 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
         std::vector<double> V, mu;
         jacobi_eig(S, nc, V, mu);
         P->coarse_mu = mu;
+        // smallest non-zero eigenvalue magnitude (the null mode of a singular
+        // plane is excluded: the gauge removes it from the error)
+        double mmax = 0.0;
+        for (double v : mu) mmax = std::max(mmax, std::fabs(v));
+        double m0 = mmax;
+        for (double v : mu)
+            if (std::fabs(v) > 1e-9 * mmax) m0 = std::min(m0, std::fabs(v));
+        P->mu0 = m0;
         P->coarse_wl.resize(size_t(nc) * nc);
         P->coarse_wr.resize(size_t(nc) * nc);
         for (int r = 0; r < nc; ++r)
@@ -590,6 +600,8 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
             if (l >= P->lds_level) o += 2 * P->levels[l].plane;
         }
     }
+
+    for (int q = 0; q < nz; ++q) P->sabs[q] = P->mu0 + std::fabs(P->shift[q]);
 
     // ---- level summary for the kernels ----
     {

@@ -9,8 +9,8 @@
 namespace mbp {
 
 void launch_lds_full(const mbp_plan* P, double* p, const double* f, const int* act, const int* nact,
-                     int nitems, int maxc, double rtol2, int* cyc, double* rnorm, double* fnorm,
-                     hipStream_t s);
+                     int nitems, int maxc, double rtol2, double etol2, int* cyc, double* rnorm,
+                     double* fnorm, hipStream_t s);
 void launch_reset_active(const mbp_plan* P, hipStream_t s);
 void launch_area_dot(const mbp_plan* P, const double* plane, double* out_sum, hipStream_t s);
 void launch_fill_int(int* p, int n, int v, hipStream_t s);
@@ -22,13 +22,13 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t blk, ints, dbls, tiles, shift, cwl, cwr, cmu, area0, ftf, fti, fhat, phat, part, fnorm,
-        rnorm, act, nact, cyc, flag, scal;
-    std::vector<size_t> p64, f64, p32, f32;
+    size_t blk, ints, dbls, tiles, shift, cwl, cwr, cmu, area0, ftf, fti, mt, fhat, phat, phatB, part,
+        fnorm, rnorm, pnorm, sabs, act, nact, cyc, flag, scal;
+    std::vector<size_t> p64, f64, p32, f32, p64B, p32B;
     size_t total;
 };
 
-Layout layout(const mbp_plan* P, size_t ftile_bytes) {
+Layout layout(const mbp_plan* P, size_t ftile_bytes, size_t mtile_bytes, int nparts) {
     Layout L{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -49,24 +49,36 @@ Layout layout(const mbp_plan* P, size_t ftile_bytes) {
     L.area0 = take(size_t(P->plane0) * sizeof(double));
     L.ftf = take(ftile_bytes);
     L.fti = take(ftile_bytes);
+    L.mt = take(mtile_bytes);
     L.fhat = take(nz * P->plane0 * sizeof(double));
     L.phat = take(nz * P->plane0 * sizeof(double));
+    const bool mixed = P->opt.precision == MBP_MIXED;
+    // out-of-place sweeps need a second buffer on every level that runs them
+    const int Lg = mixed ? P->lds_level32 : P->lds_level;  // levels below run in LDS
+    auto march = [&](int l) { return l < Lg && l < int(P->march_ok.size()) && P->march_ok[l]; };
+    L.phatB = (!mixed && march(0)) ? take(nz * P->plane0 * sizeof(double)) : 0;
     L.p64.assign(P->nlev, 0);
     L.f64.assign(P->nlev, 0);
+    L.p64B.assign(P->nlev, 0);
     for (int l = 1; l < P->nlev; ++l) {
         L.p64[l] = take(nz * P->levels[l].plane * sizeof(double));
         L.f64[l] = take(nz * P->levels[l].plane * sizeof(double));
+        if (!mixed && march(l)) L.p64B[l] = take(nz * P->levels[l].plane * sizeof(double));
     }
     L.p32.assign(P->nlev, 0);
     L.f32.assign(P->nlev, 0);
-    if (P->opt.precision == MBP_MIXED)
+    L.p32B.assign(P->nlev, 0);
+    if (mixed)
         for (int l = 0; l < P->nlev; ++l) {
             L.p32[l] = take(nz * P->levels[l].plane * sizeof(float));
             L.f32[l] = take(nz * P->levels[l].plane * sizeof(float));
+            if (march(l)) L.p32B[l] = take(nz * P->levels[l].plane * sizeof(float));
         }
-    L.part = take(nz * P->levels[0].ntiles * sizeof(double));
+    L.part = take(2 * nz * size_t(std::max(nparts, P->levels[0].ntiles)) * sizeof(double));
     L.fnorm = take(nz * sizeof(double));
     L.rnorm = take(nz * sizeof(double));
+    L.pnorm = take(nz * sizeof(double));
+    L.sabs = take(nz * sizeof(double));
     L.act = take(nz * sizeof(int));
     L.nact = take(sizeof(int) * 4);
     L.cyc = take(nz * sizeof(int));
@@ -78,17 +90,43 @@ Layout layout(const mbp_plan* P, size_t ftile_bytes) {
 
 }  // namespace
 
+constexpr int kMarchSeg = 64;  // rows per fused-sweep strip
+
+// Fused-sweep strips of every level (host tables); fills march_ok.
+void plan_march_tables(mbp_plan* P, std::vector<unsigned char>& bytes) {
+    P->march_ok.assign(P->nlev, 0);
+    P->mtile_off.assign(P->nlev, 0);
+    P->mtile_cnt.assign(P->nlev, 0);
+    bytes.clear();
+    int off = 0;
+    for (int l = 0; l < P->nlev; ++l) {
+        P->march_ok[l] = march_level_ok(P, l) ? 1 : 0;
+        if (!P->march_ok[l]) continue;
+        std::vector<unsigned char> b;
+        int cnt = 0;
+        march_build_tiles_bytes(P, l, kMarchSeg, b, &cnt);
+        P->mtile_off[l] = off;
+        P->mtile_cnt[l] = cnt;
+        off += cnt;
+        bytes.insert(bytes.end(), b.begin(), b.end());
+    }
+}
+
 size_t plan_device_bytes(const mbp_plan* P) {
+    mbp_plan tmp = *P;
+    std::vector<unsigned char> mt;
+    plan_march_tables(&tmp, mt);
     const int W = fft_columns_per_wg(P);
     size_t nt = 0;
     for (int b = 0; b < P->g.nb; ++b) nt += (size_t(P->g.nx[b]) * P->g.ny[b] + W - 1) / W;
-    return layout(P, nt * 32).total;
+    return layout(&tmp, nt * 32, mt.size(), tmp.mtile_cnt.empty() ? 0 : tmp.mtile_cnt[0]).total;
 }
 
 int plan_device_init(mbp_plan* P) {
-    std::vector<unsigned char> ftf, fti;
+    std::vector<unsigned char> ftf, fti, mt;
     fft_build_tiles(P, ftf, fti, &P->fft_ntiles);
-    Layout L = layout(P, ftf.size());
+    plan_march_tables(P, mt);
+    Layout L = layout(P, ftf.size(), mt.size(), P->mtile_cnt[0]);
     void* mem = nullptr;
     if (hipMalloc(&mem, L.total) != hipSuccess) {
         (void)hipGetLastError();
@@ -108,25 +146,34 @@ int plan_device_init(mbp_plan* P) {
     P->d_area0 = reinterpret_cast<double*>(b + L.area0);
     P->d_ftiles_fwd = b + L.ftf;
     P->d_ftiles_inv = b + L.fti;
+    P->d_mtiles = b + L.mt;
+    P->mtile_bytes = mt.size();
     P->fhat = reinterpret_cast<double*>(b + L.fhat);
     P->phat = reinterpret_cast<double*>(b + L.phat);
+    P->phatB = L.phatB ? reinterpret_cast<double*>(b + L.phatB) : nullptr;
     P->p64.assign(P->nlev, nullptr);
     P->f64.assign(P->nlev, nullptr);
+    P->p64B.assign(P->nlev, nullptr);
     P->p32.assign(P->nlev, nullptr);
     P->f32.assign(P->nlev, nullptr);
+    P->p32B.assign(P->nlev, nullptr);
     for (int l = 1; l < P->nlev; ++l) {
         P->p64[l] = reinterpret_cast<double*>(b + L.p64[l]);
         P->f64[l] = reinterpret_cast<double*>(b + L.f64[l]);
+        if (L.p64B[l]) P->p64B[l] = reinterpret_cast<double*>(b + L.p64B[l]);
     }
     if (P->opt.precision == MBP_MIXED)
         for (int l = 0; l < P->nlev; ++l) {
             P->p32[l] = reinterpret_cast<float*>(b + L.p32[l]);
             P->f32[l] = reinterpret_cast<float*>(b + L.f32[l]);
+            if (L.p32B[l]) P->p32B[l] = reinterpret_cast<float*>(b + L.p32B[l]);
         }
     P->d_part = reinterpret_cast<double*>(b + L.part);
     P->nparts = P->levels[0].ntiles;
     P->d_fnorm = reinterpret_cast<double*>(b + L.fnorm);
     P->d_rnorm = reinterpret_cast<double*>(b + L.rnorm);
+    P->d_pnorm = reinterpret_cast<double*>(b + L.pnorm);
+    P->d_sabs = reinterpret_cast<double*>(b + L.sabs);
     P->d_act = reinterpret_cast<int*>(b + L.act);
     P->d_nact = reinterpret_cast<int*>(b + L.nact);
     P->d_cyc = reinterpret_cast<int*>(b + L.cyc);
@@ -141,11 +188,13 @@ int plan_device_init(mbp_plan* P) {
               up(P->d_dbl, P->hdbl.data(), P->hdbl.size() * sizeof(double)) &&
               up(P->d_tiles, P->htiles.data(), P->htiles.size() * sizeof(int4)) &&
               up(P->d_shift, P->shift.data(), P->shift.size() * sizeof(double)) &&
+              up(P->d_sabs, P->sabs.data(), P->sabs.size() * sizeof(double)) &&
               up(P->d_cwl, P->coarse_wl.data(), P->coarse_wl.size() * sizeof(double)) &&
               up(P->d_cwr, P->coarse_wr.data(), P->coarse_wr.size() * sizeof(double)) &&
               up(P->d_cmu, P->coarse_mu.data(), P->coarse_mu.size() * sizeof(double)) &&
               up(P->d_area0, P->areas0.data(), P->areas0.size() * sizeof(double)) &&
-              up(P->d_ftiles_fwd, ftf.data(), ftf.size()) && up(P->d_ftiles_inv, fti.data(), fti.size());
+              up(P->d_ftiles_fwd, ftf.data(), ftf.size()) && up(P->d_ftiles_inv, fti.data(), fti.size()) &&
+              up(P->d_mtiles, mt.data(), mt.size());
     if (!ok) return MBP_ERR_HIP;
     void* hp = nullptr;
     if (hipHostMalloc(&hp, 4096, hipHostMallocDefault) != hipSuccess) return MBP_ERR_NOMEM;
@@ -181,6 +230,8 @@ int solve_one(mbp_plan* P, const double* rhs, double* p, double rtol, int flags,
     const bool retire = (flags & MBP_RETIRE) != 0;
     const int maxc = P->opt.max_cycles;
     const double rtol2 = rtol * rtol;
+    const double etol = P->opt.etol == 0.0 ? 10.0 * rtol : P->opt.etol;
+    const double etol2 = etol < 0.0 ? -1.0 : etol * etol;
     hipEvent_t ev[4];
     for (auto& e : ev) (void)hipEventCreate(&e);
     (void)hipEventRecord(ev[0], s);
@@ -221,7 +272,7 @@ int solve_one(mbp_plan* P, const double* rhs, double* p, double rtol, int flags,
     std::vector<int> cyc(nz, 0);
     if (status == MBP_OK) {
         if (!mixed && P->lds_level == 0) {
-            launch_lds_full(P, P->phat, P->fhat, P->d_act, P->d_nact, nz, maxc, rtol2, P->d_cyc,
+            launch_lds_full(P, P->phat, P->fhat, P->d_act, P->d_nact, nz, maxc, rtol2, etol2, P->d_cyc,
                             P->d_rnorm, P->d_fnorm, s);
             std::vector<double> rn(nz), fn(nz);
             (void)hipMemcpyAsync(cyc.data(), P->d_cyc, nz * sizeof(int), hipMemcpyDeviceToHost, s);
@@ -236,21 +287,24 @@ int solve_one(mbp_plan* P, const double* rhs, double* p, double rtol, int flags,
             if (maxratio > rtol2) status = MBP_ERR_NOT_CONVERGED;
         } else {
             int nitems = nz;
+            int fused_parts = 0;  // > 0: the last V-cycle already produced the residual partials
             for (int c = 0;; ++c) {
                 if (mixed)
                     launch_residual_to32(P, P->phat, P->fhat, P->f32[0], P->p32[0], P->d_rnorm,
                                          P->d_act, P->d_nact, nitems, s);
+                else if (fused_parts > 0)
+                    launch_finish(P, fused_parts, P->d_rnorm, P->d_act, P->d_nact, nitems, s);
                 else
                     launch_residual_norm(P, P->phat, P->fhat, P->d_rnorm, P->d_act, P->d_nact, nitems, s);
-                launch_update_active(P, rtol2, retire ? 1 : 0, c, s);
-                (void)hipMemcpyAsync(hs, P->d_scal, sizeof(double), hipMemcpyDeviceToHost, s);
+                launch_update_active(P, rtol2, etol2, retire ? 1 : 0, c, s);
+                (void)hipMemcpyAsync(hs, P->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
                 (void)hipMemcpyAsync(hi + 1, P->d_nact, sizeof(int), hipMemcpyDeviceToHost, s);
                 if (hipStreamSynchronize(s) != hipSuccess) return MBP_ERR_HIP;
                 cycles = c;
                 if (retire) {
                     nitems = hi[1];
                     if (nitems == 0) break;
-                } else if (hs[0] <= rtol2) {
+                } else if (hs[1] == 0.0) {  // every mode passed
                     maxratio = hs[0];
                     break;
                 }
@@ -260,10 +314,12 @@ int solve_one(mbp_plan* P, const double* rhs, double* p, double rtol, int flags,
                     break;
                 }
                 if (mixed) {
-                    launch_vcycle<float>(P, P->p32[0], P->f32[0], P->d_act, P->d_nact, nitems, s);
+                    launch_vcycle<float>(P, P->p32[0], P->p32B[0], P->f32[0], P->d_act, P->d_nact, nitems,
+                                         false, s);
                     launch_add_correction(P, P->phat, P->p32[0], P->d_act, P->d_nact, nitems, s);
                 } else {
-                    launch_vcycle<double>(P, P->phat, P->fhat, P->d_act, P->d_nact, nitems, s);
+                    fused_parts = launch_vcycle<double>(P, P->phat, P->phatB, P->fhat, P->d_act, P->d_nact,
+                                                        nitems, true, s);
                 }
             }
             (void)hipMemcpyAsync(cyc.data(), P->d_cyc, nz * sizeof(int), hipMemcpyDeviceToHost, s);

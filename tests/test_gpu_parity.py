@@ -162,3 +162,74 @@ def test_status_codes(torch_cuda, mbp):
     with pytest.raises(ValueError):
         plan.solve(dev(torch, f[:-1]), p)
     plan.close()
+
+
+def four_block(n=64, nz=4):
+    """2 x 2 blocks meeting at one point (joined on all inner faces)."""
+    C_, N_, D_ = W.CONNECT, W.NEUMANN, W.DIRICHLET
+    xl, xr = W.faces(n, 0.0, 1.0, 0, 1.2), W.faces(n, 1.0, 2.0)
+    yb, yt = W.faces(n, 0.0, 1.0), W.faces(n, 1.0, 2.0, 0, 1.4)
+    blocks = [
+        W.Block((1, 1), (n, n), xl, yb, (D_, C_, N_, C_)),
+        W.Block((n + 1, 1), (2 * n, n), xr, yb.copy(), (C_, N_, D_, C_)),
+        W.Block((1, n + 1), (n, 2 * n), xl.copy(), yt, (N_, C_, C_, N_)),
+        W.Block((n + 1, n + 1), (2 * n, 2 * n), xr.copy(), yt.copy(), (C_, D_, C_, N_)),
+    ]
+    return W.Problem(blocks, nz, 0.5, W.PAIRS["DN"], name=f"four_block_{n}")
+
+
+def _global_problems():
+    return [
+        W.lshape(96, 6, 1.5, 1.0),
+        four_block(64, 4),
+        W.box(256, 192, 4, 1.0, 0.75, 0.1, "DD", "NN", "PP", xfactor=1.3, yfactor=1.8, name="box256x192"),
+        W.box(250, 130, 4, 250 / 128, 130 / 128, 4 / 128, "PP", "ND", "NN", name="box250x130_oddwrap"),
+        W.box(200, 300, 6, 200 / 128, 300 / 128, 6 / 128, "DN", "PP", "DD", xfactor=2.0, name="box200x300"),
+    ]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("prob", _global_problems(), ids=lambda p: p.name)
+def test_solve_parity_global_levels(torch_cuda, mbp, prob, precision):
+    torch = torch_cuda
+    print(f"solve {prob.name} {precision}", flush=True)
+    f = W.rhs(prob, 31)
+    ref = oracle.solve(prob, f)
+    fproj = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
+    plan = mbp.Plan(prob, precision=precision)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.PROJECT_RHS)
+    got = host(p)
+    res = oracle.rel_residual(prob, got, fproj)
+    err = oracle.rel_error(got, ref)
+    print(f"  {info} residual={res:.2e} error={err:.2e}", flush=True)
+    assert info.status == 0 and res <= 1e-10 and err <= 1e-9
+    plan.close()
+
+
+@pytest.mark.parametrize("nu", [(1, 1), (2, 2), (2, 1), (1, 3)])
+def test_smoothing_counts(torch_cuda, mbp, nu):
+    torch = torch_cuda
+    prob = W.lshape(96, 4, 1.5, 1.0)
+    f = W.rhs(prob, 41, "normal")
+    ref = oracle.solve(prob, f)
+    plan = mbp.Plan(prob, nu1=nu[0], nu2=nu[1])
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.PROJECT_RHS)
+    assert info.status == 0
+    assert oracle.rel_error(host(p), ref) <= 1e-9
+    plan.close()
+
+
+def test_deterministic(torch_cuda, mbp):
+    """Two solves of the same input are bitwise equal (no races in the sweeps)."""
+    torch = torch_cuda
+    prob = four_block(64, 4)
+    f = dev(torch, W.rhs(prob, 3))
+    plan = mbp.Plan(prob)
+    p1 = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    p2 = torch.zeros_like(p1)
+    plan.solve(f, p1, rtol=1e-10)
+    plan.solve(f, p2, rtol=1e-10)
+    assert torch.equal(p1, p2)
+    plan.close()
