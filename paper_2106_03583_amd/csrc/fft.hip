@@ -193,19 +193,19 @@ __global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict_
         const int half = m / 2;
         for (int idx = threadIdx.x; idx < (half + 1) * W; idx += blockDim.x) {
             int k = idx / W, w = idx - k * W;
-            auto Y = [&](int q) -> double {  // y'_q = y_q / c_q, y'_n = 0
+            auto Y = [&](int q) __attribute__((always_inline)) -> double {  // y'_q = y_q / c_q, y'_n = 0
                 if (q >= n || w >= T.ncol) return 0.0;
                 int row = kind == Z_DD ? n - 1 - q : q;
                 double y = in[T.in_base + (long long)row * T.in_stride + w];
                 return y / (q == 0 ? sc1 : sc2);
             };
-            auto V = [&](int q) -> double2 {
+            auto V = [&](int q) __attribute__((always_inline)) -> double2 {
                 double2 c = cconj(ld2(a.post, q));
                 double2 t = make_double2(Y(q), -Y(n - q));
                 return cmul(c, t);
             };
             double2 Vk = V(k), Vmk = V(m - k);
-            auto Zk = [&](double2 A, double2 B, int kk) -> double2 {
+            auto Zk = [&](double2 A, double2 B, int kk) __attribute__((always_inline)) -> double2 {
                 double2 Bc = cconj(B);
                 double2 s = make_double2(A.x + Bc.x, A.y + Bc.y);
                 double2 d = make_double2(A.x - Bc.x, A.y - Bc.y);

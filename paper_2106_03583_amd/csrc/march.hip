@@ -14,13 +14,22 @@
 //   RES  residual of the smoothed rows, area-weighted, summed into the coarse
 //        rhs of the next level (pre-smoothing sweep + restriction);
 //   NRM  per-strip sum of the squared residual (convergence test).
+#include <type_traits>
+
 #include "internal.h"
 
 namespace mbp {
 
+// One strip of the fused sweep, with the geometry of every block its halo
+// meets, so a workgroup needs a single descriptor load before its bulk loads.
+// Region indices: row region 0 below / 1 inside / 2 above the block, column
+// region 0 left halo / 1 the block / 2 right halo.
 struct MTile {
-    int b, x0, w, y0, y1, pad0, pad1, pad2;
+    int b, x0, w, y0, y1, bnx, bny, pad;
+    int blk[3][3], off[3][3], nx[3][3], ny[3][3], cx[3][3], cy[3][3], par[3][3];
 };
+
+__device__ __forceinline__ int pick3(int i, int a, int b, int c) { return i == 0 ? a : (i == 1 ? b : c); }
 
 template <typename T>
 struct MArgs {
@@ -95,192 +104,310 @@ __device__ __forceinline__ T coarse_at(const T* __restrict__ pl, const DBlock* _
 }
 
 template <typename T>
-__device__ __forceinline__ T correction(const MArgs<T>& a, const T* __restrict__ ecq, int fb, int ci, int cj) {
-    const DBlock& d = a.B[fb];
-    const int cx = a.ip[d.pcx + ci], cy = a.ip[d.pcy + cj];
-    const T wx = T(a.dp[d.pwx + ci]), wy = T(a.dp[d.pwy + cj]);
-    const T e00 = coarse_at(ecq, a.Bc, fb, cx, cy), e10 = coarse_at(ecq, a.Bc, fb, cx + 1, cy);
-    const T e01 = coarse_at(ecq, a.Bc, fb, cx, cy + 1), e11 = coarse_at(ecq, a.Bc, fb, cx + 1, cy + 1);
+__device__ __forceinline__ T correction(const DBlock* __restrict__ B, const DBlock* __restrict__ Bc,
+                                       const int* __restrict__ ip, const double* __restrict__ dp,
+                                       const T* __restrict__ ecq, int fb, int ci, int cj) {
+    const DBlock& d = B[fb];
+    const int cx = ip[d.pcx + ci], cy = ip[d.pcy + cj];
+    const T wx = T(dp[d.pwx + ci]), wy = T(dp[d.pwy + cj]);
+    const T e00 = coarse_at(ecq, Bc, fb, cx, cy), e10 = coarse_at(ecq, Bc, fb, cx + 1, cy);
+    const T e01 = coarse_at(ecq, Bc, fb, cx, cy + 1), e11 = coarse_at(ecq, Bc, fb, cx + 1, cy + 1);
     return wy * (wx * e00 + (T(1) - wx) * e10) + (T(1) - wy) * (wx * e01 + (T(1) - wx) * e11);
 }
 
+// Compile-time loop: the body gets a constant index, so per-thread arrays
+// indexed by it stay in registers.
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// ------------------------- LDS tile form of the sweep -------------------------
+// Same sweep, same strips, but a workgroup loads its whole strip (rows y0-3 ..
+// y1+2, 64 columns) into LDS in one burst, then relaxes red, black, computes
+// the residual and restricts it with barriers between the phases.  Bulk loads
+// keep many requests in flight, which the row march cannot do in float64.
+constexpr int kTileRows = 30;               // output rows per strip (host cuts at this)
+constexpr int kLdsRows = kTileRows + 6;
+
+// Block met at (column region cr, virtual row k) of a strip of block tb:
+// column region 0 = left halo, 1 = the block, 2 = right halo.  Beyond a
+// corner: the y neighbour's x neighbour, else the x neighbour's y neighbour
+// (the host rejects levels where both exist and differ).
+__device__ __forceinline__ int block_at(const DBlock* __restrict__ B, int tb, int cr, int k, int bny) {
+    const int colb = cr == 1 ? tb : B[tb].nbr[cr == 0 ? XM : XP];
+    if (k >= 0 && k < bny) return colb;
+    const int fy = k < 0 ? YM : YP;
+    const int M = B[tb].nbr[fy];
+    if (cr == 1) return M;
+    const int fx = cr == 0 ? XM : XP;
+    if (M >= 0 && B[M].nbr[fx] >= 0) return B[M].nbr[fx];
+    if (colb >= 0 && B[colb].nbr[fy] >= 0) return B[colb].nbr[fy];
+    return -1;
+}
+
+template <typename T>
+__device__ __forceinline__ T xcoef(const DBlock* __restrict__ B, const double* __restrict__ dp, int blk,
+                                   int cc, int which) {
+    return blk >= 0 ? T(dp[B[blk].cx + which * B[blk].nx + cc]) : T(0);
+}
+
 template <typename T, bool PRO, bool RES, bool NRM>
-__global__ void __launch_bounds__(256) k_march(MArgs<T> a) {
+__global__ void __launch_bounds__(256) k_tile(const MArgs<T> args) {
+    // argument fields as scalars (no reference to the argument block survives)
+    const DBlock* __restrict__ aB = args.B;
+    const DBlock* __restrict__ aBc = args.Bc;
+    const int* __restrict__ aip = args.ip;
+    const double* __restrict__ dp = args.dp;
+    const int ntiles = args.ntiles;
+    const long long plane = args.plane, plane_c = args.plane_c;
+
+    __shared__ T sp[kLdsRows][64];
+    __shared__ T sf[kLdsRows][64];
+    __shared__ double sy[kLdsRows][3][3];  // per row and column region: wm, wp, dy
+    __shared__ int scol[kLdsRows][3];      // (row index + parity) & 1, or -1: no cell
+    __shared__ double sred[4][2];
+
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nwg = (a.ntiles + 3) >> 2;
-    const int tix = xcd_remap_m(blockIdx.x, nwg) * 4 + wave;
-    if (tix >= a.ntiles) return;
+    const int tix = xcd_remap_m(blockIdx.x, ntiles);
     const int item = blockIdx.y;
-    if (item >= *a.nact) return;
-    const int q = a.act[item];
-    const MTile t = a.tiles[tix];
-    const DBlock& b = a.B[t.b];
-    const int bny = b.ny;
-    const T sig = T(a.shift[q]);
-    const T* __restrict__ po = a.pold + q * a.plane;
-    T* __restrict__ pn = a.pnew + q * a.plane;
-    const T* __restrict__ fq = a.f + q * a.plane;
-    const T* __restrict__ ecq = PRO ? a.ec + q * a.plane_c : nullptr;
+    if (item >= *args.nact) return;
+    const int q = args.act[item];
+    const MTile& t = args.tiles[tix];
+    const int tb = t.b, tx0 = t.x0, tw = t.w, ty0 = t.y0, ty1 = t.y1;
+    const int bnx = t.bnx, bny = t.bny;
+    const int nrow = ty1 - ty0 + 6;
+    const T sig = T(args.shift[q]);
+    const T* __restrict__ po = args.pold + q * plane;
+    T* __restrict__ pn = args.pnew + q * plane;
+    const T* __restrict__ fq = args.f + q * plane;
+    const T* __restrict__ ecq = PRO ? args.ec + q * plane_c : nullptr;
 
-    // ---- the lane's cells: block and column index per row region ----
-    // Rows inside the strip's block use the block's x neighbours for the halo
-    // columns.  Rows below / above it belong to the y neighbour M; there a halo
-    // column is M's own x neighbour when that exists, else the y neighbour of
-    // the side block (the two agree wherever both exist; the host checks).
-    const int c = t.x0 - 3 + lane;
-    const bool live = lane < t.w + 6;  // beyond the right halo: unused
-    const bool inb = c >= 0 && c < b.nx;
-    int cid = -1, ci = 0;
-    if (live) {
-        if (c < 0) { cid = b.nbr[XM]; ci = cid >= 0 ? a.B[cid].nx + c : 0; }
-        else if (c >= b.nx) { cid = b.nbr[XP]; ci = c - b.nx; }
-        else { cid = t.b; ci = c; }
-    }
-    auto halo_col = [&](int fy, int& hc) -> int {
-        hc = 0;
-        if (!live) return -1;
-        const int M = b.nbr[fy];
-        if (inb) { hc = c; return M; }
-        const int fx = c < 0 ? XM : XP;
-        if (M >= 0 && a.B[M].nbr[fx] >= 0) {
-            const int X = a.B[M].nbr[fx];
-            hc = c < 0 ? a.B[X].nx + c : c - b.nx;
-            return X;
+    // ---- phase 0: per-row coefficient table ----
+    for (int e = threadIdx.x; e < 3 * nrow; e += blockDim.x) {
+        const int r = e / 3, cr = e - 3 * r;
+        const int k = ty0 - 3 + r;
+        const int rr = k < 0 ? 0 : (k >= bny ? 2 : 1);
+        const int blk = pick3(rr, pick3(cr, t.blk[0][0], t.blk[0][1], t.blk[0][2]),
+                              pick3(cr, t.blk[1][0], t.blk[1][1], t.blk[1][2]),
+                              pick3(cr, t.blk[2][0], t.blk[2][1], t.blk[2][2]));
+        if (blk < 0) {
+            scol[r][cr] = -1;
+            sy[r][cr][0] = sy[r][cr][1] = 0.0;
+            sy[r][cr][2] = 1.0;
+            continue;
         }
-        if (cid >= 0 && a.B[cid].nbr[fy] >= 0) { hc = ci; return a.B[cid].nbr[fy]; }
-        return -1;
-    };
-    int cim, cip;
-    const int kmb = halo_col(YM, cim), kpb = halo_col(YP, cip);
-    const ColBlk K0 = colblk(a.B, cid);  // rows inside [0, ny)
-    const ColBlk Km = colblk(a.B, kmb);  // rows below
-    const ColBlk Kp = colblk(a.B, kpb);  // rows above
-    const bool out_lane = lane >= 3 && lane < 3 + t.w;
-
-    // region of virtual row k for this lane: block geometry, row and column
-    auto region = [&](int k, ColBlk& R, int& cj, int& cc) -> bool {
-        if (k < 0) { R = Km; cj = Km.ny + k; cc = cim; }
-        else if (k >= bny) { R = Kp; cj = k - bny; cc = cip; }
-        else { R = K0; cj = k; cc = ci; }
-        return R.id >= 0;
-    };
-
-    // restriction bookkeeping (block b's tables; output lanes lie in block b)
-    int Ipar = 0, Inext1 = -1, Inext2 = -1, ncx = 0, ncy = 0;
-    T wrx = T(0);
-    bool leader = false;
-    if (RES) {
-        const DBlock& bc = a.Bc[t.b];
-        ncx = bc.nx;
-        ncy = bc.ny;
-        auto parent = [&](int col) { return min(col >> 1, ncx - 1); };
-        if (c >= 0 && c < b.nx) {
-            Ipar = parent(c);
-            wrx = T(a.dp[b.rwx + c]);
-            leader = out_lane && (c == 2 * Ipar);
-        }
-        Inext1 = (c + 1 < b.nx && c + 1 >= 0) ? parent(c + 1) : -1;
-        Inext2 = (c + 2 < b.nx && c + 2 >= 0) ? parent(c + 2) : -1;
+        const int ny = pick3(rr, pick3(cr, t.ny[0][0], t.ny[0][1], t.ny[0][2]),
+                             pick3(cr, t.ny[1][0], t.ny[1][1], t.ny[1][2]),
+                             pick3(cr, t.ny[2][0], t.ny[2][1], t.ny[2][2]));
+        const int cy = pick3(rr, pick3(cr, t.cy[0][0], t.cy[0][1], t.cy[0][2]),
+                             pick3(cr, t.cy[1][0], t.cy[1][1], t.cy[1][2]),
+                             pick3(cr, t.cy[2][0], t.cy[2][1], t.cy[2][2]));
+        const int par = pick3(rr, pick3(cr, t.par[0][0], t.par[0][1], t.par[0][2]),
+                              pick3(cr, t.par[1][0], t.par[1][1], t.par[1][2]),
+                              pick3(cr, t.par[2][0], t.par[2][1], t.par[2][2]));
+        const int cj = k < 0 ? ny + k : (k >= bny ? k - bny : k);
+        sy[r][cr][0] = dp[cy + cj];
+        sy[r][cr][1] = dp[cy + ny + cj];
+        sy[r][cr][2] = dp[cy + 2 * ny + cj];
+        scol[r][cr] = (cj + par) & 1;
     }
 
-    // ---- register window ----
-    T p0 = T(0), p1 = T(0), p2 = T(0), p3 = T(0), p4 = T(0);  // rows k-4 .. k
-    T f1 = T(0), f2 = T(0), f3 = T(0), f4 = T(0);             // rows k-3 .. k
-    T accy = T(0);
+    // ---- the lane's column: region, per-row-region block and column index ----
+    const int c = tx0 - 3 + lane;
+    const bool live = lane < tw + 6;
+    const int cr = c < 0 ? 0 : (c < bnx ? 1 : 2);
+    const int b0 = live ? pick3(cr, t.blk[1][0], t.blk[1][1], t.blk[1][2]) : -1;
+    const int bm = live ? pick3(cr, t.blk[0][0], t.blk[0][1], t.blk[0][2]) : -1;
+    const int bp = live ? pick3(cr, t.blk[2][0], t.blk[2][1], t.blk[2][2]) : -1;
+    const int nx0 = pick3(cr, t.nx[1][0], t.nx[1][1], t.nx[1][2]);
+    const int nxm = pick3(cr, t.nx[0][0], t.nx[0][1], t.nx[0][2]);
+    const int nxp = pick3(cr, t.nx[2][0], t.nx[2][1], t.nx[2][2]);
+    const int nym = pick3(cr, t.ny[0][0], t.ny[0][1], t.ny[0][2]);
+    // column index inside the region's block
+    const int ci = cr == 0 ? nx0 + c : (cr == 2 ? c - bnx : c);
+    const int cim = cr == 0 ? nxm + c : (cr == 2 ? c - bnx : c);
+    const int cip = cr == 0 ? nxp + c : (cr == 2 ? c - bnx : c);
+    const int off0 = b0 >= 0 ? pick3(cr, t.off[1][0], t.off[1][1], t.off[1][2]) + ci : 0;
+    const int offm = bm >= 0 ? pick3(cr, t.off[0][0], t.off[0][1], t.off[0][2]) + cim : 0;
+    const int offp = bp >= 0 ? pick3(cr, t.off[2][0], t.off[2][1], t.off[2][2]) + cip : 0;
+    const int cx0 = pick3(cr, t.cx[1][0], t.cx[1][1], t.cx[1][2]);
+    const int cxm = pick3(cr, t.cx[0][0], t.cx[0][1], t.cx[0][2]);
+    const int cxp = pick3(cr, t.cx[2][0], t.cx[2][1], t.cx[2][2]);
+    // x coefficients per row region (lane constants)
+    const T xwm0 = b0 >= 0 ? T(dp[cx0 + ci]) : T(0), xwp0 = b0 >= 0 ? T(dp[cx0 + nx0 + ci]) : T(0);
+    const T xd0 = b0 >= 0 ? T(dp[cx0 + 2 * nx0 + ci]) : T(0);
+    const T xwmm = bm >= 0 ? T(dp[cxm + cim]) : T(0), xwpm = bm >= 0 ? T(dp[cxm + nxm + cim]) : T(0);
+    const T xdm = bm >= 0 ? T(dp[cxm + 2 * nxm + cim]) : T(0);
+    const T xwmp = bp >= 0 ? T(dp[cxp + cip]) : T(0), xwpp = bp >= 0 ? T(dp[cxp + nxp + cip]) : T(0);
+    const T xdp = bp >= 0 ? T(dp[cxp + 2 * nxp + cip]) : T(0);
+
+    // coarse columns of the correction for inside rows (resolved per lane)
+    int cbaseA = 0, cbaseB = 0, cstrA = 0, cstrB = 0, ncyc = 0, bpcy = 0, bpwy = 0;
+    T csA = T(0), csB = T(0), cwx = T(0);
+    if (PRO) {
+        ncyc = aBc[tb].ny;
+        bpcy = aB[tb].pcy;
+        bpwy = aB[tb].pwy;
+        if (b0 >= 0) {
+            const int cx = aip[aB[b0].pcx + ci];
+            cwx = T(dp[aB[b0].pwx + ci]);
+            int I = cx;
+            for (int s = 0; s < 2; ++s, ++I) {
+                int cb = b0, II = I;
+                T sg = T(1);
+                if (II < 0) {
+                    if (aBc[cb].nbr[XM] >= 0) { cb = aBc[cb].nbr[XM]; II = aBc[cb].nx - 1; }
+                    else { if (aBc[cb].bc[XM] == MBP_DIRICHLET) sg = T(-1); II = 0; }
+                } else if (II >= aBc[cb].nx) {
+                    if (aBc[cb].nbr[XP] >= 0) { cb = aBc[cb].nbr[XP]; II = 0; }
+                    else { if (aBc[cb].bc[XP] == MBP_DIRICHLET) sg = T(-1); II = aBc[cb].nx - 1; }
+                }
+                if (s == 0) { cbaseA = aBc[cb].off + II; cstrA = aBc[cb].nx; csA = sg; }
+                else { cbaseB = aBc[cb].off + II; cstrB = aBc[cb].nx; csB = sg; }
+            }
+        }
+    }
+
+    // ---- phase 1: load p and f of every held row.  All loads of the strip
+    //      are issued first (constant trip count, values in registers), then
+    //      written to LDS, so they overlap in flight. ----
+    constexpr int NR = (kLdsRows + 3) / 4;
+    T lp[NR], lf[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) {
+        const int r = wave + 4 * rr;
+        const int k = ty0 - 3 + r;
+        lp[rr] = T(0);
+        lf[rr] = T(0);
+        if (r >= nrow) continue;
+        const bool below = k < 0, above = k >= bny;
+        const bool alive = below ? bm >= 0 : (above ? bp >= 0 : b0 >= 0);
+        if (!alive) continue;
+        const int o = below ? offm + (nym + k) * nxm : (above ? offp + (k - bny) * nxp : off0 + k * nx0);
+        lp[rr] = po[o];
+        lf[rr] = fq[o];
+    }
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) {
+        const int r = wave + 4 * rr;
+        if (r >= nrow) continue;
+        sp[r][lane] = lp[rr];
+        sf[r][lane] = lf[rr];
+    }
+    // coarse-grid correction of the held rows (bilinear, physical weights)
+    if (PRO) {
+#pragma unroll 3
+        for (int rr = 0; rr < NR; ++rr) {
+            const int r = wave + 4 * rr;
+            if (r >= nrow) continue;
+            const int k = ty0 - 3 + r;
+            const bool below = k < 0, above = k >= bny;
+            const bool alive = below ? bm >= 0 : (above ? bp >= 0 : b0 >= 0);
+            if (!alive) continue;
+            T corr;
+            const int cy = (!below && !above) ? aip[bpcy + k] : -1;
+            if (!below && !above && cy >= 0 && cy + 1 < ncyc) {
+                const T wy = T(dp[bpwy + k]);
+                corr = wy * (cwx * csA * ecq[cbaseA + cy * cstrA] + (T(1) - cwx) * csB * ecq[cbaseB + cy * cstrB]) +
+                       (T(1) - wy) * (cwx * csA * ecq[cbaseA + (cy + 1) * cstrA] +
+                                      (T(1) - cwx) * csB * ecq[cbaseB + (cy + 1) * cstrB]);
+            } else if (below) {
+                corr = correction(aB, aBc, aip, dp, ecq, bm, cim, nym + k);
+            } else if (above) {
+                corr = correction(aB, aBc, aip, dp, ecq, bp, cip, k - bny);
+            } else {
+                corr = correction(aB, aBc, aip, dp, ecq, b0, ci, k);
+            }
+            sp[r][lane] += corr;
+        }
+    }
+    __syncthreads();
+
+    // ---- phases 2 and 3: red on rows 1 .. nrow-2 / lanes 1 .. 62, then black
+    //      on rows 2 .. nrow-3 / lanes 2 .. 61 (the valid region shrinks) ----
+    for (int colour = 0; colour < 2; ++colour) {
+        if (lane >= 1 + colour && lane <= 62 - colour) {
+            for (int r = wave; r < nrow; r += 4) {
+                if (r < 1 + colour || r > nrow - 2 - colour) continue;
+                const int k = ty0 - 3 + r;
+                const int sc = scol[r][cr];
+                const bool below = k < 0, above = k >= bny;
+                const bool alive = below ? bm >= 0 : (above ? bp >= 0 : b0 >= 0);
+                if (sc < 0 || !alive) continue;
+                const int cc = below ? cim : (above ? cip : ci);
+                if (((cc + sc) & 1) != colour) continue;
+                const T wm = below ? xwmm : (above ? xwmp : xwm0);
+                const T wp = below ? xwpm : (above ? xwpp : xwp0);
+                const T xd = below ? xdm : (above ? xdp : xd0);
+                const T d = xd + T(sy[r][cr][2]) + sig;
+                const T off = wm * sp[r][lane - 1] + wp * sp[r][lane + 1] + T(sy[r][cr][0]) * sp[r - 1][lane] +
+                              T(sy[r][cr][1]) * sp[r + 1][lane];
+                sp[r][lane] = (sf[r][lane] - off) / d;
+            }
+        }
+        __syncthreads();
+    }
+    // ---- phase 4: store, residual (weighted residual kept in sf for the restriction) ----
+    const bool out_lane = lane >= 3 && lane < 3 + tw;
+    const T wrx = (RES && out_lane) ? T(dp[aB[tb].rwx + c]) : T(0);
+    const int rwy = aB[tb].rwy;
     double nrm = 0.0, pnr = 0.0;
-    int curJ = -1;
-
-    // relax one cell of the given colour (row values: dn = row below, up = row above)
-    auto relax = [&](T& cen, T dn, T up, T fv, int k, int colour) {
-        const T xm = shfl_up1(cen), xp = shfl_dn1(cen);
-        ColBlk R;
-        int cj, cc;
-        if (!region(k, R, cj, cc)) return;
-        if (((cc + cj + R.par) & 1) != colour) return;
-        const double* dp = a.dp;
-        const T d = T(dp[R.cx + 2 * R.nx + cc]) + T(dp[R.cy + 2 * R.ny + cj]) + sig;
-        const T off = T(dp[R.cx + cc]) * xm + T(dp[R.cx + R.nx + cc]) * xp + T(dp[R.cy + cj]) * dn +
-                      T(dp[R.cy + R.ny + cj]) * up;
-        cen = (fv - off) / d;
-    };
-
-    const int kbeg = t.y0 - 3, kend = t.y1 + 2;
-    for (int k = kbeg; k <= kend; ++k) {
-        // shift the window and load row k
-        p0 = p1; p1 = p2; p2 = p3; p3 = p4;
-        f1 = f2; f2 = f3; f3 = f4;
-        {
-            ColBlk R;
-            int cj, cc;
-            T pv = T(0), fv = T(0);
-            if (region(k, R, cj, cc)) {
-                const long long o = R.off + (long long)cj * R.nx + cc;
-                pv = po[o];
-                fv = fq[o];
-                if (PRO) pv += correction(a, ecq, R.id, cc, cj);
-            }
-            p4 = pv;
-            f4 = fv;
-        }
-        // red cells of row k-1 (old black neighbours), black cells of row k-2
-        if (k - 1 >= t.y0 - 2) relax(p3, p2, p4, f3, k - 1, 0);
-        if (k - 2 >= t.y0 - 1) relax(p2, p1, p3, f2, k - 2, 1);
-        // row k-2 is final: store it
-        if (k - 2 >= t.y0 && k - 2 < t.y1 && out_lane) {
-            const long long o = K0.off + (long long)(k - 2) * K0.nx + ci;
-            pn[o] = p2;
-        }
-        // residual of row k-3 (rows k-4 .. k-2 are final)
-        if (RES || NRM) {
-            const int kr = k - 3;
-            const T xm = shfl_up1(p1), xp = shfl_dn1(p1);
-            T r = T(0);
-            if (kr >= t.y0 && kr < t.y1 && out_lane) {
-                const double* dp = a.dp;
-                const T d = T(dp[K0.cx + 2 * K0.nx + ci]) + T(dp[K0.cy + 2 * K0.ny + kr]) + sig;
-                r = f1 - (T(dp[K0.cx + ci]) * xm + T(dp[K0.cx + K0.nx + ci]) * xp +
-                          T(dp[K0.cy + kr]) * p0 + T(dp[K0.cy + K0.ny + kr]) * p2 + d * p1);
+    for (int r = wave; r < nrow; r += 4) {
+        const int k = ty0 - 3 + r;
+        const bool own = r >= 3 && k < ty1 && out_lane;
+        if (own) {
+            const T pc = sp[r][lane];
+            pn[off0 + k * nx0] = pc;
+            if (RES || NRM) {
+                const T d = xd0 + T(sy[r][1][2]) + sig;
+                const T res = sf[r][lane] - (xwm0 * sp[r][lane - 1] + xwp0 * sp[r][lane + 1] +
+                                             T(sy[r][1][0]) * sp[r - 1][lane] + T(sy[r][1][1]) * sp[r + 1][lane] + d * pc);
                 if (NRM) {
-                    nrm += double(r) * double(r);
-                    pnr += double(p1) * double(p1);
+                    nrm += double(res) * double(res);
+                    pnr += double(pc) * double(pc);
                 }
+                if (RES) sf[r][lane] = res * wrx * T(dp[rwy + k]);
             }
-            if (RES) {
-                const bool inrow = kr >= t.y0 && kr < t.y1;
-                T rw = (inrow && out_lane) ? r * wrx : T(0);
-                const T v1 = shfl_dn1(rw);
-                const T v2 = __shfl_down(rw, 2);
-                if (inrow) {
-                    const int J = min(kr >> 1, ncy - 1);
-                    T sx = rw;
-                    if (Inext1 == Ipar) sx += v1;
-                    if (Inext2 == Ipar) sx += v2;
-                    accy += T(a.dp[b.rwy + kr]) * sx;
-                    curJ = J;
-                    // flush when the next row belongs to another coarse row (or the strip ends)
-                    const int Jn = (kr + 1 < t.y1) ? min((kr + 1) >> 1, ncy - 1) : -1;
-                    if (Jn != J) {
-                        if (leader) {
-                            const DBlock& bc = a.Bc[t.b];
-                            const long long o = q * a.plane_c + bc.off + (long long)J * bc.nx + Ipar;
-                            a.fc[o] = accy;
-                            a.pc[o] = T(0);
-                        }
-                        accy = T(0);
-                    }
-                }
+        } else if (RES) {
+            sf[r][lane] = T(0);
+        }
+    }
+    if (RES) {
+        __syncthreads();
+        // leaders: first fine column / row of each coarse cell inside the strip
+        const int ncx = aBc[tb].nx, ncy = aBc[tb].ny, bcoff = aBc[tb].off;
+        if (out_lane && c == 2 * min(c >> 1, ncx - 1)) {
+            const int I = min(c >> 1, ncx - 1);
+            const int i1 = (I == ncx - 1) ? bnx : 2 * I + 2;  // exclusive fine end
+            for (int r = wave; r < nrow; r += 4) {
+                const int k = ty0 - 3 + r;
+                if (r < 3 || k >= ty1) continue;
+                const int J = min(k >> 1, ncy - 1);
+                if (k != 2 * J) continue;
+                const int j1 = (J == ncy - 1) ? bny : 2 * J + 2;
+                T s = T(0);
+                for (int kk = k; kk < j1; ++kk)
+                    for (int x = c; x < i1; ++x) s += sf[r + (kk - k)][lane + (x - c)];
+                const long long o = q * plane_c + bcoff + (long long)J * ncx + I;
+                args.fc[o] = s;
+                args.pc[o] = T(0);
             }
         }
     }
-    (void)curJ;
     if (NRM) {
         for (int o = 32; o > 0; o >>= 1) {
             nrm += __shfl_xor(nrm, o);
             pnr += __shfl_xor(pnr, o);
         }
-        if (lane == 0) {
-            a.part[2 * ((long long)q * a.ntiles + tix)] = nrm;
-            a.part[2 * ((long long)q * a.ntiles + tix) + 1] = pnr;
+        if (lane == 0) { sred[wave][0] = nrm; sred[wave][1] = pnr; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            args.part[2 * ((long long)q * ntiles + tix)] = sred[0][0] + sred[1][0] + sred[2][0] + sred[3][0];
+            args.part[2 * ((long long)q * ntiles + tix) + 1] = sred[0][1] + sred[1][1] + sred[2][1] + sred[3][1];
         }
     }
 }
@@ -295,7 +422,7 @@ void march_build_tiles(const mbp_plan* P, int l, int seg, std::vector<MTile>& ou
     const Level& L = P->levels[l];
     const bool has_coarse = l + 1 < P->nlev;
     for (int b = 0; b < L.nb; ++b) {
-        auto cuts = [&](int n, int nc, int maxw) {
+        auto cuts = [&](int n, int nc, int maxw) __attribute__((always_inline)) {
             std::vector<int> edges{0};
             int start = 0;
             for (int I = 0; I < (has_coarse ? nc : n); ++I) {
@@ -313,10 +440,39 @@ void march_build_tiles(const mbp_plan* P, int l, int seg, std::vector<MTile>& ou
         const int ncy = has_coarse ? P->levels[l + 1].ny[b] : 0;
         std::vector<int> ex = cuts(L.nx[b], ncx, 58);
         std::vector<int> ey = cuts(L.ny[b], ncy, seg);
+        // block met at (row region rr, column region cr), same rule as the halo lanes
+        const Geometry& g = P->g;
+        auto at = [&](int rr, int cr) {
+            const int colb = cr == 1 ? b : g.nbr[b][cr == 0 ? XM : XP];
+            if (rr == 1) return colb;
+            const int fy = rr == 0 ? YM : YP;
+            const int M = g.nbr[b][fy];
+            if (cr == 1) return M;
+            const int fx = cr == 0 ? XM : XP;
+            if (M >= 0 && g.nbr[M][fx] >= 0) return g.nbr[M][fx];
+            if (colb >= 0 && g.nbr[colb][fy] >= 0) return g.nbr[colb][fy];
+            return -1;
+        };
+        MTile base{};
+        base.b = b;
+        base.bnx = L.nx[b];
+        base.bny = L.ny[b];
+        for (int rr = 0; rr < 3; ++rr)
+            for (int cr = 0; cr < 3; ++cr) {
+                const int k = at(rr, cr);
+                base.blk[rr][cr] = k;
+                if (k < 0) continue;
+                const DBlock& d = P->hblk[L.blk_off + k];
+                base.off[rr][cr] = d.off;
+                base.nx[rr][cr] = d.nx;
+                base.ny[rr][cr] = d.ny;
+                base.cx[rr][cr] = d.cx;
+                base.cy[rr][cr] = d.cy;
+                base.par[rr][cr] = d.par;
+            }
         for (size_t yi = 0; yi + 1 < ey.size(); ++yi)
             for (size_t xi = 0; xi + 1 < ex.size(); ++xi) {
-                MTile t{};
-                t.b = b;
+                MTile t = base;
                 t.x0 = ex[xi];
                 t.w = ex[xi + 1] - ex[xi];
                 t.y0 = ey[yi];
@@ -383,8 +539,7 @@ static MArgs<T> margs(const mbp_plan* P, int l, const T* pold, T* pnew, const T*
 
 template <typename T, bool PRO, bool RES, bool NRM>
 static void launch_march(const MArgs<T>& a, int nitems, hipStream_t s) {
-    const int nwg = (a.ntiles + 3) / 4;
-    hipLaunchKernelGGL((k_march<T, PRO, RES, NRM>), dim3(nwg, nitems), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_tile<T, PRO, RES, NRM>), dim3(a.ntiles, nitems), dim3(256), 0, s, a);
 }
 
 // Pre-smoothing sweep of level l (old -> new) fused with the residual

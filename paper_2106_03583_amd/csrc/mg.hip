@@ -444,7 +444,7 @@ k_apply3d(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntil
         const long long c = base + k * cols + j * b.nx + i;
         const double v = p[c];
         // x-y neighbours (other blocks addressed through their own base)
-        auto at = [&](const DBlock& bb, int ii, int jj) {
+        auto at = [&](const DBlock& bb, int ii, int jj) __attribute__((always_inline)) {
             return p[(long long)bb.off * nz + k * (long long)bb.nx * bb.ny + jj * bb.nx + ii];
         };
         double xm = 0, xp = 0, ym = 0, yp = 0;
@@ -782,8 +782,8 @@ int launch_vcycle(const mbp_plan* P, T* p0, T* p0B, T* f0, const int* act, const
     auto P_ = [&](int l) -> T* { return l == 0 ? p0 : level_p<T>(P, l); };
     auto PB_ = [&](int l) -> T* { return l == 0 ? p0B : level_pB<T>(P, l); };
     auto F_ = [&](int l) -> T* { return l == 0 ? f0 : level_f<T>(P, l); };
-    auto use_march = [&](int l) { return fused_ok && P->march_ok[l] && PB_(l) != nullptr; };
-    auto rbgs = [&](int l) {
+    auto use_march = [&](int l) __attribute__((always_inline)) { return fused_ok && P->march_ok[l] && PB_(l) != nullptr; };
+    auto rbgs = [&](int l) __attribute__((always_inline)) {
         const Level& Lf = P->levels[l];
         for (int colour = 0; colour < (Lf.oddwrap ? 4 : 2); ++colour)
             hipLaunchKernelGGL(k_rbgs<T>, dim3(Lf.ntiles, nitems), blk, 0, s, P->d_blk + Lf.blk_off,

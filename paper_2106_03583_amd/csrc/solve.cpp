@@ -90,7 +90,7 @@ Layout layout(const mbp_plan* P, size_t ftile_bytes, size_t mtile_bytes, int npa
 
 }  // namespace
 
-constexpr int kMarchSeg = 64;  // rows per fused-sweep strip
+constexpr int kMarchSeg = 30;  // rows per fused-sweep strip (the LDS tile height)
 
 // Fused-sweep strips of every level (host tables); fills march_ok.
 void plan_march_tables(mbp_plan* P, std::vector<unsigned char>& bytes) {
