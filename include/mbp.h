@@ -218,6 +218,22 @@ int mbp_inverse_transform(mbp_plan* plan, const double* phat_dev, double* p_dev,
 int mbp_apply_operator(mbp_plan* plan, const double* p_dev, double* out_dev, void* stream);
 int mbp_modal_shift(const mbp_plan* plan, double* shift_host);
 
+/* Kernel timing for roofline reports.  While enabled, the finest-level
+ * fused smoothing launches of every solve on the plan are bracketed by HIP
+ * events on the solve's stream.  mbp_profile_read waits for those events and
+ * returns, per kernel class (0: pre-smoothing sweep + restriction, 1:
+ * correction + post-smoothing sweep + residual norm), the launch count, the
+ * summed duration in ms and the cells processed (plane cells x active modes,
+ * summed over launches); enabling again clears the record.  Errors:
+ * MBP_ERR_INVALID for a NULL plan. */
+typedef struct {
+    int64_t launches[2];
+    double total_ms[2];
+    double cells[2];
+} mbp_profile_info;
+int mbp_profile_enable(mbp_plan* plan, int enable);
+int mbp_profile_read(mbp_plan* plan, mbp_profile_info* out);
+
 /* Release the plan's device memory.  The caller ensures no work is in
  * flight on it.  NULL is ignored. */
 void mbp_plan_destroy(mbp_plan* plan);

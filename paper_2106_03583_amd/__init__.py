@@ -8,7 +8,7 @@ PyTorch supplies device memory (float64 CUDA/HIP tensors) and streams.
     info = plan.solve(rhs, p, rtol=1e-10)     # rhs, p: float64 device tensors
 
 The library is loaded from this directory (libmbp.so, built by
-``paper_2106_03583_amd.build``); importing fails loudly when it is missing.
+``paper_2106_03583_amd/build.py``); importing fails loudly when it is missing.
 """
 from __future__ import annotations
 
@@ -49,6 +49,10 @@ class SolveInfo(C.Structure):
                 ("t_ms", C.c_double * 4)]
 
 
+class ProfileInfo(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 2), ("total_ms", C.c_double * 2), ("cells", C.c_double * 2)]
+
+
 class PlanSummary(C.Structure):
     _fields_ = [("ncells", C.c_int64), ("nlevels", C.c_int32), ("coarse_cells", C.c_int32),
                 ("singular", C.c_int32), ("nblocks", C.c_int32), ("workspace_bytes", C.c_int64),
@@ -57,7 +61,7 @@ class PlanSummary(C.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"libmbp.so not built at {LIB_PATH}; run python -m paper_2106_03583_amd.build")
+        raise ImportError(f"libmbp.so not built at {LIB_PATH}; run python paper_2106_03583_amd/build.py")
     lib = C.CDLL(LIB_PATH)
     P, I, D, VP = C.c_void_p, C.c_int, C.c_double, C.c_void_p
     sig = {
@@ -77,6 +81,8 @@ def _load():
         "mbp_apply_operator": (I, [P, VP, VP, VP]),
         "mbp_modal_shift": (I, [P, C.POINTER(D)]),
         "mbp_plan_destroy": (None, [P]),
+        "mbp_profile_enable": (I, [P, I]),
+        "mbp_profile_read": (I, [P, C.POINTER(ProfileInfo)]),
         "mbp_server_create": (I, [C.c_size_t, I, C.POINTER(Options), C.POINTER(P)]),
         "mbp_server_submit": (I, [P, C.POINTER(BlockDesc), I, C.POINTER(SynthDesc), VP, VP, D, I,
                                   C.POINTER(C.c_uint64)]),
@@ -98,7 +104,7 @@ EXPORTED = [
     "mbp_plan_layout", "mbp_solve", "mbp_solve_batch", "mbp_forward_transform",
     "mbp_inverse_transform", "mbp_apply_operator", "mbp_modal_shift", "mbp_plan_destroy",
     "mbp_server_create", "mbp_server_submit", "mbp_server_poll", "mbp_server_wait",
-    "mbp_server_destroy",
+    "mbp_server_destroy", "mbp_profile_enable", "mbp_profile_read",
 ]
 
 
@@ -256,6 +262,14 @@ class Plan:
         out = np.empty(self.nz, dtype=np.float64)
         _check(lib.mbp_modal_shift(self._h, out.ctypes.data_as(C.POINTER(C.c_double))), "modal_shift")
         return out
+
+    def profile(self, enable: bool = True):
+        _check(lib.mbp_profile_enable(self._h, 1 if enable else 0), "mbp_profile_enable")
+
+    def profile_read(self) -> dict:
+        pi = ProfileInfo()
+        _check(lib.mbp_profile_read(self._h, C.byref(pi)), "mbp_profile_read")
+        return {"launches": list(pi.launches), "total_ms": list(pi.total_ms), "cells": list(pi.cells)}
 
     def close(self):
         if self._h:

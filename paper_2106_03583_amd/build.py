@@ -1,6 +1,9 @@
 """Build libmbp.so (HIP, gfx950) in-tree.
 
-    python -m paper_2106_03583_amd.build        # or build() from Python
+    python paper_2106_03583_amd/build.py        # or build() from Python
+
+It runs as a plain script so that a stale or missing library does not stop
+the package import from reaching it.
 
 Every source under csrc/ is compiled with hipcc for gfx950 and linked into
 paper_2106_03583_amd/libmbp.so.  Objects go to _build/ at the repository root.

@@ -153,6 +153,30 @@ int mbp_modal_shift(const mbp_plan* plan, double* shift_host) {
     return MBP_OK;
 }
 
+int mbp_profile_enable(mbp_plan* plan, int enable) {
+    if (!plan) return MBP_ERR_INVALID;
+    plan->prof = enable != 0;
+    plan->prof_used[0] = plan->prof_used[1] = 0;
+    return MBP_OK;
+}
+
+int mbp_profile_read(mbp_plan* plan, mbp_profile_info* out) {
+    if (!plan || !out) return MBP_ERR_INVALID;
+    std::memset(out, 0, sizeof(*out));
+    for (int c = 0; c < 2; ++c)
+        for (size_t i = 0; i < plan->prof_used[c]; ++i) {
+            hipEvent_t a = static_cast<hipEvent_t>(plan->prof_ev[c][i][0]);
+            hipEvent_t b = static_cast<hipEvent_t>(plan->prof_ev[c][i][1]);
+            if (hipEventSynchronize(b) != hipSuccess) return MBP_ERR_HIP;
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return MBP_ERR_HIP;
+            out->launches[c] += 1;
+            out->total_ms[c] += ms;
+            out->cells[c] += plan->prof_cells[c][i];
+        }
+    return MBP_OK;
+}
+
 void mbp_plan_destroy(mbp_plan* plan) {
     if (!plan) return;
     plan_device_free(plan);

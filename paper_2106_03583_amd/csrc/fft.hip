@@ -9,6 +9,8 @@
 // All transforms are orthonormal.  The complex FFT is a mixed-radix Stockham
 // autosort held in LDS; a workgroup transforms W neighbouring columns, whose
 // z rows are read and written as contiguous W-element segments.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace mbp {
@@ -45,47 +47,87 @@ __device__ __forceinline__ int xcd_remap(int g, int n) {
     return x * per + min(x, rem) + l;
 }
 
+// DFT of length R of v[0..R-1] in place, forward sign e^{-2 pi i rs/R}.
+// Radices 2, 4 and 8 use their closed-form roots; odd radices read the roots
+// tw[(r s mod R) m / R] from the twiddle table.
+template <int R>
+__device__ __forceinline__ void dft(double2* v, const double* __restrict__ tw, int m) {
+    if constexpr (R == 2) {
+        const double2 a = v[0], b = v[1];
+        v[0] = make_double2(a.x + b.x, a.y + b.y);
+        v[1] = make_double2(a.x - b.x, a.y - b.y);
+    } else if constexpr (R == 4) {
+        const double2 s02 = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
+        const double2 d02 = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
+        const double2 s13 = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
+        const double2 d13 = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
+        v[0] = make_double2(s02.x + s13.x, s02.y + s13.y);
+        v[2] = make_double2(s02.x - s13.x, s02.y - s13.y);
+        v[1] = make_double2(d02.x + d13.y, d02.y - d13.x);  // d02 - i d13
+        v[3] = make_double2(d02.x - d13.y, d02.y + d13.x);  // d02 + i d13
+    } else if constexpr (R == 8) {
+        // two length-4 DFTs of the even / odd samples, then the radix-2 step
+        // with the eighth roots e^{-i pi s / 4}
+        double2 e[4] = {v[0], v[2], v[4], v[6]};
+        double2 o[4] = {v[1], v[3], v[5], v[7]};
+        dft<4>(e, tw, m);
+        dft<4>(o, tw, m);
+        const double h = 0.70710678118654752440;
+        const double2 w1 = make_double2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));   // e^{-i pi/4} o1
+        const double2 w2 = make_double2(o[2].y, -o[2].x);                                // -i o2
+        const double2 w3 = make_double2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));  // e^{-3i pi/4} o3
+        v[0] = make_double2(e[0].x + o[0].x, e[0].y + o[0].y);
+        v[4] = make_double2(e[0].x - o[0].x, e[0].y - o[0].y);
+        v[1] = make_double2(e[1].x + w1.x, e[1].y + w1.y);
+        v[5] = make_double2(e[1].x - w1.x, e[1].y - w1.y);
+        v[2] = make_double2(e[2].x + w2.x, e[2].y + w2.y);
+        v[6] = make_double2(e[2].x - w2.x, e[2].y - w2.y);
+        v[3] = make_double2(e[3].x + w3.x, e[3].y + w3.y);
+        v[7] = make_double2(e[3].x - w3.x, e[3].y - w3.y);
+    } else {
+        double2 y[R];
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            double2 acc = v[0];
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const double2 rt = ld2(tw, ((r * s) % R) * (m / R));
+                const double2 pr = cmul(v[r], rt);
+                acc.x += pr.x;
+                acc.y += pr.y;
+            }
+            y[s] = acc;
+        }
+#pragma unroll
+        for (int s = 0; s < R; ++s) v[s] = y[s];
+    }
+}
+
 // One Stockham stage of radix R over W columns held column-major in LDS
 // (column stride cs complex values).  Reads all inputs into registers before
 // a barrier, then writes the outputs, so the stage runs in place.
 template <int R, int BPT>
-__device__ void stage(double2* z, int cs, int m, int W, int Ns, const double* tw) {
+__device__ void stage(double2* z, int cs, int m, int W, int Ns, const double* __restrict__ tw) {
     const int nbf = m / R;
     const int total = W * nbf;
+    const int step = m / (Ns * R);  // twiddle index stride
     double2 v[BPT][R];
     int dst[BPT];
 #pragma unroll
     for (int t = 0; t < BPT; ++t) {
-        int b = threadIdx.x + t * blockDim.x;
+        const int b = threadIdx.x + t * blockDim.x;
         dst[t] = -1;
         if (b < total) {
-            int w = b / nbf, j = b - w * nbf;
-            int k = j % Ns;
+            const int w = b / nbf, j = b - w * nbf;
+            const int k = j % Ns;
             const double2* col = z + w * cs;
-            int step = m / (Ns * R);  // twiddle index stride
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 double2 x = col[j + r * nbf];
                 if (r > 0 && k > 0) x = cmul(x, ld2(tw, (k * r * step) % m));
                 v[t][r] = x;
             }
-            // DFT of length R with the roots e^{-2 pi i r s / R} = tw[(r s mod R) * m / R]
-            double2 y[R];
-#pragma unroll
-            for (int s = 0; s < R; ++s) {
-                double2 acc = v[t][0];
-#pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    int e = (r * s) % R;
-                    double2 rt = ld2(tw, e * (m / R));
-                    double2 pr = cmul(v[t][r], rt);
-                    acc.x += pr.x;
-                    acc.y += pr.y;
-                }
-                y[s] = acc;
-            }
-#pragma unroll
-            for (int s = 0; s < R; ++s) v[t][s] = y[s];
+            dft<R>(v[t], tw, m);
             dst[t] = w * cs + (j / Ns) * Ns * R + k;
         }
     }
@@ -107,36 +149,52 @@ __device__ void stage_dispatch(double2* z, int cs, int m, int W, int Ns, const d
         stage<R, 1>(z, cs, m, W, Ns, tw);  // the host keeps W * m / R <= 256 here
     } else {
         if (bpt <= 1) stage<R, 1>(z, cs, m, W, Ns, tw);
-        else if (bpt <= 2) stage<R, 2>(z, cs, m, W, Ns, tw);
-        else stage<R, 4>(z, cs, m, W, Ns, tw);
+        else stage<R, 2>(z, cs, m, W, Ns, tw);  // the host keeps W * m / R <= 512
     }
 }
 
+// Radix classes: 0 = powers of two only, 1 = with 3 / 5 / 7, 2 = any prime
+// up to 31.  Each class is its own kernel so the power-of-two transforms do
+// not carry the register footprint of the long odd butterflies.
+template <int CLASS>
 __device__ void fft_columns(double2* z, int cs, const FFTArgs& a) {
     int Ns = 1;
     for (int s = 0; s < a.nstage; ++s) {
-        int R = a.radix[s];
+        const int R = a.radix[s];
         switch (R) {
             case 2: stage_dispatch<2>(z, cs, a.m, a.W, Ns, a.tw); break;
-            case 3: stage_dispatch<3>(z, cs, a.m, a.W, Ns, a.tw); break;
             case 4: stage_dispatch<4>(z, cs, a.m, a.W, Ns, a.tw); break;
-            case 5: stage_dispatch<5>(z, cs, a.m, a.W, Ns, a.tw); break;
-            case 7: stage_dispatch<7>(z, cs, a.m, a.W, Ns, a.tw); break;
             case 8: stage_dispatch<8>(z, cs, a.m, a.W, Ns, a.tw); break;
-            case 11: stage_dispatch<11>(z, cs, a.m, a.W, Ns, a.tw); break;
-            case 13: stage_dispatch<13>(z, cs, a.m, a.W, Ns, a.tw); break;
-            case 17: stage_dispatch<17>(z, cs, a.m, a.W, Ns, a.tw); break;
-            case 19: stage_dispatch<19>(z, cs, a.m, a.W, Ns, a.tw); break;
-            case 23: stage_dispatch<23>(z, cs, a.m, a.W, Ns, a.tw); break;
-            case 29: stage_dispatch<29>(z, cs, a.m, a.W, Ns, a.tw); break;
-            case 31: stage_dispatch<31>(z, cs, a.m, a.W, Ns, a.tw); break;
-            default: break;  // rejected on the host
+            default:
+                if constexpr (CLASS >= 1) {
+                    switch (R) {
+                        case 3: stage_dispatch<3>(z, cs, a.m, a.W, Ns, a.tw); break;
+                        case 5: stage_dispatch<5>(z, cs, a.m, a.W, Ns, a.tw); break;
+                        case 7: stage_dispatch<7>(z, cs, a.m, a.W, Ns, a.tw); break;
+                        default:
+                            if constexpr (CLASS >= 2) {
+                                switch (R) {
+                                    case 11: stage_dispatch<11>(z, cs, a.m, a.W, Ns, a.tw); break;
+                                    case 13: stage_dispatch<13>(z, cs, a.m, a.W, Ns, a.tw); break;
+                                    case 17: stage_dispatch<17>(z, cs, a.m, a.W, Ns, a.tw); break;
+                                    case 19: stage_dispatch<19>(z, cs, a.m, a.W, Ns, a.tw); break;
+                                    case 23: stage_dispatch<23>(z, cs, a.m, a.W, Ns, a.tw); break;
+                                    case 29: stage_dispatch<29>(z, cs, a.m, a.W, Ns, a.tw); break;
+                                    case 31: stage_dispatch<31>(z, cs, a.m, a.W, Ns, a.tw); break;
+                                    default: break;  // rejected on the host
+                                }
+                            }
+                            break;
+                    }
+                }
+                break;
         }
         Ns *= R;
     }
 }
 
 // Forward (dir = 0) or inverse (dir = 1) transform of W columns per workgroup.
+template <int CLASS>
 __global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict__ tiles, int ntiles,
                                              int dir, const double* __restrict__ in,
                                              double* __restrict__ out, int* nonfinite) {
@@ -153,6 +211,7 @@ __global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict_
     // ---------------- load + pre-processing ----------------
     if (!inv_cos) {
         bool bad = false;
+#pragma unroll 8
         for (int idx = threadIdx.x; idx < n * W; idx += blockDim.x) {
             int k = idx / W, w = idx - k * W;
             double x = 0.0;
@@ -191,40 +250,55 @@ __global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict_
         // Z_k = (V_k + conj V_{m-k}) + i (V_k - conj V_{m-k}) e^{2 pi i k/n};
         // the FFT below then computes conj(IFFT) of conj(Z).
         const int half = m / 2;
+#pragma unroll 4
         for (int idx = threadIdx.x; idx < (half + 1) * W; idx += blockDim.x) {
-            int k = idx / W, w = idx - k * W;
-            auto Y = [&](int q) __attribute__((always_inline)) -> double {  // y'_q = y_q / c_q, y'_n = 0
-                if (q >= n || w >= T.ncol) return 0.0;
-                int row = kind == Z_DD ? n - 1 - q : q;
-                double y = in[T.in_base + (long long)row * T.in_stride + w];
-                return y / (q == 0 ? sc1 : sc2);
-            };
-            auto V = [&](int q) __attribute__((always_inline)) -> double2 {
-                double2 c = cconj(ld2(a.post, q));
-                double2 t = make_double2(Y(q), -Y(n - q));
-                return cmul(c, t);
-            };
-            double2 Vk = V(k), Vmk = V(m - k);
-            auto Zk = [&](double2 A, double2 B, int kk) __attribute__((always_inline)) -> double2 {
-                double2 Bc = cconj(B);
-                double2 s = make_double2(A.x + Bc.x, A.y + Bc.y);
-                double2 d = make_double2(A.x - Bc.x, A.y - Bc.y);
-                double2 e = cconj(ld2(a.twn, kk));  // e^{+2 pi i kk / n}
-                double2 id = cmul(make_double2(-d.y, d.x), e);
-                return make_double2(s.x + id.x, s.y + id.y);
-            };
-            if (k < m) z[w * cs + k] = cconj(Zk(Vk, Vmk, k));
-            if (k > 0 && m - k != k && m - k < m) z[w * cs + (m - k)] = cconj(Zk(Vmk, Vk, m - k));
+            const int k = idx / W, w = idx - k * W;
+            const bool colok = w < T.ncol;
+            // y'_q = y_q / c_q at q = k, n-k, m-k, m+k (y'_n = 0)
+            double yv0, yv1, yv2, yv3;
+#define MBP_LOAD_Y(qq, dst)                                                                   \
+    {                                                                                          \
+        double y_ = 0.0;                                                                       \
+        if ((qq) < n && colok) {                                                               \
+            const int row_ = kind == Z_DD ? n - 1 - (qq) : (qq);                               \
+            y_ = in[T.in_base + (long long)row_ * T.in_stride + w] / ((qq) == 0 ? sc1 : sc2);   \
+        }                                                                                      \
+        dst = y_;                                                                              \
+    }
+            MBP_LOAD_Y(k, yv0)
+            MBP_LOAD_Y(n - k, yv1)
+            MBP_LOAD_Y(m - k, yv2)
+            MBP_LOAD_Y(m + k, yv3)
+#undef MBP_LOAD_Y
+            // V_q = e^{i pi q/(2n)} (y'_q - i y'_{n-q}) for q = k and m - k
+            const double2 Vk = cmul(cconj(ld2(a.post, k)), make_double2(yv0, -yv1));
+            const double2 Vmk = cmul(cconj(ld2(a.post, m - k)), make_double2(yv2, -yv3));
+            // Z_kk = (A + conj B) + i (A - conj B) e^{2 pi i kk / n}
+            {
+                const double2 Bc = cconj(Vmk);
+                const double2 s = make_double2(Vk.x + Bc.x, Vk.y + Bc.y);
+                const double2 d = make_double2(Vk.x - Bc.x, Vk.y - Bc.y);
+                const double2 id = cmul(make_double2(-d.y, d.x), cconj(ld2(a.twn, k)));
+                if (k < m) z[w * cs + k] = cconj(make_double2(s.x + id.x, s.y + id.y));
+            }
+            if (k > 0 && m - k != k && m - k < m) {
+                const double2 Bc = cconj(Vk);
+                const double2 s = make_double2(Vmk.x + Bc.x, Vmk.y + Bc.y);
+                const double2 d = make_double2(Vmk.x - Bc.x, Vmk.y - Bc.y);
+                const double2 id = cmul(make_double2(-d.y, d.x), cconj(ld2(a.twn, m - k)));
+                z[w * cs + (m - k)] = cconj(make_double2(s.x + id.x, s.y + id.y));
+            }
         }
         __syncthreads();
     }
 
     // ---------------- complex FFT of length m ----------------
-    fft_columns(z, cs, a);
+    fft_columns<CLASS>(z, cs, a);
 
     // ---------------- post-processing + store ----------------
     if (inv_cos) {
         const double inv_n = 1.0 / n;
+#pragma unroll 8
         for (int idx = threadIdx.x; idx < n * W; idx += blockDim.x) {
             int j = idx / W, w = idx - j * W;
             if (w >= T.ncol) continue;
@@ -237,6 +311,7 @@ __global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict_
         return;
     }
     if (kind == Z_ND || kind == Z_DN) {
+#pragma unroll 4
         for (int idx = threadIdx.x; idx < m * W; idx += blockDim.x) {
             int k = idx / W, w = idx - k * W;
             if (w >= T.ncol) continue;
@@ -253,6 +328,7 @@ __global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict_
         return;
     }
     // PP / NN / DD: real DFT X_k (k = 0..m) from the half-length FFT
+#pragma unroll 4
     for (int idx = threadIdx.x; idx < (m + 1) * W; idx += blockDim.x) {
         int k = idx / W, w = idx - k * W;
         if (w >= T.ncol) continue;
@@ -287,12 +363,14 @@ int fft_col_stride(const mbp_plan* P);
 // Columns per workgroup: at most 16, the LDS image W * cs complex values must
 // fit the budget, and every stage must fit 256 threads x (4 butterflies for
 // radices <= 8, 1 butterfly for the larger odd radices).
+constexpr int64_t kFFTLds = 80 * 1024;  // two workgroups per CU
+
 int fft_columns_per_wg(const mbp_plan* P) {
     const int m = P->fft.m;
     int W = 16;
-    while (W > 1 && int64_t(W) * fft_col_stride(P) * 16 > P->lds_limit) W >>= 1;
+    while (W > 1 && int64_t(W) * fft_col_stride(P) * 16 > std::min<int64_t>(kFFTLds, P->lds_limit)) W >>= 1;
     for (int R : P->fft.radices)
-        while (W > 1 && W * (m / R) > (R > 8 ? 256 : 4 * 256)) W >>= 1;
+        while (W > 1 && W * (m / R) > (R > 8 ? 256 : 2 * 256)) W >>= 1;
     return W;
 }
 
@@ -300,7 +378,7 @@ int fft_columns_per_wg(const mbp_plan* P) {
 // bank pattern when the padded image still fits.
 int fft_col_stride(const mbp_plan* P) {
     const int m = P->fft.m;
-    return (int64_t(8) * (m + 1) * 16 <= P->lds_limit) ? m + 1 : m;
+    return (int64_t(8) * (m + 1) * 16 <= std::min<int64_t>(kFFTLds, P->lds_limit)) ? m + 1 : m;
 }
 
 void fft_build_tiles(const mbp_plan* P, std::vector<unsigned char>& fwd, std::vector<unsigned char>& inv,
@@ -355,26 +433,42 @@ static size_t lds_bytes(const mbp_plan* P) {
     return size_t(fft_columns_per_wg(P)) * fft_col_stride(P) * sizeof(double2);
 }
 
-static void set_lds_fft(size_t bytes) {
+static int radix_class(const mbp_plan* P) {
+    int c = 0;
+    for (int R : P->fft.radices) {
+        if (R == 3 || R == 5 || R == 7) c = std::max(c, 1);
+        else if (R > 8) c = 2;
+    }
+    return c;
+}
+
+template <int CLASS>
+static void launch_r2r(const mbp_plan* P, const FFTArgs& a, const void* tiles, int dir, const double* in,
+                       double* out, int* nonfinite, hipStream_t s) {
+    const size_t bytes = lds_bytes(P);
     if (bytes > 64 * 1024)
-        hipFuncSetAttribute(reinterpret_cast<const void*>(k_r2r), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            int(bytes));
+        hipFuncSetAttribute(reinterpret_cast<const void*>(k_r2r<CLASS>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+    hipLaunchKernelGGL(k_r2r<CLASS>, dim3(P->fft_ntiles), dim3(256), bytes, s, a,
+                       reinterpret_cast<const FTile*>(tiles), P->fft_ntiles, dir, in, out, nonfinite);
+}
+
+static void run_r2r(const mbp_plan* P, const void* tiles, int dir, const double* in, double* out,
+                    int* nonfinite, hipStream_t s) {
+    const FFTArgs a = make_args(P);
+    switch (radix_class(P)) {
+        case 0: launch_r2r<0>(P, a, tiles, dir, in, out, nonfinite, s); break;
+        case 1: launch_r2r<1>(P, a, tiles, dir, in, out, nonfinite, s); break;
+        default: launch_r2r<2>(P, a, tiles, dir, in, out, nonfinite, s); break;
+    }
 }
 
 void launch_forward(const mbp_plan* P, const double* f, double* fhat, int* nonfinite, hipStream_t s) {
-    FFTArgs a = make_args(P);
-    set_lds_fft(lds_bytes(P));
-    hipLaunchKernelGGL(k_r2r, dim3(P->fft_ntiles), dim3(256), lds_bytes(P), s, a,
-                       reinterpret_cast<const FTile*>(P->d_ftiles_fwd), P->fft_ntiles, 0, f, fhat,
-                       nonfinite);
+    run_r2r(P, P->d_ftiles_fwd, 0, f, fhat, nonfinite, s);
 }
 
 void launch_inverse(const mbp_plan* P, const double* phat, double* p, hipStream_t s) {
-    FFTArgs a = make_args(P);
-    set_lds_fft(lds_bytes(P));
-    hipLaunchKernelGGL(k_r2r, dim3(P->fft_ntiles), dim3(256), lds_bytes(P), s, a,
-                       reinterpret_cast<const FTile*>(P->d_ftiles_inv), P->fft_ntiles, 1, phat, p,
-                       nullptr);
+    run_r2r(P, P->d_ftiles_inv, 1, phat, p, nullptr, s);
 }
 
 }  // namespace mbp

@@ -151,6 +151,11 @@ struct mbp_plan {
     double* d_scal = nullptr;     // 8 doubles of scratch scalars
     void* graph_exec = nullptr;   // cached batched replay (hipGraphExec_t)
     void* host_pinned = nullptr;  // small pinned buffer for convergence readback
+    // kernel timing (mbp_profile_*): event pairs around finest-level sweeps
+    bool prof = false;
+    std::vector<std::array<void*, 2>> prof_ev[2];  // hipEvent_t pairs per kernel class
+    std::vector<double> prof_cells[2];
+    size_t prof_used[2] = {0, 0};
 };
 
 namespace mbp {
@@ -185,6 +190,10 @@ int launch_vcycle(const mbp_plan* P, T* p0, T* p0B, T* f0, const int* act, const
                   int nitems, bool norm0, hipStream_t s);
 void launch_finish(const mbp_plan* P, int nparts, double* out, const int* act, const int* nact,
                    int nitems, hipStream_t s);
+
+// kernel timing helpers (solve.cpp)
+void prof_begin(const mbp_plan* P, int cls, hipStream_t s, double cells);
+void prof_end(const mbp_plan* P, int cls, hipStream_t s);
 
 // march.hip
 struct MTile;

@@ -801,7 +801,9 @@ int launch_vcycle(const mbp_plan* P, T* p0, T* p0B, T* f0, const int* act, const
                 march_sweep<T>(P, l, a, b, F_(l), act, nact, nitems, s);
                 std::swap(a, b);
             }
+            if (l == 0) prof_begin(P, 0, s, double(Lf.plane) * nitems);
             march_pre<T>(P, l, a, b, F_(l), F_(l + 1), P_(l + 1), act, nact, nitems, s);
+            if (l == 0) prof_end(P, 0, s);
         } else {
             for (int it = 0; it < nu1; ++it) rbgs(l);
             hipLaunchKernelGGL(k_restrict<T>, dim3(Lc.ntiles, nitems), blk, 0, s, P->d_blk + Lf.blk_off,
@@ -828,7 +830,9 @@ int launch_vcycle(const mbp_plan* P, T* p0, T* p0B, T* f0, const int* act, const
             T* cur = (nu1 % 2 == 1) ? b : a;
             T* oth = (cur == a) ? b : a;
             const bool nrm = norm0 && l == 0 && nu2 == 1;
+            if (l == 0) prof_begin(P, 1, s, double(Lf.plane) * nitems);
             march_post<T>(P, l, cur, oth, F_(l), P_(l + 1), nrm, act, nact, nitems, s);
+            if (l == 0) prof_end(P, 1, s);
             std::swap(cur, oth);
             for (int it = 1; it < nu2; ++it) {
                 const bool last = it == nu2 - 1;

@@ -202,7 +202,41 @@ int plan_device_init(mbp_plan* P) {
     return MBP_OK;
 }
 
+// Event pairs around a finest-level sweep launch (only while profiling).
+// The plan object is logically const for the kernels; the record is mutable.
+void prof_begin(const mbp_plan* Pc, int cls, hipStream_t s, double cells) {
+    mbp_plan* P = const_cast<mbp_plan*>(Pc);
+    if (!P->prof) return;
+    auto& v = P->prof_ev[cls];
+    const size_t i = P->prof_used[cls];
+    if (i == v.size()) {
+        std::array<void*, 2> e{nullptr, nullptr};
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+        e[0] = a;
+        e[1] = b;
+        v.push_back(e);
+        P->prof_cells[cls].push_back(0.0);
+    }
+    P->prof_cells[cls][i] = cells;
+    (void)hipEventRecord(static_cast<hipEvent_t>(v[i][0]), s);
+}
+
+void prof_end(const mbp_plan* Pc, int cls, hipStream_t s) {
+    mbp_plan* P = const_cast<mbp_plan*>(Pc);
+    if (!P->prof) return;
+    const size_t i = P->prof_used[cls];
+    if (i >= P->prof_ev[cls].size()) return;
+    (void)hipEventRecord(static_cast<hipEvent_t>(P->prof_ev[cls][i][1]), s);
+    P->prof_used[cls] = i + 1;
+}
+
 void plan_device_free(mbp_plan* P) {
+    for (int c = 0; c < 2; ++c)
+        for (auto& e : P->prof_ev[c]) {
+            (void)hipEventDestroy(static_cast<hipEvent_t>(e[0]));
+            (void)hipEventDestroy(static_cast<hipEvent_t>(e[1]));
+        }
     if (P->dmem) (void)hipFree(P->dmem);
     if (P->host_pinned) (void)hipHostFree(P->host_pinned);
     P->dmem = nullptr;
