@@ -1,0 +1,298 @@
+"""Throughput of the FFT-accelerated multi-block Poisson solve on one GPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lshape|box|cube32]
+                    [--precision fp64|mixed] [--lockstep] [--no-cpu] [--no-variants]
+
+One step is one complete solve of the pressure-Poisson problem (Algorithm 1):
+forward z-transform, the shifted 2D multigrid solves of every mode to a
+relative residual of 1e-10, inverse transform.  The rhs is resident in device
+memory before the timed region starts.  The default workload is the
+three-block L-shaped cross-section (each block 256 x 256, tanh-stretched y,
+Neumann walls) with 512 periodic z cells, solved in FP64, each mode stopped
+at its own convergence test.
+
+Output: one JSON line with grid points/s (``value``), solves/s, the roofline
+record of the dominant kernel (the finest-level fused smoothing sweep, timed
+with events on the solve stream) and the CPU oracle timed on a bounded sample
+of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+import workloads as W  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+RTOL = 1e-10
+
+
+def _workload(name: str):
+    if name == "lshape":
+        return W.config2(), W.CONFIG_SEEDS[2], W.CONFIG_DIST[2]
+    if name == "box":
+        return W.config3(), W.CONFIG_SEEDS[3], W.CONFIG_DIST[3]
+    if name == "cube32":
+        return W.config1(), W.CONFIG_SEEDS[1], W.CONFIG_DIST[1]
+    raise SystemExit(f"unknown workload {name}")
+
+
+def _bytes_per_cell(precision: str) -> float:
+    """Method bytes of one finest-level fused launch per plane cell and mode.
+
+    Each launch does one red-black smoothing sweep (read p and f, write p:
+    3 words) plus either the residual with its restriction (read p and f,
+    write a quarter-size coarse rhs: 2.25 words) or the prolongation with its
+    correction (2.25 words), so 5.25 words per cell.
+    """
+    w = 8.0 if precision == "fp64" else 4.0
+    return 5.25 * w
+
+
+def _vcycle_bytes_per_point(precision: str, nu1: int, nu2: int) -> float:
+    """Method bytes of one V-cycle per fine point: (sweeps*3 + 4.5) words x 4/3."""
+    w = 8.0 if precision == "fp64" else 4.0
+    return ((nu1 + nu2) * 3.0 + 4.5) * w * 4.0 / 3.0
+
+
+def _traffic_record():
+    """HBM bytes per launch of the dominant kernel from the committed counter summary."""
+    path = os.path.join(HERE, "profiles", "traffic_fused_sweep_lshape_256x3x512.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    return rec
+
+
+def cpu_baseline(prob, f, budget_s: float = 20.0) -> dict:
+    """The FP64 oracle (Algorithm 1 with sparse LU per mode) on a bounded sample.
+
+    Sample: the full forward and inverse transforms, plus k factorisations and
+    solves of shifted planes with distinct shifts (smallest |shift| first, as
+    long as the time budget lasts); the full-solve time is extrapolated as
+    transforms + factorisations x (distinct shifts)/k + plane solves x nz/k.
+    """
+    import oracle
+    from oracle.solve import _geom, _plane_factor, _plane_solve, assemble_2d, _to_modes, _from_modes
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    g = _geom(prob)
+    T = oracle.basis(g.zkind, g.nz)
+    lam = oracle.eigenvalues(g.zkind, g.nz)
+    key = np.round(lam, 12)
+    distinct = len(set(key.tolist()))
+    _, first = np.unique(key, return_index=True)
+    order = sorted(first.tolist(), key=lambda q: abs(lam[q]))
+    t0 = time.perf_counter()
+    fp = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
+    fhat = _to_modes(g, fp, T)
+    t_fwd = time.perf_counter() - t0
+    A2 = assemble_2d(g)
+    phat = np.zeros_like(fhat)
+    t_fac = t_sol = 0.0
+    k = 0
+    sing_xy = not g.has_dirichlet_xy()
+    spent = time.perf_counter()
+    for q in order:
+        t1 = time.perf_counter()
+        fac = _plane_factor(g, A2, lam[q] / (g.dz * g.dz), (lam[q] == 0.0) and sing_xy)
+        t2 = time.perf_counter()
+        phat[q] = _plane_solve(fac, fhat[q])
+        t3 = time.perf_counter()
+        t_fac += t2 - t1
+        t_sol += t3 - t2
+        k += 1
+        if time.perf_counter() - spent > budget_s or k >= 64:
+            break
+    t0 = time.perf_counter()
+    _from_modes(g, phat, T)
+    t_inv = time.perf_counter() - t0
+    nz = g.nz
+    t_est = t_fwd + t_inv + t_fac * distinct / k + t_sol * nz / k
+    return {
+        "value": float(prob.ncells / t_est),
+        "unit": "grid points/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"FP64 oracle (Algorithm 1, sparse LU per shifted plane) on the same field: full forward "
+                   f"and inverse transforms ({t_fwd + t_inv:.1f} s), {k} of {distinct} distinct plane "
+                   f"factorisations with their solves ({t_fac + t_sol:.1f} s); full solve extrapolated as "
+                   f"transforms + factorisations x {distinct}/{k} + solves x {nz}/{k} = {t_est:.1f} s; "
+                   f"BLAS threads {threads}, factorisations single-threaded"),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="lshape", choices=["lshape", "box", "cube32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--lockstep", action="store_true", help="iterate all modes until the global test passes")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-variants", action="store_true", help="skip the short runs of the other forms")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the solver runs every mode of a problem on a single "
+              "device; multi-GPU sharding is not implemented (use --gpus 1).", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2106_03583_amd as mbp
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    prob, seed, dist = _workload(args.workload)
+    f = W.rhs(prob, seed, dist)
+    fd = torch.from_numpy(f).cuda()
+    flags = mbp.PROJECT_RHS | (0 if args.lockstep else mbp.RETIRE)
+    t0 = time.perf_counter()
+    plan = mbp.Plan(prob, precision=args.precision)
+    t_plan = (time.perf_counter() - t0) * 1e3
+    p = torch.zeros_like(fd)
+    print(f"# workload {prob.name} cells={prob.ncells} precision={args.precision} "
+          f"retire={not args.lockstep} plan_ms={t_plan:.1f}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        plan.solve(fd, p, rtol=RTOL, flags=flags)
+    torch.cuda.synchronize()
+
+    plan.profile(True)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    infos = []
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        infos.append(plan.solve(fd, p, rtol=RTOL, flags=flags, stream=stream))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = ev0.elapsed_time(ev1)
+    prof = plan.profile_read()
+    plan.profile(False)
+    ms_step = ms / args.steps
+    print(f"# timed {args.steps} solves: {ms_step:.2f} ms/solve (wall {wall * 1e3 / args.steps:.2f})",
+          file=sys.stderr, flush=True)
+
+    # correctness of the last solve: the solver's modal test and an
+    # independent physical-space residual through the 3D operator
+    last = infos[-1]
+    ok = all(i.status == 0 and i.rel_residual <= RTOL for i in infos)
+    Ap = torch.empty_like(fd)
+    plan.apply(p, Ap)
+    fpr = fd - last.removed_mean
+    res3d = float(torch.linalg.vector_norm(fpr - Ap) / torch.linalg.vector_norm(fpr))
+
+    # roofline of the dominant kernel (finest-level fused sweep)
+    cls = int(np.argmax(prof["total_ms"]))
+    launches = prof["launches"][cls]
+    roof = None
+    if launches > 0:
+        avg_ms = prof["total_ms"][cls] / launches
+        cells = prof["cells"][cls] / launches
+        bpc = _bytes_per_cell(args.precision)
+        achieved = bpc * cells / (avg_ms * 1e-3) / 1e9
+        traffic = None
+        tr = _traffic_record()
+        if tr and tr.get("kernel_class") == cls and tr.get("workload") == prob.name \
+                and tr.get("precision") == args.precision:
+            traffic = tr.get("bytes_per_launch")
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": ["k_tile pre-smooth+residual+restrict", "k_tile correct+post-smooth+norm"][cls],
+                "avg_launch_ms": round(avg_ms, 4), "launches": launches,
+                "bytes_per_launch": bpc * cells}
+
+    # all V-cycle work of the timed solves against the V-cycle byte model
+    vb = _vcycle_bytes_per_point(args.precision, 1, 1)
+    plane = prob.ncells // prob.nz
+    mg_ms = sum(i.t_ms[1] for i in infos) / len(infos)
+    cyc = sum(int(i.cycles_per_mode.sum()) if not args.lockstep else i.cycles * prob.nz for i in infos) / len(infos)
+    vcycle = {"bytes_per_point": vb, "mode_cycles": cyc, "mg_ms": round(mg_ms, 3),
+              "achieved_GBs": round(vb * plane * cyc / (mg_ms * 1e-3) / 1e9, 1)}
+    vcycle["frac"] = round(vcycle["achieved_GBs"] / HBM_PEAK_GBS, 4)
+
+    variants = {}
+    if not args.no_variants:
+        for name, prec, fl in [("fp64_lockstep", "fp64", mbp.PROJECT_RHS),
+                               ("fp64_retire", "fp64", mbp.PROJECT_RHS | mbp.RETIRE),
+                               ("mixed_retire", "mixed", mbp.PROJECT_RHS | mbp.RETIRE)]:
+            if prec == args.precision and fl == flags:
+                variants[name] = {"ms_per_solve": round(ms_step, 3), "rel_residual": last.rel_residual}
+                continue
+            pl = mbp.Plan(prob, precision=prec)
+            q = torch.zeros_like(fd)
+            pl.solve(fd, q, rtol=RTOL, flags=fl)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            n = 3
+            for _ in range(n):
+                inf = pl.solve(fd, q, rtol=RTOL, flags=fl, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            variants[name] = {"ms_per_solve": round(a.elapsed_time(b) / n, 3),
+                              "rel_residual": inf.rel_residual, "status": inf.status,
+                              "max_abs_diff_vs_timed": float((q - p).abs().max())}
+            pl.close()
+            del q
+
+    cpu = None
+    if not args.no_cpu:
+        print("# cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(prob, f)
+
+    value = prob.ncells * args.steps / (ms * 1e-3)
+    out = {
+        "metric": "grid points/s at 1e-10 relative residual",
+        "value": value,
+        "unit": "grid points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32-in-f64",
+        "data": "synthetic (seeded)",
+        "config": {"workload": prob.name, "cells": prob.ncells, "nz": prob.nz,
+                   "blocks": len(prob.blocks), "precision": args.precision,
+                   "mode_stop": "lockstep" if args.lockstep else "per-mode", "rtol": RTOL},
+        "solves_per_s": 1e3 / ms_step,
+        "ok": ok,
+        "rel_residual_modal": last.rel_residual,
+        "rel_residual_3d": res3d,
+        "cycles_max": last.cycles,
+        "t_ms_last": [round(t, 3) for t in last.t_ms],
+        "plan_ms": round(t_plan, 1),
+        "roofline": roof,
+        "vcycle_roofline": vcycle,
+        "variants": variants,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+    return 0 if ok else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())
