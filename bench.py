@@ -144,6 +144,8 @@ def main(argv=None):
     ap.add_argument("--lockstep", action="store_true", help="iterate all modes until the global test passes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the short runs of the other forms")
+    ap.add_argument("--copy-calibrate", action="store_true",
+                    help="only run five 1 GiB device-to-device copies (scale for HBM byte counters)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -158,6 +160,21 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if args.copy_calibrate:
+        n = 1 << 27
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(5):
+            y.copy_(x)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / 5
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "ms": ms,
+                          "GBs": 16 * n / (ms * 1e-3) / 1e9}), flush=True)
+        return 0
     prob, seed, dist = _workload(args.workload)
     f = W.rhs(prob, seed, dist)
     fd = torch.from_numpy(f).cuda()

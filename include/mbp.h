@@ -63,6 +63,8 @@ extern "C" {
 #define MBP_PROJECT_RHS 1 /* singular problems: remove the volume-weighted mean of rhs */
 #define MBP_WARM_START  2 /* p_dev holds the initial guess (Sec. 3.3.1: latest solution) */
 #define MBP_RETIRE      4 /* retire each z mode as soon as it converges (else lockstep) */
+#define MBP_AUTOTUNE    8 /* mbp_solve_batch: time candidate schedules on this call and keep
+                             the fastest for later calls with the same plan set */
 
 /* One block of the x-y cross-section (Table 2: lo / hi in index space,
  * inclusive, cells = hi - lo + 1; physical face coordinates).
@@ -195,14 +197,26 @@ int mbp_plan_layout(const mbp_plan* plan, int64_t* block_offsets, size_t* worksp
 int mbp_solve(mbp_plan* plan, const double* rhs_dev, double* p_dev, double rtol, int flags,
               void* stream, mbp_solve_info* info);
 
-/* Many independent solves in one call.  All z modes of all problems are put
- * on one device work list; converged modes are retired on the device and the
- * whole multigrid loop is replayed from one captured HIP graph per call
- * signature.  Plans may differ in size and conditions and must be distinct.
+/* Many independent solves in one call (Algorithm 1 for each).  After the
+ * forward transforms and one eager cycle, the cycles of every unfinished
+ * problem are captured into one HIP graph (one branch per internal stream)
+ * and replayed, a few cycles per replay; inside a replay the device tests
+ * every mode and retires converged ones, so finished problems cost only
+ * empty launches until the host, reading the active counts after each
+ * replay, captures a smaller graph.  Plans may differ in size, conditions
+ * and precision and must be distinct; each must be idle.  Every item runs
+ * with per-mode retirement.  The stream count and cycles per replay come
+ * from a cache keyed by the plan set, filled when a call passes
+ * MBP_AUTOTUNE (default 4 streams, 4 cycles).  Stream-ordered on `stream`
+ * at entry and exit; the call returns after the results are read back.
  * Returns MBP_OK if every item converged, else the first failing item's
  * status; infos (optional, count entries) hold the per-item reports. */
 int mbp_solve_batch(mbp_plan* const* plans, const double* const* rhs_dev, double* const* p_dev,
                     int count, double rtol, int flags, void* stream, mbp_solve_info* infos);
+
+/* Schedule the batch autotuner chose for this plan set: MBP_OK with the
+ * stream count and cycles per replay, or MBP_PENDING if none is cached. */
+int mbp_batch_schedule(mbp_plan* const* plans, int count, int* streams, int* cycles_per_replay);
 
 /* Building blocks of the solve, exposed for checking and for callers that
  * compose their own pipelines.  All are stream-ordered and asynchronous.
@@ -246,8 +260,11 @@ void mbp_plan_destroy(mbp_plan* plan);
  * and `hbm_budget` bytes of plan memory are free (continuous batching).
  *   mbp_server_create: opt may be NULL.  slots in [1, 64].
  *   mbp_server_submit: rhs_dev / p_dev stay owned by the caller and must stay
- *     valid until the ticket completes; returns MBP_ERR_TOO_LARGE when the
- *     request alone exceeds the budget, MBP_ERR_INVALID for a bad problem.
+ *     valid until the ticket completes; rhs_dev must already hold its data
+ *     (its producing stream synchronised).  The descriptor is copied.
+ *     Returns MBP_ERR_TOO_LARGE when the request alone exceeds the budget,
+ *     MBP_ERR_INVALID for a bad problem.  Requests run with per-mode
+ *     retirement and the server's options.
  *   mbp_server_poll: MBP_PENDING, or the request's final status with info
  *     filled; latency_ms (optional) = completion - submission, wall clock.
  *   mbp_server_wait: blocks until the ticket completes, then as poll.

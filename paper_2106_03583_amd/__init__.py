@@ -26,7 +26,7 @@ ERR_INVALID, ERR_NOMEM, ERR_HIP, ERR_NOT_CONVERGED = -1, -2, -3, -4
 ERR_NONFINITE, ERR_INCOMPATIBLE, ERR_BUSY, ERR_TOO_LARGE, ERR_NO_DEVICE = -5, -6, -7, -8, -9
 DIRICHLET, NEUMANN, CONNECT, PERIODIC = 1, 2, 3, 4
 FP64, MIXED = 0, 1
-PROJECT_RHS, WARM_START, RETIRE = 1, 2, 4
+PROJECT_RHS, WARM_START, RETIRE, AUTOTUNE = 1, 2, 4, 8
 
 
 class BlockDesc(C.Structure):
@@ -76,6 +76,7 @@ def _load():
         "mbp_solve": (I, [P, VP, VP, D, I, VP, C.POINTER(SolveInfo)]),
         "mbp_solve_batch": (I, [C.POINTER(P), C.POINTER(VP), C.POINTER(VP), I, D, I, VP,
                                 C.POINTER(SolveInfo)]),
+        "mbp_batch_schedule": (I, [C.POINTER(P), I, C.POINTER(I), C.POINTER(I)]),
         "mbp_forward_transform": (I, [P, VP, VP, VP]),
         "mbp_inverse_transform": (I, [P, VP, VP, VP]),
         "mbp_apply_operator": (I, [P, VP, VP, VP]),
@@ -104,7 +105,7 @@ EXPORTED = [
     "mbp_plan_layout", "mbp_solve", "mbp_solve_batch", "mbp_forward_transform",
     "mbp_inverse_transform", "mbp_apply_operator", "mbp_modal_shift", "mbp_plan_destroy",
     "mbp_server_create", "mbp_server_submit", "mbp_server_poll", "mbp_server_wait",
-    "mbp_server_destroy", "mbp_profile_enable", "mbp_profile_read",
+    "mbp_server_destroy", "mbp_profile_enable", "mbp_profile_read", "mbp_batch_schedule",
 ]
 
 
@@ -299,6 +300,18 @@ def solve_batch(plans: Sequence[Plan], rhs: Sequence, p: Sequence, rtol=1e-10, f
     if raise_on_error and st != OK:
         raise MBPError(st, "mbp_solve_batch")
     return [Info(infos[i], cpms[i]) for i in range(n)]
+
+
+def batch_schedule(plans: Sequence[Plan]):
+    """(streams, cycles per replay) the batch autotuner chose for this plan set, or None."""
+    n = len(plans)
+    hs = (C.c_void_p * n)(*[pl.handle.value for pl in plans])
+    a, b = C.c_int(), C.c_int()
+    st = lib.mbp_batch_schedule(hs, n, C.byref(a), C.byref(b))
+    if st == PENDING:
+        return None
+    _check(st, "mbp_batch_schedule")
+    return a.value, b.value
 
 
 class Server:

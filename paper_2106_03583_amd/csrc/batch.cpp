@@ -1,26 +1,254 @@
-// Batched solves (placeholder: sequential until the graph-replayed form lands).
+// Batched solves: many independent problems (each with all of its modes)
+// driven together.  After the prologue and one eager cycle, the cycles of
+// every unfinished problem are captured into one HIP graph, one branch per
+// stream, and replayed chunk by chunk: inside a replay the device runs the
+// convergence test and retires converged modes (and so finished problems,
+// whose kernels then exit at once); the host reads the active counts after
+// each replay and re-captures when the set has shrunk enough to pay off.
+// The number of streams and the cycles per replay come from a small online
+// autotuner, cached per batch signature.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
 #include "internal.h"
 
 namespace mbp {
 
+namespace {
+
+struct BatchTune {
+    int streams = 4;
+    int chunk = 4;
+};
+
+std::mutex g_tune_mu;
+std::map<uint64_t, BatchTune> g_tune;
+
+uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);
+    return h;
+}
+
+uint64_t batch_signature(mbp_plan* const* plans, int count) {
+    uint64_t h = 1469598103934665603ULL;
+    for (int i = 0; i < count; ++i) {
+        h = mix(h, uint64_t(plans[i]->ncells));
+        h = mix(h, uint64_t(plans[i]->g.nz));
+        h = mix(h, uint64_t(plans[i]->opt.precision));
+    }
+    return h;
+}
+
+constexpr int kMaxStreams = 8;
+
+struct Graph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    std::vector<int> members;
+    long long modes = 0;  // active modes captured (grid sizes)
+    void reset() {
+        if (e) (void)hipGraphExecDestroy(e);
+        if (g) (void)hipGraphDestroy(g);
+        e = nullptr;
+        g = nullptr;
+        members.clear();
+        modes = 0;
+    }
+};
+
+}  // namespace
+
 int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const* p, int count,
                 double rtol, int flags, hipStream_t s, mbp_solve_info* infos) {
-    int first = MBP_OK;
-    for (int i = 0; i < count; ++i) {
-        int st = solve_one(plans[i], rhs[i], p[i], rtol, flags | plans[i]->opt.flags | MBP_RETIRE, s,
-                           infos ? &infos[i] : nullptr);
-        if (st != MBP_OK && first == MBP_OK) first = st;
+    std::vector<SolveCtx> cx(count);
+    for (int i = 0; i < count; ++i)
+        ctx_init(cx[i], plans[i], rhs[i], p[i], rtol, flags | plans[i]->opt.flags | MBP_RETIRE);
+
+    const uint64_t sig = batch_signature(plans, count);
+    BatchTune tune;
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(sig);
+        if (it != g_tune.end()) {
+            tune = it->second;
+            have = true;
+        }
     }
-    return first;
+    std::vector<BatchTune> trials;
+    if ((flags & MBP_AUTOTUNE) && !have)
+        trials = {{4, 4}, {1, 4}, {8, 4}, {2, 4}, {4, 2}, {4, 8}};
+
+    // streams: [0] is the capture origin; all of them are forked from s
+    hipStream_t st[kMaxStreams];
+    hipEvent_t ev_fork, ev_join[kMaxStreams], t0, t1;
+    for (int k = 0; k < kMaxStreams; ++k) {
+        if (hipStreamCreateWithFlags(&st[k], hipStreamNonBlocking) != hipSuccess) return MBP_ERR_HIP;
+        (void)hipEventCreateWithFlags(&ev_join[k], hipEventDisableTiming);
+    }
+    (void)hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
+    (void)hipEventCreate(&t0);
+    (void)hipEventCreate(&t1);
+    auto fork = [&](hipStream_t from, int S) {
+        (void)hipEventRecord(ev_fork, from);
+        for (int k = 0; k < S; ++k)
+            if (st[k] != from) (void)hipStreamWaitEvent(st[k], ev_fork, 0);
+    };
+    auto join = [&](hipStream_t to, int S) {
+        for (int k = 0; k < S; ++k) {
+            if (st[k] == to) continue;
+            (void)hipEventRecord(ev_join[k], st[k]);
+            (void)hipStreamWaitEvent(to, ev_join[k], 0);
+        }
+    };
+    int status = MBP_OK;
+    auto fail = [&](int e) {
+        if (status == MBP_OK) status = e;
+    };
+
+    // prologue of every problem, then the checks that need the host
+    int S = std::min(std::max(1, tune.streams), std::min(count, kMaxStreams));
+    fork(s, S);
+    for (int i = 0; i < count; ++i) ctx_prologue(cx[i], st[i % S]);
+    join(s, S);
+    if (hipStreamSynchronize(s) != hipSuccess) fail(MBP_ERR_HIP);
+    for (int i = 0; i < count && status == MBP_OK; ++i) ctx_check(cx[i]);
+
+    // problems whose whole hierarchy fits in LDS: one launch each; the
+    // others run their first cycle (from zero) eagerly
+    if (status == MBP_OK) {
+        fork(s, S);
+        for (int i = 0; i < count; ++i) {
+            SolveCtx& c = cx[i];
+            if (c.done) continue;
+            if (c.full_lds) {
+                mbp_plan* P = c.P;
+                launch_lds_full(P, P->phat, P->fhat, P->d_act, P->d_nact, P->g.nz, P->opt.max_cycles, c.rtol2,
+                                c.etol2, P->d_cyc, P->d_rnorm, P->d_fnorm, st[i % S]);
+                c.done = true;
+                continue;
+            }
+            ctx_test(c, st[i % S]);
+            ctx_vcycle(c, st[i % S]);
+        }
+        join(s, S);
+    }
+
+    // captured cycles, replayed until every problem is done
+    Graph G;
+    size_t trial = 0;
+    BatchTune cur = trials.empty() ? tune : trials[0];
+    double best_cost = 1e300;
+    BatchTune best = cur;
+    while (status == MBP_OK) {
+        std::vector<int> act;
+        long long modes = 0;
+        for (int i = 0; i < count; ++i)
+            if (!cx[i].done) {
+                act.push_back(i);
+                modes += cx[i].nitems;
+            }
+        if (act.empty()) break;
+        const bool retune = trial < trials.size();
+        if (retune) cur = trials[trial];
+        const int Sc = std::min(std::max(1, cur.streams), std::min(int(act.size()), kMaxStreams));
+        bool recapture = G.e == nullptr || retune || act.size() < G.members.size() ||
+                         modes * 4 < G.modes * 3;
+        if (recapture) {
+            G.reset();
+            if (hipStreamBeginCapture(st[0], hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                fail(MBP_ERR_HIP);
+                break;
+            }
+            fork(st[0], Sc);
+            for (int it = 0; it < cur.chunk; ++it)
+                for (size_t a = 0; a < act.size(); ++a) {
+                    SolveCtx& c = cx[act[a]];
+                    ctx_test(c, st[a % Sc]);
+                    ctx_vcycle(c, st[a % Sc]);
+                }
+            join(st[0], Sc);
+            if (hipStreamEndCapture(st[0], &G.g) != hipSuccess ||
+                hipGraphInstantiate(&G.e, G.g, nullptr, nullptr, 0) != hipSuccess) {
+                (void)hipGetLastError();
+                G.reset();
+                fail(MBP_ERR_HIP);
+                break;
+            }
+            G.members = act;
+            G.modes = modes;
+        }
+        (void)hipEventRecord(t0, s);
+        if (hipGraphLaunch(G.e, s) != hipSuccess) {
+            fail(MBP_ERR_HIP);
+            break;
+        }
+        (void)hipEventRecord(t1, s);
+        for (int i : act) ctx_state_readback(cx[i], s);
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            fail(MBP_ERR_HIP);
+            break;
+        }
+        if (retune) {
+            // cost per active mode-cell and cycle of this replay
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, t0, t1);
+            double work = 0.0;
+            for (int i : act) work += double(cx[i].nitems) * double(cx[i].P->plane0);
+            const double cost = ms / std::max(1.0, work * cur.chunk);
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = cur;
+            }
+            if (++trial == trials.size()) {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                g_tune[sig] = best;
+                tune = best;
+                cur = best;
+                G.reset();
+            }
+        }
+        for (int i : act) ctx_state_apply(cx[i]);
+    }
+    G.reset();
+    if (trial > 0 && trial < trials.size()) {
+        // the batch finished before every candidate ran: keep the best seen
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[sig] = best;
+    }
+
+    // epilogue and results
+    fork(s, S);
+    for (int i = 0; i < count; ++i) ctx_epilogue(cx[i], st[i % S]);
+    join(s, S);
+    for (int i = 0; i < count; ++i) {
+        const int r = ctx_info(cx[i], s, infos ? &infos[i] : nullptr);
+        if (r != MBP_OK) fail(r);
+        else if (cx[i].status != MBP_OK) fail(cx[i].status);
+    }
+    for (int k = 0; k < kMaxStreams; ++k) {
+        (void)hipStreamDestroy(st[k]);
+        (void)hipEventDestroy(ev_join[k]);
+    }
+    (void)hipEventDestroy(ev_fork);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    return status;
+}
+
+// Schedule chosen for a batch signature (for reports and tests).
+int batch_tuning(mbp_plan* const* plans, int count, int* streams, int* chunk) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(batch_signature(plans, count));
+    if (it == g_tune.end()) return MBP_PENDING;
+    *streams = it->second.streams;
+    *chunk = it->second.chunk;
+    return MBP_OK;
 }
 
 }  // namespace mbp
-
-extern "C" {
-int mbp_server_create(size_t, int, const mbp_options*, mbp_server**) { return MBP_ERR_INVALID; }
-int mbp_server_submit(mbp_server*, const mbp_block_desc*, int, const mbp_synth_desc*, const double*,
-                      double*, double, int, uint64_t*) { return MBP_ERR_INVALID; }
-int mbp_server_poll(mbp_server*, uint64_t, mbp_solve_info*, double*) { return MBP_ERR_INVALID; }
-int mbp_server_wait(mbp_server*, uint64_t, mbp_solve_info*, double*) { return MBP_ERR_INVALID; }
-void mbp_server_destroy(mbp_server*) {}
-}

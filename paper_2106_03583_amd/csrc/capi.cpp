@@ -11,6 +11,7 @@ namespace mbp {
 void launch_fill_int(int* p, int n, int v, hipStream_t s);
 int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const* p, int count,
                 double rtol, int flags, hipStream_t s, mbp_solve_info* infos);
+int batch_tuning(mbp_plan* const* plans, int count, int* streams, int* chunk);
 }
 
 extern "C" {
@@ -117,8 +118,12 @@ int mbp_solve(mbp_plan* plan, const double* rhs_dev, double* p_dev, double rtol,
 int mbp_solve_batch(mbp_plan* const* plans, const double* const* rhs_dev, double* const* p_dev,
                     int count, double rtol, int flags, void* stream, mbp_solve_info* infos) {
     if (!plans || !rhs_dev || !p_dev || count < 1 || !(rtol > 0.0)) return MBP_ERR_INVALID;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return MBP_ERR_HIP;
     for (int i = 0; i < count; ++i) {
-        if (!plans[i] || !rhs_dev[i] || !p_dev[i] || plans[i]->busy) return MBP_ERR_INVALID;
+        if (!plans[i] || !rhs_dev[i] || !p_dev[i] || rhs_dev[i] == p_dev[i]) return MBP_ERR_INVALID;
+        if (plans[i]->busy) return MBP_ERR_BUSY;
+        if (plans[i]->device != dev) return MBP_ERR_INVALID;
         for (int k = 0; k < i; ++k)
             if (plans[k] == plans[i]) return MBP_ERR_INVALID;
     }
@@ -127,6 +132,13 @@ int mbp_solve_batch(mbp_plan* const* plans, const double* const* rhs_dev, double
                          infos);
     for (int i = 0; i < count; ++i) plans[i]->busy = false;
     return st;
+}
+
+int mbp_batch_schedule(mbp_plan* const* plans, int count, int* streams, int* cycles_per_replay) {
+    if (!plans || count < 1 || !streams || !cycles_per_replay) return MBP_ERR_INVALID;
+    for (int i = 0; i < count; ++i)
+        if (!plans[i]) return MBP_ERR_INVALID;
+    return batch_tuning(plans, count, streams, cycles_per_replay);
 }
 
 int mbp_forward_transform(mbp_plan* plan, const double* f_dev, double* fhat_dev, void* stream) {

@@ -183,13 +183,20 @@ void launch_apply3d(const mbp_plan* P, const double* p, double* out, hipStream_t
 // One V-cycle on every active mode.  p0 / f0: finest-level iterate and rhs;
 // p0B: second finest buffer for the out-of-place sweeps (the result is
 // always left in p0).  With norm0 the finest post-smoothing sweep also
-// produces per-strip squared residuals; returns the strip count then (0 if
-// the caller must evaluate the residual itself).
+// produces per-strip squared residuals; returns the partial count then (0 if
+// the caller must evaluate the residual itself).  zero0: p0 holds zeros
+// (the first cycle), so the fused finest sweeps need not read it.
 template <typename T>
 int launch_vcycle(const mbp_plan* P, T* p0, T* p0B, T* f0, const int* act, const int* nact,
-                  int nitems, bool norm0, hipStream_t s);
+                  int nitems, bool norm0, bool zero0, hipStream_t s);
 void launch_finish(const mbp_plan* P, int nparts, double* out, const int* act, const int* nact,
                    int nitems, hipStream_t s);
+// Whole solve of every mode for plans whose hierarchy fits in LDS.
+void launch_lds_full(const mbp_plan* P, double* p, const double* f, const int* act, const int* nact,
+                     int nitems, int maxc, double rtol2, double etol2, int* cyc, double* rnorm,
+                     double* fnorm, hipStream_t s);
+// First cycle from a zero guess: residual norms are the rhs norms.
+void launch_norm_from_rhs(const mbp_plan* P, int nitems, hipStream_t s);
 
 // kernel timing helpers (solve.cpp)
 void prof_begin(const mbp_plan* P, int cls, hipStream_t s, double cells);
@@ -201,10 +208,10 @@ bool march_level_ok(const mbp_plan* P, int l);
 void march_build_tiles_bytes(const mbp_plan* P, int l, int seg, std::vector<unsigned char>& out, int* count);
 template <typename T>
 void march_pre(const mbp_plan* P, int l, const T* pold, T* pnew, const T* f, T* fc, T* pc,
-               const int* act, const int* nact, int nitems, hipStream_t s);
+               const int* act, const int* nact, int nitems, bool zero_in, hipStream_t s);
 template <typename T>
 void march_sweep(const mbp_plan* P, int l, const T* pold, T* pnew, const T* f, const int* act,
-                 const int* nact, int nitems, hipStream_t s);
+                 const int* nact, int nitems, bool zero_in, hipStream_t s);
 template <typename T>
 void march_post(const mbp_plan* P, int l, const T* pold, T* pnew, const T* f, const T* ec, bool norm,
                 const int* act, const int* nact, int nitems, hipStream_t s);
@@ -216,7 +223,7 @@ void launch_residual_to32(const mbp_plan* P, const double* p, const double* f, f
 void launch_add_correction(const mbp_plan* P, double* p, const float* e32, const int* act,
                            const int* nact, int nitems, hipStream_t s);
 void launch_plane_norm(const mbp_plan* P, const double* f, double* out, hipStream_t s);
-void launch_update_active(const mbp_plan* P, double rtol2, double etol2, int retire, int cycle,
+void launch_update_active(const mbp_plan* P, double rtol2, double etol2, int retire, int maxc,
                           hipStream_t s);
 void launch_zero(double* p, size_t n, hipStream_t s);
 void launch_zero32(float* p, size_t n, hipStream_t s);
@@ -228,5 +235,31 @@ int plan_device_init(mbp_plan* P);
 void plan_device_free(mbp_plan* P);
 int solve_one(mbp_plan* P, const double* rhs, double* p, double rtol, int flags, hipStream_t s,
               mbp_solve_info* info);
+
+// One solve in flight: the stages of Algorithm 1 shared by the single and
+// the batched forms.
+struct SolveCtx {
+    mbp_plan* P = nullptr;
+    const double* rhs = nullptr;
+    double* p = nullptr;
+    double rtol2 = 0.0, etol2 = 0.0;
+    int flags = 0;
+    bool mixed = false, retire = false, warm = false, full_lds = false;
+    int status = 0;
+    double removed = 0.0;
+    int nitems = 0;       // host upper bound on the active modes (grid sizes)
+    int fused_parts = 0;  // partials left by the last V-cycle (0: explicit residual)
+    int cycles = 0;       // V-cycles launched so far
+    bool done = false;
+};
+void ctx_init(SolveCtx& c, mbp_plan* P, const double* rhs, double* p, double rtol, int flags);
+void ctx_prologue(SolveCtx& c, hipStream_t s);  // ends with an async readback of the checks
+void ctx_check(SolveCtx& c);                    // after that readback synchronised
+void ctx_test(SolveCtx& c, hipStream_t s);      // residual norms + convergence update
+void ctx_vcycle(SolveCtx& c, hipStream_t s);    // one V-cycle of the active modes
+void ctx_state_readback(SolveCtx& c, hipStream_t s);
+void ctx_state_apply(SolveCtx& c);              // after that readback synchronised
+void ctx_epilogue(SolveCtx& c, hipStream_t s);
+int ctx_info(SolveCtx& c, hipStream_t s, mbp_solve_info* info);  // synchronises s
 
 }  // namespace mbp

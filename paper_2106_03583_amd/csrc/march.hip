@@ -1,19 +1,20 @@
 // Fused one-pass smoothing kernels for the global-memory multigrid levels.
 //
-// One wave owns a strip of up to 58 output columns of one block and marches
-// down its rows, keeping a five-row register window.  Each step loads one
-// row, relaxes the red cells of the row above it and the black cells of the
-// row above that, so a whole red-black Gauss-Seidel sweep costs one read of
-// p and f and one write of p.  Lanes 0-2 and 61-63 (and three rows above and
-// below the strip) are halo: they are relaxed too, from the same old values
-// the owning strip sees, so every strip reproduces the sweep exactly.  The
-// sweep is out of place (old -> new buffer), which keeps the halo reads free
-// of races between strips.  Optional fusions:
-//   PRO  add the bilinear coarse-grid correction to every row as it loads
-//        (prolongation + correction before the post-smoothing sweep);
-//   RES  residual of the smoothed rows, area-weighted, summed into the coarse
-//        rhs of the next level (pre-smoothing sweep + restriction);
-//   NRM  per-strip sum of the squared residual (convergence test).
+// A workgroup owns a strip of one block: up to 58 output columns and 22
+// output rows, held in LDS with three halo columns and rows on every side
+// (rows and columns of neighbouring blocks across joined faces).  One
+// launch runs a whole red-black Gauss-Seidel sweep out of place (old -> new
+// buffer), so a sweep costs one read of p and f and one write of p; the halo
+// cells are relaxed too, from the same old values the owning strip sees, so
+// every strip reproduces the global sweep exactly.  Optional fusions:
+//   PRO  add the bilinear coarse-grid correction before the sweep
+//        (prolongation + correction + post-smoothing);
+//   RES  residual of the smoothed cells, area-weighted and summed into the
+//        coarse rhs of the next level (pre-smoothing + restriction);
+//   NRM  per-wave sums of the squared residual and solution (convergence).
+// A workgroup runs several modes of its strip in turn, issuing the loads of
+// the next mode before relaxing the current one.
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -51,7 +52,11 @@ struct MArgs {
     const int* act;
     const int* nact;
     double* part;      // NRM: per (mode, tile) partial sums
+    int per;           // modes per workgroup (consecutive active items)
+    int zero_in;       // the old iterate is zero: pold is not read
 };
+
+constexpr int kMaxModes = 8;  // most modes one workgroup runs in turn
 
 __device__ __forceinline__ int xcd_remap_m(int g, int n) {
     int x = g & 7, l = g >> 3;
@@ -110,9 +115,15 @@ __device__ __forceinline__ T correction(const DBlock* __restrict__ B, const DBlo
     const DBlock& d = B[fb];
     const int cx = ip[d.pcx + ci], cy = ip[d.pcy + cj];
     const T wx = T(dp[d.pwx + ci]), wy = T(dp[d.pwy + cj]);
-    const T e00 = coarse_at(ecq, Bc, fb, cx, cy), e10 = coarse_at(ecq, Bc, fb, cx + 1, cy);
-    const T e01 = coarse_at(ecq, Bc, fb, cx, cy + 1), e11 = coarse_at(ecq, Bc, fb, cx + 1, cy + 1);
-    return wy * (wx * e00 + (T(1) - wx) * e10) + (T(1) - wy) * (wx * e01 + (T(1) - wx) * e11);
+    // one corner at a time: this path is rare and must stay light on registers
+    T acc = T(0);
+#pragma unroll 1
+    for (int corner = 0; corner < 4; ++corner) {
+        const int dx = corner & 1, dy = corner >> 1;
+        const T w = (dx ? T(1) - wx : wx) * (dy ? T(1) - wy : wy);
+        acc += w * coarse_at(ecq, Bc, fb, cx + dx, cy + dy);
+    }
+    return acc;
 }
 
 // Compile-time loop: the body gets a constant index, so per-thread arrays
@@ -126,12 +137,43 @@ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 // ------------------------- LDS tile form of the sweep -------------------------
-// Same sweep, same strips, but a workgroup loads its whole strip (rows y0-3 ..
-// y1+2, 64 columns) into LDS in one burst, then relaxes red, black, computes
-// the residual and restricts it with barriers between the phases.  Bulk loads
-// keep many requests in flight, which the row march cannot do in float64.
-constexpr int kTileRows = 30;               // output rows per strip (host cuts at this)
+// A workgroup owns one strip (rows y0-3 .. y1+2, 64 columns) and runs the
+// sweep for up to kMaxModes modes of it in turn.  The strip geometry (row
+// and lane tables) is set up once; the loads of the next mode (p, f and the
+// coarse correction rows) are issued before the current mode is relaxed, so
+// they are in flight during its compute.  p and f are staged in LDS.  Phases per mode: stage p (+ correction), red, black, store with the
+// residual, restriction / norm.
+constexpr int kTileRows = 22;               // output rows per strip (host cuts at this)
 constexpr int kLdsRows = kTileRows + 6;
+constexpr int kRowsPerWave = kLdsRows / 4;  // contiguous rows per wave
+constexpr int kCoarseRows = 16;             // coarse rows of the correction staged per strip
+static_assert(kLdsRows % 4 == 0, "four waves share the strip rows");
+static_assert(kCoarseRows % 4 == 0, "four waves share the coarse rows");
+constexpr int kNoRow = -1000000;            // row table: not a row of the strip's own block
+
+// Offset and sign of coarse value (I, J) of block b, one cell beyond a face
+// allowed: y first (neighbour or mirror), then x, as coarse_at reads it.
+template <typename T>
+__device__ __forceinline__ int coarse_addr(const DBlock* __restrict__ B, int b, int I, int J, T& sign) {
+    T s = T(1);
+    const DBlock* bb = &B[b];
+    if (J < 0) {
+        if (bb->nbr[YM] >= 0) { bb = &B[bb->nbr[YM]]; J = bb->ny - 1; }
+        else { if (bb->bc[YM] == MBP_DIRICHLET) s = -s; J = 0; }
+    } else if (J >= bb->ny) {
+        if (bb->nbr[YP] >= 0) { bb = &B[bb->nbr[YP]]; J = 0; }
+        else { if (bb->bc[YP] == MBP_DIRICHLET) s = -s; J = bb->ny - 1; }
+    }
+    if (I < 0) {
+        if (bb->nbr[XM] >= 0) { bb = &B[bb->nbr[XM]]; I = bb->nx - 1; }
+        else { if (bb->bc[XM] == MBP_DIRICHLET) s = -s; I = 0; }
+    } else if (I >= bb->nx) {
+        if (bb->nbr[XP] >= 0) { bb = &B[bb->nbr[XP]]; I = 0; }
+        else { if (bb->bc[XP] == MBP_DIRICHLET) s = -s; I = bb->nx - 1; }
+    }
+    sign = s;
+    return bb->off + J * bb->nx + I;
+}
 
 // Block met at (column region cr, virtual row k) of a strip of block tb:
 // column region 0 = left halo, 1 = the block, 2 = right halo.  Beyond a
@@ -149,48 +191,70 @@ __device__ __forceinline__ int block_at(const DBlock* __restrict__ B, int tb, in
     return -1;
 }
 
-template <typename T>
-__device__ __forceinline__ T xcoef(const DBlock* __restrict__ B, const double* __restrict__ dp, int blk,
-                                   int cc, int which) {
-    return blk >= 0 ? T(dp[B[blk].cx + which * B[blk].nx + cc]) : T(0);
-}
-
 template <typename T, bool PRO, bool RES, bool NRM>
-__global__ void __launch_bounds__(256) k_tile(const MArgs<T> args) {
+__device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
     // argument fields as scalars (no reference to the argument block survives)
     const DBlock* __restrict__ aB = args.B;
     const DBlock* __restrict__ aBc = args.Bc;
     const int* __restrict__ aip = args.ip;
     const double* __restrict__ dp = args.dp;
     const int ntiles = args.ntiles;
+    const int per = args.per;
     const long long plane = args.plane, plane_c = args.plane_c;
+    const T* __restrict__ pold = args.pold;
+    T* __restrict__ pnew = args.pnew;
+    const T* __restrict__ fsrc = args.f;
+    const T* __restrict__ ec = args.ec;
 
     __shared__ T sp[kLdsRows][64];
     __shared__ T sf[kLdsRows][64];
-    __shared__ double sy[kLdsRows][3][3];  // per row and column region: wm, wp, dy
-    __shared__ int scol[kLdsRows][3];      // (row index + parity) & 1, or -1: no cell
-    __shared__ double sred[4][2];
+    __shared__ T sE[PRO ? kCoarseRows : 1][64];  // x-interpolated coarse correction per lane
+    __shared__ double sy[kLdsRows][3][3];        // per row and column region: wm, wp, dy
+    __shared__ int scol[kLdsRows][3];            // (row index + parity) & 1, or -1: no cell
+    __shared__ int scy[kLdsRows];                // PRO: coarse lower row of inside rows, kNoRow else
+    __shared__ double swy[kLdsRows];             // PRO: weight of that row; RES: row restriction weight
+    __shared__ int sgo[PRO ? 6 : 1][64];         // PRO: coarse column A, B offsets: ghost row below,
+    __shared__ T sgw[PRO ? 6 : 1][64];           //      ghost row above, inside rows; weights with signs
+    __shared__ T sxc[2][3][64];                  // x coefficients of the halo rows below / above
+    __shared__ int sq[kMaxModes];
+    __shared__ double ssig[kMaxModes];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tix = xcd_remap_m(blockIdx.x, ntiles);
-    const int item = blockIdx.y;
-    if (item >= *args.nact) return;
-    const int q = args.act[item];
+    const int nact = *args.nact;
+    const int i0 = blockIdx.y * per;
+    const int i1 = min(i0 + per, nact);
+    if (i0 >= i1) return;
     const MTile& t = args.tiles[tix];
     const int tb = t.b, tx0 = t.x0, tw = t.w, ty0 = t.y0, ty1 = t.y1;
     const int bnx = t.bnx, bny = t.bny;
     const int nrow = ty1 - ty0 + 6;
-    const T sig = T(args.shift[q]);
-    const T* __restrict__ po = args.pold + q * plane;
-    T* __restrict__ pn = args.pnew + q * plane;
-    const T* __restrict__ fq = args.f + q * plane;
-    const T* __restrict__ ecq = PRO ? args.ec + q * plane_c : nullptr;
 
-    // ---- phase 0: per-row coefficient table ----
+    // ---- strip tables (once per workgroup) ----
+    if (threadIdx.x < i1 - i0) {
+        const int q = args.act[i0 + threadIdx.x];
+        sq[threadIdx.x] = q;
+        ssig[threadIdx.x] = args.shift[q];
+    }
+    int ncyc = 0, bpcy = 0, bpwy = 0;
+    if (PRO) {
+        ncyc = aBc[tb].ny;
+        bpcy = aB[tb].pcy;
+        bpwy = aB[tb].pwy;
+    }
+    const int rwy = RES ? aB[tb].rwy : 0;
     for (int e = threadIdx.x; e < 3 * nrow; e += blockDim.x) {
         const int r = e / 3, cr = e - 3 * r;
         const int k = ty0 - 3 + r;
         const int rr = k < 0 ? 0 : (k >= bny ? 2 : 1);
+        if (cr == 1) {
+            if (PRO) {
+                scy[r] = rr == 1 ? aip[bpcy + k] : kNoRow;
+                swy[r] = rr == 1 ? dp[bpwy + k] : 0.0;
+            } else if (RES) {
+                swy[r] = rr == 1 ? dp[rwy + k] : 0.0;
+            }
+        }
         const int blk = pick3(rr, pick3(cr, t.blk[0][0], t.blk[0][1], t.blk[0][2]),
                               pick3(cr, t.blk[1][0], t.blk[1][1], t.blk[1][2]),
                               pick3(cr, t.blk[2][0], t.blk[2][1], t.blk[2][2]));
@@ -240,176 +304,281 @@ __global__ void __launch_bounds__(256) k_tile(const MArgs<T> args) {
     // x coefficients per row region (lane constants)
     const T xwm0 = b0 >= 0 ? T(dp[cx0 + ci]) : T(0), xwp0 = b0 >= 0 ? T(dp[cx0 + nx0 + ci]) : T(0);
     const T xd0 = b0 >= 0 ? T(dp[cx0 + 2 * nx0 + ci]) : T(0);
-    const T xwmm = bm >= 0 ? T(dp[cxm + cim]) : T(0), xwpm = bm >= 0 ? T(dp[cxm + nxm + cim]) : T(0);
-    const T xdm = bm >= 0 ? T(dp[cxm + 2 * nxm + cim]) : T(0);
-    const T xwmp = bp >= 0 ? T(dp[cxp + cip]) : T(0), xwpp = bp >= 0 ? T(dp[cxp + nxp + cip]) : T(0);
-    const T xdp = bp >= 0 ? T(dp[cxp + 2 * nxp + cip]) : T(0);
+    if (wave == 0) {
+        sxc[0][0][lane] = bm >= 0 ? T(dp[cxm + cim]) : T(0);
+        sxc[0][1][lane] = bm >= 0 ? T(dp[cxm + nxm + cim]) : T(0);
+        sxc[0][2][lane] = bm >= 0 ? T(dp[cxm + 2 * nxm + cim]) : T(0);
+        sxc[1][0][lane] = bp >= 0 ? T(dp[cxp + cip]) : T(0);
+        sxc[1][1][lane] = bp >= 0 ? T(dp[cxp + nxp + cip]) : T(0);
+        sxc[1][2][lane] = bp >= 0 ? T(dp[cxp + 2 * nxp + cip]) : T(0);
+    }
+
+    // the wave's rows: offsets inside the plane and which of them hold a cell
+    const int rbase = wave * kRowsPerWave;
+    int roff[kRowsPerWave];
+    unsigned amask = 0;
+#pragma unroll
+    for (int m = 0; m < kRowsPerWave; ++m) {
+        const int r = rbase + m;
+        const int k = ty0 - 3 + r;
+        const bool below = k < 0, above = k >= bny;
+        const bool alive = r < nrow && (below ? bm >= 0 : (above ? bp >= 0 : b0 >= 0));
+        roff[m] = !alive ? 0 : (below ? offm + (nym + k) * nxm : (above ? offp + (k - bny) * nxp : off0 + k * nx0));
+        amask |= alive ? (1u << m) : 0u;
+    }
 
     // coarse columns of the correction for inside rows (resolved per lane)
-    int cbaseA = 0, cbaseB = 0, cstrA = 0, cstrB = 0, ncyc = 0, bpcy = 0, bpwy = 0;
-    T csA = T(0), csB = T(0), cwx = T(0);
-    if (PRO) {
-        ncyc = aBc[tb].ny;
-        bpcy = aB[tb].pcy;
-        bpwy = aB[tb].pwy;
-        if (b0 >= 0) {
-            const int cx = aip[aB[b0].pcx + ci];
-            cwx = T(dp[aB[b0].pwx + ci]);
-            int I = cx;
-            for (int s = 0; s < 2; ++s, ++I) {
-                int cb = b0, II = I;
-                T sg = T(1);
-                if (II < 0) {
-                    if (aBc[cb].nbr[XM] >= 0) { cb = aBc[cb].nbr[XM]; II = aBc[cb].nx - 1; }
-                    else { if (aBc[cb].bc[XM] == MBP_DIRICHLET) sg = T(-1); II = 0; }
-                } else if (II >= aBc[cb].nx) {
-                    if (aBc[cb].nbr[XP] >= 0) { cb = aBc[cb].nbr[XP]; II = 0; }
-                    else { if (aBc[cb].bc[XP] == MBP_DIRICHLET) sg = T(-1); II = aBc[cb].nx - 1; }
-                }
-                if (s == 0) { cbaseA = aBc[cb].off + II; cstrA = aBc[cb].nx; csA = sg; }
-                else { cbaseB = aBc[cb].off + II; cstrB = aBc[cb].nx; csB = sg; }
+    int cstrA = 0, cstrB = 0;
+    if (PRO && b0 >= 0) {
+        const int cx = aip[aB[b0].pcx + ci];
+        const T cwx = T(dp[aB[b0].pwx + ci]);
+        int I = cx;
+        for (int s = 0; s < 2; ++s, ++I) {
+            int cb = b0, II = I;
+            T sg = T(1);
+            if (II < 0) {
+                if (aBc[cb].nbr[XM] >= 0) { cb = aBc[cb].nbr[XM]; II = aBc[cb].nx - 1; }
+                else { if (aBc[cb].bc[XM] == MBP_DIRICHLET) sg = T(-1); II = 0; }
+            } else if (II >= aBc[cb].nx) {
+                if (aBc[cb].nbr[XP] >= 0) { cb = aBc[cb].nbr[XP]; II = 0; }
+                else { if (aBc[cb].bc[XP] == MBP_DIRICHLET) sg = T(-1); II = aBc[cb].nx - 1; }
+            }
+            if (s == 0) { cstrA = aBc[cb].nx; }
+            else { cstrB = aBc[cb].nx; }
+            if (wave == 2) {
+                sgo[4 + s][lane] = aBc[cb].off + II;
+                sgw[4 + s][lane] = sg * (s == 0 ? cwx : T(1) - cwx);
             }
         }
-    }
-
-    // ---- phase 1: load p and f of every held row.  All loads of the strip
-    //      are issued first (constant trip count, values in registers), then
-    //      written to LDS, so they overlap in flight. ----
-    constexpr int NR = (kLdsRows + 3) / 4;
-    T lp[NR], lf[NR];
-#pragma unroll
-    for (int rr = 0; rr < NR; ++rr) {
-        const int r = wave + 4 * rr;
-        const int k = ty0 - 3 + r;
-        lp[rr] = T(0);
-        lf[rr] = T(0);
-        if (r >= nrow) continue;
-        const bool below = k < 0, above = k >= bny;
-        const bool alive = below ? bm >= 0 : (above ? bp >= 0 : b0 >= 0);
-        if (!alive) continue;
-        const int o = below ? offm + (nym + k) * nxm : (above ? offp + (k - bny) * nxp : off0 + k * nx0);
-        lp[rr] = po[o];
-        lf[rr] = fq[o];
-    }
-#pragma unroll
-    for (int rr = 0; rr < NR; ++rr) {
-        const int r = wave + 4 * rr;
-        if (r >= nrow) continue;
-        sp[r][lane] = lp[rr];
-        sf[r][lane] = lf[rr];
-    }
-    // coarse-grid correction of the held rows (bilinear, physical weights)
-    if (PRO) {
-#pragma unroll 3
-        for (int rr = 0; rr < NR; ++rr) {
-            const int r = wave + 4 * rr;
-            if (r >= nrow) continue;
-            const int k = ty0 - 3 + r;
-            const bool below = k < 0, above = k >= bny;
-            const bool alive = below ? bm >= 0 : (above ? bp >= 0 : b0 >= 0);
-            if (!alive) continue;
-            T corr;
-            const int cy = (!below && !above) ? aip[bpcy + k] : -1;
-            if (!below && !above && cy >= 0 && cy + 1 < ncyc) {
-                const T wy = T(dp[bpwy + k]);
-                corr = wy * (cwx * csA * ecq[cbaseA + cy * cstrA] + (T(1) - cwx) * csB * ecq[cbaseB + cy * cstrB]) +
-                       (T(1) - wy) * (cwx * csA * ecq[cbaseA + (cy + 1) * cstrA] +
-                                      (T(1) - cwx) * csB * ecq[cbaseB + (cy + 1) * cstrB]);
-            } else if (below) {
-                corr = correction(aB, aBc, aip, dp, ecq, bm, cim, nym + k);
-            } else if (above) {
-                corr = correction(aB, aBc, aip, dp, ecq, bp, cip, k - bny);
-            } else {
-                corr = correction(aB, aBc, aip, dp, ecq, b0, ci, k);
-            }
-            sp[r][lane] += corr;
+        // ghost coarse rows below (J = -1) and above (J = ncyc), resolved from
+        // this lane's block the same way as the cell-by-cell correction
+        if (wave < 2) {
+            const int J = wave == 0 ? -1 : ncyc;
+            T sa, sb;
+            const int oa = coarse_addr(aBc, b0, cx, J, sa);
+            const int ob = coarse_addr(aBc, b0, cx + 1, J, sb);
+            sgo[2 * wave][lane] = oa;
+            sgo[2 * wave + 1][lane] = ob;
+            sgw[2 * wave][lane] = sa * cwx;
+            sgw[2 * wave + 1][lane] = sb * (T(1) - cwx);
         }
+    } else if (PRO && wave < 3) {
+        sgo[2 * wave][lane] = sgo[2 * wave + 1][lane] = 0;
+        sgw[2 * wave][lane] = sgw[2 * wave + 1][lane] = T(0);
     }
-    __syncthreads();
-
-    // ---- phases 2 and 3: red on rows 1 .. nrow-2 / lanes 1 .. 62, then black
-    //      on rows 2 .. nrow-3 / lanes 2 .. 61 (the valid region shrinks) ----
-    for (int colour = 0; colour < 2; ++colour) {
-        if (lane >= 1 + colour && lane <= 62 - colour) {
-            for (int r = wave; r < nrow; r += 4) {
-                if (r < 1 + colour || r > nrow - 2 - colour) continue;
-                const int k = ty0 - 3 + r;
-                const int sc = scol[r][cr];
-                const bool below = k < 0, above = k >= bny;
-                const bool alive = below ? bm >= 0 : (above ? bp >= 0 : b0 >= 0);
-                if (sc < 0 || !alive) continue;
-                const int cc = below ? cim : (above ? cip : ci);
-                if (((cc + sc) & 1) != colour) continue;
-                const T wm = below ? xwmm : (above ? xwmp : xwm0);
-                const T wp = below ? xwpm : (above ? xwpp : xwp0);
-                const T xd = below ? xdm : (above ? xdp : xd0);
-                const T d = xd + T(sy[r][cr][2]) + sig;
-                const T off = wm * sp[r][lane - 1] + wp * sp[r][lane + 1] + T(sy[r][cr][0]) * sp[r - 1][lane] +
-                              T(sy[r][cr][1]) * sp[r + 1][lane];
-                sp[r][lane] = (sf[r][lane] - off) / d;
-            }
-        }
-        __syncthreads();
-    }
-    // ---- phase 4: store, residual (weighted residual kept in sf for the restriction) ----
     const bool out_lane = lane >= 3 && lane < 3 + tw;
     const T wrx = (RES && out_lane) ? T(dp[aB[tb].rwx + c]) : T(0);
-    const int rwy = aB[tb].rwy;
-    double nrm = 0.0, pnr = 0.0;
-    for (int r = wave; r < nrow; r += 4) {
-        const int k = ty0 - 3 + r;
-        const bool own = r >= 3 && k < ty1 && out_lane;
-        if (own) {
-            const T pc = sp[r][lane];
-            pn[off0 + k * nx0] = pc;
-            if (RES || NRM) {
-                const T d = xd0 + T(sy[r][1][2]) + sig;
-                const T res = sf[r][lane] - (xwm0 * sp[r][lane - 1] + xwp0 * sp[r][lane + 1] +
-                                             T(sy[r][1][0]) * sp[r - 1][lane] + T(sy[r][1][1]) * sp[r + 1][lane] + d * pc);
-                if (NRM) {
-                    nrm += double(res) * double(res);
-                    pnr += double(pc) * double(pc);
-                }
-                if (RES) sf[r][lane] = res * wrx * T(dp[rwy + k]);
+
+    // ---- loads of one mode: p and f of the wave's rows, coarse rows ----
+    T lp[kRowsPerWave], lf[kRowsPerWave];
+    T leA[kCoarseRows / 4], leB[kCoarseRows / 4];
+    const bool zin = args.zero_in != 0;
+    auto issue_pf = [&](int q) __attribute__((always_inline)) {
+        const T* __restrict__ fq = fsrc + q * plane;
+#pragma unroll
+        for (int m = 0; m < kRowsPerWave; ++m) {
+            lp[m] = T(0);
+            lf[m] = T(0);
+            if ((amask >> m) & 1u) {
+                if (!zin) lp[m] = pold[q * plane + roff[m]];
+                lf[m] = fq[roff[m]];
             }
-        } else if (RES) {
-            sf[r][lane] = T(0);
         }
+    };
+    auto issue_e = [&](int q, int cyb) __attribute__((always_inline)) {
+        const T* __restrict__ ecq = ec + q * plane_c;
+#pragma unroll
+        for (int m = 0; m < kCoarseRows / 4; ++m) {
+            const int J = cyb + wave + 4 * m;
+            leA[m] = T(0);
+            leB[m] = T(0);
+            if (b0 >= 0 && J >= 0 && J < ncyc) {
+                leA[m] = ecq[sgo[4][lane] + J * cstrA];
+                leB[m] = ecq[sgo[5][lane] + J * cstrB];
+            } else if (b0 >= 0 && (J == -1 || J == ncyc)) {
+                const int g = J < 0 ? 0 : 2;
+                leA[m] = ecq[sgo[g][lane]];
+                leB[m] = ecq[sgo[g + 1][lane]];
+            }
+        }
+    };
+
+    issue_pf(args.act[i0]);
+    __syncthreads();  // strip tables ready
+    int cyb = kNoRow;  // first coarse row staged for the correction
+    if (PRO) {
+        for (int r = 0; r < nrow; ++r)
+            if (scy[r] != kNoRow) { cyb = scy[r]; break; }
+        issue_e(sq[0], cyb);
     }
-    if (RES) {
+
+    for (int it = i0; it < i1; ++it) {
+        const int q = sq[it - i0];
+        const T sig = T(ssig[it - i0]);
+        // stage this mode
+#pragma unroll
+        for (int m = 0; m < kRowsPerWave; ++m) {
+            if (rbase + m < nrow) {
+                sp[rbase + m][lane] = lp[m];
+                sf[rbase + m][lane] = lf[m];
+            }
+        }
+        if (PRO) {
+#pragma unroll
+            for (int m = 0; m < kCoarseRows / 4; ++m) {
+                const int J = cyb + wave + 4 * m;
+                const int g = J == -1 ? 0 : (J == ncyc ? 2 : 4);
+                sE[wave + 4 * m][lane] = sgw[g][lane] * leA[m] + sgw[g + 1][lane] * leB[m];
+            }
+        }
         __syncthreads();
-        // leaders: first fine column / row of each coarse cell inside the strip
-        const int ncx = aBc[tb].nx, ncy = aBc[tb].ny, bcoff = aBc[tb].off;
-        if (out_lane && c == 2 * min(c >> 1, ncx - 1)) {
-            const int I = min(c >> 1, ncx - 1);
-            const int i1 = (I == ncx - 1) ? bnx : 2 * I + 2;  // exclusive fine end
-            for (int r = wave; r < nrow; r += 4) {
+        // halo rows of other blocks: correction cell by cell, before the next
+        // mode's loads take the registers
+        if (PRO) {
+            const T* __restrict__ ecq = ec + q * plane_c;
+#pragma unroll 1
+            for (int m = 0; m < kRowsPerWave; ++m) {
+                const int r = rbase + m;
+                if (!((amask >> m) & 1u)) continue;
+                const int cy = scy[r];
+                if (cy != kNoRow && cy - cyb + 1 < kCoarseRows) continue;
                 const int k = ty0 - 3 + r;
-                if (r < 3 || k >= ty1) continue;
-                const int J = min(k >> 1, ncy - 1);
-                if (k != 2 * J) continue;
-                const int j1 = (J == ncy - 1) ? bny : 2 * J + 2;
-                T s = T(0);
-                for (int kk = k; kk < j1; ++kk)
-                    for (int x = c; x < i1; ++x) s += sf[r + (kk - k)][lane + (x - c)];
-                const long long o = q * plane_c + bcoff + (long long)J * ncx + I;
-                args.fc[o] = s;
-                args.pc[o] = T(0);
+                T corr;
+                if (k < 0) corr = correction(aB, aBc, aip, dp, ecq, bm, cim, nym + k);
+                else if (k >= bny) corr = correction(aB, aBc, aip, dp, ecq, bp, cip, k - bny);
+                else corr = correction(aB, aBc, aip, dp, ecq, b0, ci, k);
+                sp[r][lane] += corr;
             }
         }
-    }
-    if (NRM) {
-        for (int o = 32; o > 0; o >>= 1) {
-            nrm += __shfl_xor(nrm, o);
-            pnr += __shfl_xor(pnr, o);
+        // the next mode's loads fly during this mode's compute
+        if (it + 1 < i1) {
+            issue_pf(sq[it + 1 - i0]);
+            if (PRO) issue_e(sq[it + 1 - i0], cyb);
         }
-        if (lane == 0) { sred[wave][0] = nrm; sred[wave][1] = pnr; }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            args.part[2 * ((long long)q * ntiles + tix)] = sred[0][0] + sred[1][0] + sred[2][0] + sred[3][0];
-            args.part[2 * ((long long)q * ntiles + tix) + 1] = sred[0][1] + sred[1][1] + sred[2][1] + sred[3][1];
+        // coarse-grid correction of the rows inside the block (bilinear,
+        // physical weights) from the staged coarse rows
+        if (PRO) {
+#pragma unroll
+            for (int m = 0; m < kRowsPerWave; ++m) {
+                const int r = rbase + m;
+                const int cy = scy[r < nrow ? r : 0];
+                if (((amask >> m) & 1u) && r < nrow && cy != kNoRow && cy - cyb + 1 < kCoarseRows) {
+                    const T wy = T(swy[r]);
+                    sp[r][lane] += wy * sE[cy - cyb][lane] + (T(1) - wy) * sE[cy - cyb + 1][lane];
+                }
+            }
+            __syncthreads();
         }
+
+        // red on rows 1 .. nrow-2 / lanes 1 .. 62, then black on rows
+        // 2 .. nrow-3 / lanes 2 .. 61 (the valid region shrinks)
+#pragma unroll
+        for (int colour = 0; colour < 2; ++colour) {
+            if (lane >= 1 + colour && lane <= 62 - colour) {
+#pragma unroll
+                for (int m = 0; m < kRowsPerWave; ++m) {
+                    const int r = rbase + m;
+                    if (!((amask >> m) & 1u) || r < 1 + colour || r > nrow - 2 - colour) continue;
+                    const int k = ty0 - 3 + r;
+                    const int sc = scol[r][cr];
+                    const bool below = k < 0, above = k >= bny;
+                    const int cc = below ? cim : (above ? cip : ci);
+                    if (sc < 0 || ((cc + sc) & 1) != colour) continue;
+                    T wm = xwm0, wp = xwp0, xd = xd0;
+                    if (below || above) {
+                        const int h = below ? 0 : 1;
+                        wm = sxc[h][0][lane];
+                        wp = sxc[h][1][lane];
+                        xd = sxc[h][2][lane];
+                    }
+                    const T d = xd + T(sy[r][cr][2]) + sig;
+                    const T off = wm * sp[r][lane - 1] + wp * sp[r][lane + 1] + T(sy[r][cr][0]) * sp[r - 1][lane] +
+                                  T(sy[r][cr][1]) * sp[r + 1][lane];
+                    sp[r][lane] = (sf[r][lane] - off) / d;
+                }
+            }
+            __syncthreads();
+        }
+
+        // store, residual (weighted for the restriction, squared for the norm)
+        double nrm = 0.0, pnr = 0.0;
+        T wres[kRowsPerWave];
+#pragma unroll
+        for (int m = 0; m < kRowsPerWave; ++m) {
+            const int r = rbase + m;
+            const int k = ty0 - 3 + r;
+            wres[m] = T(0);
+            if (r >= 3 && k < ty1 && out_lane) {
+                const T pc = sp[r][lane];
+                pnew[q * plane + roff[m]] = pc;
+                if (RES || NRM) {
+                    const T d = xd0 + T(sy[r][1][2]) + sig;
+                    const T res = sf[r][lane] - (xwm0 * sp[r][lane - 1] + xwp0 * sp[r][lane + 1] +
+                                           T(sy[r][1][0]) * sp[r - 1][lane] + T(sy[r][1][1]) * sp[r + 1][lane] +
+                                           d * pc);
+                    if (NRM) {
+                        nrm += double(res) * double(res);
+                        pnr += double(pc) * double(pc);
+                    }
+                    if (RES) wres[m] = res * wrx * T(swy[r]);
+                }
+            }
+        }
+        if (NRM) {
+            // one partial pair per wave: no barrier on the way out
+            for (int o = 32; o > 0; o >>= 1) {
+                nrm += __shfl_xor(nrm, o);
+                pnr += __shfl_xor(pnr, o);
+            }
+            if (lane == 0) {
+                const long long o = 2 * (((long long)q * ntiles + tix) * 4 + wave);
+                args.part[o] = nrm;
+                args.part[o + 1] = pnr;
+            }
+        }
+        if (RES) {
+            __syncthreads();  // every residual has read its neighbours
+#pragma unroll
+            for (int m = 0; m < kRowsPerWave; ++m)
+                if (rbase + m < nrow) sp[rbase + m][lane] = wres[m];
+            __syncthreads();
+            // one thread per coarse cell of the strip (the strip owns whole
+            // coarse cells; the last cell of an odd count spans three)
+            const int ncx = aBc[tb].nx, ncy = aBc[tb].ny, bcoff = aBc[tb].off;
+            const int I0 = tx0 >> 1, J0 = ty0 >> 1;
+            const int I1 = (tx0 + tw == bnx) ? ncx : (tx0 + tw) >> 1;
+            const int J1 = (ty1 == bny) ? ncy : ty1 >> 1;
+            const int nI = I1 - I0, ncell = nI * (J1 - J0);
+            for (int e = threadIdx.x; e < ncell; e += blockDim.x) {
+                const int J = J0 + e / nI, I = I0 + e % nI;
+                const int x1 = (I == ncx - 1) ? bnx : 2 * I + 2;
+                const int y1 = (J == ncy - 1) ? bny : 2 * J + 2;
+                const int lx = 2 * I - tx0 + 3, ry = 2 * J - ty0 + 3;
+                T sum = sp[ry][lx] + sp[ry][lx + 1] + sp[ry + 1][lx] + sp[ry + 1][lx + 1];
+                if (x1 - 2 * I == 3) sum += sp[ry][lx + 2] + sp[ry + 1][lx + 2];
+                if (y1 - 2 * J == 3) {
+                    sum += sp[ry + 2][lx] + sp[ry + 2][lx + 1];
+                    if (x1 - 2 * I == 3) sum += sp[ry + 2][lx + 2];
+                }
+                const long long o = q * plane_c + bcoff + (long long)J * ncx + I;
+                args.fc[o] = sum;
+                if (args.pc) args.pc[o] = T(0);
+            }
+        }
+        __syncthreads();  // LDS is restaged by the next mode
     }
+}
+
+// Sweep kernels.  The correction form holds more state per lane; it is
+// capped at three waves per SIMD, the others keep the compiler's choice.
+template <typename T, bool RES, bool NRM>
+__global__ void __launch_bounds__(256) k_tile(const MArgs<T> args) {
+    tile_sweep<T, false, RES, NRM>(args);
+}
+
+template <typename T, bool NRM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_tile_corr(const MArgs<T> args) {
+    tile_sweep<T, true, false, NRM>(args);
 }
 
 // ------------------------------- host side -------------------------------
@@ -537,25 +706,41 @@ static MArgs<T> margs(const mbp_plan* P, int l, const T* pold, T* pnew, const T*
     return a;
 }
 
+// Modes per workgroup: enough workgroups to fill the chip several times
+// over, each reusing its strip set-up for as many modes as that allows.
+static int modes_per_wg(int ntiles, int nitems) {
+    const long long target = 256LL * 12;
+    long long per = (long long)ntiles * nitems / target;
+    return int(std::max(1LL, std::min<long long>(kMaxModes, per)));
+}
+
 template <typename T, bool PRO, bool RES, bool NRM>
-static void launch_march(const MArgs<T>& a, int nitems, hipStream_t s) {
-    hipLaunchKernelGGL((k_tile<T, PRO, RES, NRM>), dim3(a.ntiles, nitems), dim3(256), 0, s, a);
+static void launch_march(MArgs<T> a, int nitems, hipStream_t s) {
+    a.per = modes_per_wg(a.ntiles, nitems);
+    const int groups = (nitems + a.per - 1) / a.per;
+    if constexpr (PRO)
+        hipLaunchKernelGGL((k_tile_corr<T, NRM>), dim3(a.ntiles, groups), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_tile<T, RES, NRM>), dim3(a.ntiles, groups), dim3(256), 0, s, a);
 }
 
 // Pre-smoothing sweep of level l (old -> new) fused with the residual
-// restriction into level l+1 (rhs fc, initial guess pc = 0).
+// restriction into level l+1 (rhs fc; pc, if given, set to the zero initial
+// guess).  zero_in: the old iterate is zero and is not read.
 template <typename T>
 void march_pre(const mbp_plan* P, int l, const T* pold, T* pnew, const T* f, T* fc, T* pc,
-               const int* act, const int* nact, int nitems, hipStream_t s) {
+               const int* act, const int* nact, int nitems, bool zero_in, hipStream_t s) {
     MArgs<T> a = margs<T>(P, l, pold, pnew, f, nullptr, fc, pc, act, nact);
+    a.zero_in = zero_in ? 1 : 0;
     launch_march<T, false, true, false>(a, nitems, s);
 }
 
 // Plain sweep (extra smoothing steps).
 template <typename T>
 void march_sweep(const mbp_plan* P, int l, const T* pold, T* pnew, const T* f, const int* act,
-                 const int* nact, int nitems, hipStream_t s) {
+                 const int* nact, int nitems, bool zero_in, hipStream_t s) {
     MArgs<T> a = margs<T>(P, l, pold, pnew, f, nullptr, nullptr, nullptr, act, nact);
+    a.zero_in = zero_in ? 1 : 0;
     launch_march<T, false, false, false>(a, nitems, s);
 }
 
@@ -570,13 +755,13 @@ void march_post(const mbp_plan* P, int l, const T* pold, T* pnew, const T* f, co
 }
 
 template void march_pre<double>(const mbp_plan*, int, const double*, double*, const double*, double*,
-                                double*, const int*, const int*, int, hipStream_t);
+                                double*, const int*, const int*, int, bool, hipStream_t);
 template void march_pre<float>(const mbp_plan*, int, const float*, float*, const float*, float*, float*,
-                               const int*, const int*, int, hipStream_t);
+                               const int*, const int*, int, bool, hipStream_t);
 template void march_sweep<double>(const mbp_plan*, int, const double*, double*, const double*,
-                                  const int*, const int*, int, hipStream_t);
+                                  const int*, const int*, int, bool, hipStream_t);
 template void march_sweep<float>(const mbp_plan*, int, const float*, float*, const float*, const int*,
-                                 const int*, int, hipStream_t);
+                                 const int*, int, bool, hipStream_t);
 template void march_post<double>(const mbp_plan*, int, const double*, double*, const double*,
                                  const double*, bool, const int*, const int*, int, hipStream_t);
 template void march_post<float>(const mbp_plan*, int, const float*, float*, const float*, const float*,

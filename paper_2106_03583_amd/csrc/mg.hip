@@ -11,6 +11,10 @@
 // correction (fused), and an exact coarsest solve from a precomputed
 // eigen-decomposition.  Fine levels stream through HBM with tiled kernels;
 // the levels whose hierarchy fits in LDS run inside one workgroup per mode.
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "internal.h"
 
 namespace mbp {
@@ -345,12 +349,14 @@ k_addcorr(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntil
 __global__ void __launch_bounds__(1024)
 k_update(int nz, const double* __restrict__ rnorm, const double* __restrict__ fnorm,
          const double* __restrict__ pnorm, const double* __restrict__ sabs, double rtol2, double etol2,
-         int retire, int cycle, int* __restrict__ act, int* __restrict__ nact, int* __restrict__ cyc,
-         double* __restrict__ scal) {
+         int retire, int maxc, int* __restrict__ act, int* __restrict__ nact, int* __restrict__ cyc,
+         double* __restrict__ scal, int* __restrict__ state) {
+    // state[0]: non-finite rhs, state[1]: cycle counter, state[2]: max cycles reached
     __shared__ int keep[4096];
-    __shared__ int cnt;
     __shared__ double mx[16];
     const int n = *nact;
+    const int cycle = state[1];
+    const bool stop = cycle >= maxc;
     double m = 0.0;
     for (int it = threadIdx.x; it < n; it += blockDim.x) {
         const int q = act[it];
@@ -361,7 +367,7 @@ k_update(int nz, const double* __restrict__ rnorm, const double* __restrict__ fn
         const bool err_ok = etol2 < 0.0 || 4.0 * rnorm[q] <= etol2 * sabs[q] * sabs[q] * pnorm[q];
         const bool done = ratio <= rtol2 && err_ok;
         keep[it] = done ? -1 : q;
-        if (done || !retire) cyc[q] = cycle;
+        if (done || !retire || stop) cyc[q] = cycle;
     }
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
     if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = m;
@@ -370,20 +376,22 @@ k_update(int nz, const double* __restrict__ rnorm, const double* __restrict__ fn
         double g = 0.0;
         for (int w = 0; w < int(blockDim.x >> 6); ++w) g = fmax(g, mx[w]);
         scal[0] = g;
+        int c = 0;
         if (!retire) {  // lockstep: done when every mode passes both tests
-            int c = 0;
             for (int it = 0; it < n; ++it) c += keep[it] >= 0 ? 1 : 0;
             scal[1] = double(c);
-        }
-        if (retire) {
-            int c = 0;
+        } else {
             for (int it = 0; it < n; ++it)
                 if (keep[it] >= 0) act[c++] = keep[it];
-            cnt = c;
+            if (stop && c > 0) {
+                state[2] = 1;
+                c = 0;
+            }
             *nact = c;
         }
+        if (stop && !retire && c > 0) state[2] = 1;
+        state[1] = cycle + 1;
     }
-    (void)cnt;
 }
 
 __global__ void k_zero64(double* p, long long n) {
@@ -760,8 +768,18 @@ double* level_f<double>(const mbp_plan* P, int l) { return P->f64[l]; }
 template <>
 float* level_f<float>(const mbp_plan* P, int l) { return P->f32[l]; }
 
+// Raise a kernel's dynamic LDS limit once per device and size, so that
+// launches recorded into a graph later never need the call.
 static void set_lds(const void* fn, size_t bytes) {
-    if (bytes > 64 * 1024) hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+    if (bytes <= 64 * 1024) return;
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, size_t> done;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    size_t& have = done[{fn, dev}];
+    if (have >= bytes) return;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) == hipSuccess) have = bytes;
 }
 
 template <typename T>
@@ -773,7 +791,7 @@ float* level_pB<float>(const mbp_plan* P, int l) { return P->p32B[l]; }
 
 template <typename T>
 int launch_vcycle(const mbp_plan* P, T* p0, T* p0B, T* f0, const int* act, const int* nact, int nitems,
-                  bool norm0, hipStream_t s) {
+                  bool norm0, bool zero0, hipStream_t s) {
     const bool is32 = sizeof(T) == 4;
     const int L = is32 ? P->lds_level32 : P->lds_level;
     const dim3 blk(kTileX, kRowsPerPass);
@@ -794,15 +812,20 @@ int launch_vcycle(const mbp_plan* P, T* p0, T* p0B, T* f0, const int* act, const
         const Level& Lf = P->levels[l];
         const Level& Lc = P->levels[l + 1];
         if (use_march(l)) {
-            // sweeps alternate A -> B -> A ...; the restricting sweep ends in B
+            // sweeps alternate A -> B -> A ...; the restricting sweep ends in B.
+            // Coarse levels start from zero, so their first sweep reads no p;
+            // the next level needs zeros written only if it reads its guess.
+            bool zin = l == 0 ? zero0 : true;
             T* a = P_(l);
             T* b = PB_(l);
             for (int it = 0; it + 1 < nu1; ++it) {
-                march_sweep<T>(P, l, a, b, F_(l), act, nact, nitems, s);
+                march_sweep<T>(P, l, a, b, F_(l), act, nact, nitems, zin, s);
+                zin = false;
                 std::swap(a, b);
             }
+            T* pc = (l + 1 < L && !use_march(l + 1)) ? P_(l + 1) : nullptr;
             if (l == 0) prof_begin(P, 0, s, double(Lf.plane) * nitems);
-            march_pre<T>(P, l, a, b, F_(l), F_(l + 1), P_(l + 1), act, nact, nitems, s);
+            march_pre<T>(P, l, a, b, F_(l), F_(l + 1), pc, act, nact, nitems, zin, s);
             if (l == 0) prof_end(P, 0, s);
         } else {
             for (int it = 0; it < nu1; ++it) rbgs(l);
@@ -839,10 +862,10 @@ int launch_vcycle(const mbp_plan* P, T* p0, T* p0B, T* f0, const int* act, const
                 if (norm0 && l == 0 && last) {
                     // extra sweeps do not carry the norm; the caller evaluates it
                 }
-                march_sweep<T>(P, l, cur, oth, F_(l), act, nact, nitems, s);
+                march_sweep<T>(P, l, cur, oth, F_(l), act, nact, nitems, false, s);
                 std::swap(cur, oth);
             }
-            if (nrm) nparts = P->mtile_cnt[0];
+            if (nrm) nparts = 4 * P->mtile_cnt[0];  // one partial pair per wave of each strip
         } else {
             hipLaunchKernelGGL(k_prolong<T>, dim3(Lf.ntiles, nitems), blk, 0, s, P->d_blk + Lf.blk_off,
                                P->d_blk + Lc.blk_off, P->d_tiles + Lf.tile_off, Lf.ntiles, P->d_dbl,
@@ -855,9 +878,24 @@ int launch_vcycle(const mbp_plan* P, T* p0, T* p0B, T* f0, const int* act, const
 }
 
 template int launch_vcycle<double>(const mbp_plan*, double*, double*, double*, const int*, const int*,
-                                   int, bool, hipStream_t);
+                                   int, bool, bool, hipStream_t);
 template int launch_vcycle<float>(const mbp_plan*, float*, float*, float*, const int*, const int*, int,
-                                  bool, hipStream_t);
+                                  bool, bool, hipStream_t);
+
+__global__ void k_norm_from_rhs(const double* __restrict__ fnorm, double* __restrict__ rnorm,
+                                double* __restrict__ pnorm, const int* __restrict__ act,
+                                const int* __restrict__ nact) {
+    const int item = blockIdx.x * blockDim.x + threadIdx.x;
+    if (item >= *nact) return;
+    const int q = act[item];
+    rnorm[q] = fnorm[q];
+    pnorm[q] = 0.0;
+}
+
+void launch_norm_from_rhs(const mbp_plan* P, int nitems, hipStream_t s) {
+    hipLaunchKernelGGL(k_norm_from_rhs, dim3((nitems + 255) / 256), dim3(256), 0, s, P->d_fnorm, P->d_rnorm,
+                       P->d_pnorm, P->d_act, P->d_nact);
+}
 
 void launch_finish(const mbp_plan* P, int nparts, double* out, const int* act, const int* nact,
                    int nitems, hipStream_t s) {
@@ -913,10 +951,11 @@ void launch_plane_norm(const mbp_plan* P, const double* f, double* out, hipStrea
                        out, nullptr);
 }
 
-void launch_update_active(const mbp_plan* P, double rtol2, double etol2, int retire, int cycle,
+void launch_update_active(const mbp_plan* P, double rtol2, double etol2, int retire, int maxc,
                           hipStream_t s) {
     hipLaunchKernelGGL(k_update, dim3(1), dim3(1024), 0, s, P->g.nz, P->d_rnorm, P->d_fnorm, P->d_pnorm,
-                       P->d_sabs, rtol2, etol2, retire, cycle, P->d_act, P->d_nact, P->d_cyc, P->d_scal);
+                       P->d_sabs, rtol2, etol2, retire, maxc, P->d_act, P->d_nact, P->d_cyc, P->d_scal,
+                       P->d_flag);
 }
 
 void launch_reset_active(const mbp_plan* P, hipStream_t s) {

@@ -8,9 +8,6 @@
 
 namespace mbp {
 
-void launch_lds_full(const mbp_plan* P, double* p, const double* f, const int* act, const int* nact,
-                     int nitems, int maxc, double rtol2, double etol2, int* cyc, double* rnorm,
-                     double* fnorm, hipStream_t s);
 void launch_reset_active(const mbp_plan* P, hipStream_t s);
 void launch_area_dot(const mbp_plan* P, const double* plane, double* out_sum, hipStream_t s);
 void launch_fill_int(int* p, int n, int v, hipStream_t s);
@@ -90,7 +87,7 @@ Layout layout(const mbp_plan* P, size_t ftile_bytes, size_t mtile_bytes, int npa
 
 }  // namespace
 
-constexpr int kMarchSeg = 30;  // rows per fused-sweep strip (the LDS tile height)
+constexpr int kMarchSeg = 22;  // rows per fused-sweep strip (the LDS tile height)
 
 // Fused-sweep strips of every level (host tables); fills march_ok.
 void plan_march_tables(mbp_plan* P, std::vector<unsigned char>& bytes) {
@@ -119,14 +116,14 @@ size_t plan_device_bytes(const mbp_plan* P) {
     const int W = fft_columns_per_wg(P);
     size_t nt = 0;
     for (int b = 0; b < P->g.nb; ++b) nt += (size_t(P->g.nx[b]) * P->g.ny[b] + W - 1) / W;
-    return layout(&tmp, nt * 32, mt.size(), tmp.mtile_cnt.empty() ? 0 : tmp.mtile_cnt[0]).total;
+    return layout(&tmp, nt * 32, mt.size(), tmp.mtile_cnt.empty() ? 0 : 4 * tmp.mtile_cnt[0]).total;
 }
 
 int plan_device_init(mbp_plan* P) {
     std::vector<unsigned char> ftf, fti, mt;
     fft_build_tiles(P, ftf, fti, &P->fft_ntiles);
     plan_march_tables(P, mt);
-    Layout L = layout(P, ftf.size(), mt.size(), P->mtile_cnt[0]);
+    Layout L = layout(P, ftf.size(), mt.size(), 4 * P->mtile_cnt[0]);
     void* mem = nullptr;
     if (hipMalloc(&mem, L.total) != hipSuccess) {
         (void)hipGetLastError();
@@ -243,160 +240,221 @@ void plan_device_free(mbp_plan* P) {
     P->host_pinned = nullptr;
 }
 
+// ---------------------------------------------------------------------------
+// Solve stages.  Algorithm 1 as a sequence of stream-ordered stages so that
+// the single solve and the batched form share them: prologue (forward
+// transform, compatibility, norms), cycles (convergence test, then one
+// V-cycle of every mode still active; the device keeps the active list and
+// the cycle count), epilogue (gauge, inverse transform).
+// ---------------------------------------------------------------------------
+
 namespace {
-
-struct Readback {
-    double maxratio;
-    int nact;
-    int flag;
-    double s1, s2;
-};
-
+// layout of the plan's pinned readback buffer
+constexpr int kPinScal = 0;     // doubles 0..7: d_scal
+constexpr int kPinSum = 8;      // double: singular-plane area sum
+constexpr int kPinInts = 32;    // ints (byte offset 256): flag[0..3], nact
 }  // namespace
 
-// Algorithm 1: forward transform, per-mode multigrid to the tolerance,
-// inverse transform.  Host-driven: convergence data is read back once per
-// cycle (the plain form; the batched form replays a captured graph instead).
+void ctx_init(SolveCtx& c, mbp_plan* P, const double* rhs, double* p, double rtol, int flags) {
+    c = SolveCtx{};
+    c.P = P;
+    c.rhs = rhs;
+    c.p = p;
+    c.rtol2 = rtol * rtol;
+    const double etol = P->opt.etol == 0.0 ? 10.0 * rtol : P->opt.etol;
+    c.etol2 = etol < 0.0 ? -1.0 : etol * etol;
+    c.flags = flags;
+    c.mixed = P->opt.precision == MBP_MIXED;
+    c.retire = (flags & MBP_RETIRE) != 0;
+    c.warm = (flags & MBP_WARM_START) != 0;
+    c.full_lds = !c.mixed && P->lds_level == 0;
+    c.nitems = P->g.nz;
+}
+
+static double* pin_d(const mbp_plan* P) { return static_cast<double*>(P->host_pinned); }
+static int* pin_i(const mbp_plan* P) { return reinterpret_cast<int*>(pin_d(P) + kPinInts); }
+
+void ctx_prologue(SolveCtx& c, hipStream_t s) {
+    mbp_plan* P = c.P;
+    const int nz = P->g.nz;
+    launch_fill_int(P->d_flag, 4, 0, s);
+    launch_forward(P, c.rhs, P->fhat, P->d_flag, s);
+    if (P->g.singular) {
+        if (c.flags & MBP_PROJECT_RHS) launch_singular_fix(P, P->fhat, P->d_scal + 4, s);
+        else launch_area_dot(P, P->fhat, P->d_scal + 4, s);
+    }
+    launch_plane_norm(P, P->fhat, P->d_fnorm, s);
+    if (c.warm) launch_forward(P, c.p, P->phat, nullptr, s);
+    else launch_zero(P->phat, size_t(nz) * P->plane0, s);
+    launch_reset_active(P, s);
+    (void)hipMemcpyAsync(pin_i(P), P->d_flag, 4 * sizeof(int), hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(pin_d(P) + kPinSum, P->d_scal + 4, sizeof(double), hipMemcpyDeviceToHost, s);
+}
+
+void ctx_check(SolveCtx& c) {
+    mbp_plan* P = c.P;
+    const int nz = P->g.nz;
+    if (pin_i(P)[0]) c.status = MBP_ERR_NONFINITE;
+    if (c.status == MBP_OK && P->g.singular) {
+        const double mean_q0 = pin_d(P)[kPinSum] / P->area_sum;  // area-weighted mean of fhat_0
+        c.removed = mean_q0 / std::sqrt(double(nz));               // volume-weighted mean of f
+        if (!(c.flags & MBP_PROJECT_RHS)) {
+            // compatible if the mean is at rounding level of the plane's rms
+            double fn0 = 0.0;
+            (void)hipMemcpy(&fn0, P->d_fnorm, sizeof(double), hipMemcpyDeviceToHost);
+            const double rms = std::sqrt(fn0 / double(P->plane0));
+            if (std::fabs(mean_q0) > 1e-12 * (rms + 1e-300)) c.status = MBP_ERR_INCOMPATIBLE;
+            c.removed = 0.0;
+        }
+    }
+    if (c.status != MBP_OK) c.done = true;
+}
+
+// Convergence test of the current iterate (Sec. 3's per-mode systems each
+// stop on their own when retiring).
+void ctx_test(SolveCtx& c, hipStream_t s) {
+    mbp_plan* P = c.P;
+    const bool zero = c.cycles == 0 && !c.warm;  // p = 0: the residual is f itself
+    if (c.mixed)
+        launch_residual_to32(P, P->phat, P->fhat, P->f32[0], P->p32[0], P->d_rnorm, P->d_act, P->d_nact,
+                             c.nitems, s);
+    else if (zero)
+        launch_norm_from_rhs(P, c.nitems, s);
+    else if (c.fused_parts > 0)
+        launch_finish(P, c.fused_parts, P->d_rnorm, P->d_act, P->d_nact, c.nitems, s);
+    else
+        launch_residual_norm(P, P->phat, P->fhat, P->d_rnorm, P->d_act, P->d_nact, c.nitems, s);
+    launch_update_active(P, c.rtol2, c.etol2, c.retire ? 1 : 0, P->opt.max_cycles, s);
+}
+
+void ctx_vcycle(SolveCtx& c, hipStream_t s) {
+    mbp_plan* P = c.P;
+    const bool zero = c.cycles == 0 && !c.warm;
+    if (c.mixed) {
+        launch_vcycle<float>(P, P->p32[0], P->p32B[0], P->f32[0], P->d_act, P->d_nact, c.nitems, false, true,
+                             s);
+        launch_add_correction(P, P->phat, P->p32[0], P->d_act, P->d_nact, c.nitems, s);
+    } else {
+        c.fused_parts = launch_vcycle<double>(P, P->phat, P->phatB, P->fhat, P->d_act, P->d_nact, c.nitems,
+                                              true, zero, s);
+    }
+    ++c.cycles;
+}
+
+void ctx_state_readback(SolveCtx& c, hipStream_t s) {
+    mbp_plan* P = c.P;
+    (void)hipMemcpyAsync(pin_d(P) + kPinScal, P->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(pin_i(P), P->d_flag, 4 * sizeof(int), hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(pin_i(P) + 4, P->d_nact, sizeof(int), hipMemcpyDeviceToHost, s);
+}
+
+// After the readback synchronised: stop when every mode retired (retiring
+// form) or every mode passed (lockstep), or when the cycle budget ran out.
+void ctx_state_apply(SolveCtx& c) {
+    mbp_plan* P = c.P;
+    const int* hi = pin_i(P);
+    const bool hitmax = hi[2] != 0;
+    bool converged;
+    if (c.retire) {
+        c.nitems = hi[4];
+        converged = c.nitems == 0 && !hitmax;
+    } else {
+        converged = pin_d(P)[kPinScal + 1] == 0.0;
+    }
+    if (converged) {
+        c.done = true;
+    } else if (hitmax) {
+        c.status = MBP_ERR_NOT_CONVERGED;
+        c.done = true;
+    }
+}
+
+void ctx_epilogue(SolveCtx& c, hipStream_t s) {
+    mbp_plan* P = c.P;
+    if (c.status == MBP_OK || c.status == MBP_ERR_NOT_CONVERGED) {
+        if (P->g.singular) launch_singular_fix(P, P->phat, P->d_scal + 5, s);
+        launch_inverse(P, P->phat, c.p, s);
+    }
+}
+
+// Host-side result record; synchronises the stream.
+int ctx_info(SolveCtx& c, hipStream_t s, mbp_solve_info* info) {
+    mbp_plan* P = c.P;
+    const int nz = P->g.nz;
+    std::vector<int> cyc(nz, 0);
+    std::vector<double> rn(nz, 0.0), fn(nz, 0.0);
+    (void)hipMemcpyAsync(cyc.data(), P->d_cyc, nz * sizeof(int), hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(rn.data(), P->d_rnorm, nz * sizeof(double), hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(fn.data(), P->d_fnorm, nz * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return MBP_ERR_HIP;
+    if (hipGetLastError() != hipSuccess) return MBP_ERR_HIP;
+    double maxratio = 0.0;
+    int cycles = 0;
+    for (int q = 0; q < nz; ++q) {
+        maxratio = std::max(maxratio, fn[q] > 0 ? rn[q] / fn[q] : (rn[q] > 0 ? 1e300 : 0.0));
+        cycles = std::max(cycles, cyc[q]);
+    }
+    if (c.status == MBP_OK && c.full_lds && maxratio > c.rtol2) c.status = MBP_ERR_NOT_CONVERGED;
+    if (info) {
+        info->status = c.status;
+        info->cycles = cycles;
+        info->rel_residual = std::sqrt(maxratio);
+        info->removed_mean = c.status == MBP_ERR_NONFINITE ? 0.0 : c.removed;
+        if (info->cycles_per_mode) std::memcpy(info->cycles_per_mode, cyc.data(), nz * sizeof(int));
+    }
+    return MBP_OK;
+}
+
+// Algorithm 1 for one problem: forward transform, per-mode multigrid to the
+// tolerance, inverse transform.  Host-driven: the convergence state is read
+// back once per cycle (the batched form replays captured cycles instead).
 int solve_one(mbp_plan* P, const double* rhs, double* p, double rtol, int flags, hipStream_t s,
               mbp_solve_info* info) {
-    const int nz = P->g.nz;
-    const bool mixed = P->opt.precision == MBP_MIXED;
-    const bool retire = (flags & MBP_RETIRE) != 0;
-    const int maxc = P->opt.max_cycles;
-    const double rtol2 = rtol * rtol;
-    const double etol = P->opt.etol == 0.0 ? 10.0 * rtol : P->opt.etol;
-    const double etol2 = etol < 0.0 ? -1.0 : etol * etol;
+    SolveCtx c;
+    ctx_init(c, P, rhs, p, rtol, flags);
     hipEvent_t ev[4];
     for (auto& e : ev) (void)hipEventCreate(&e);
     (void)hipEventRecord(ev[0], s);
-    launch_fill_int(P->d_flag, 4, 0, s);
-    launch_forward(P, rhs, P->fhat, P->d_flag, s);
-    if (P->g.singular) {
-        if (flags & MBP_PROJECT_RHS) launch_singular_fix(P, P->fhat, P->d_scal + 1, s);
-        else launch_area_dot(P, P->fhat, P->d_scal + 1, s);
-    }
-    launch_plane_norm(P, P->fhat, P->d_fnorm, s);
-    if (flags & MBP_WARM_START) launch_forward(P, p, P->phat, nullptr, s);
-    else launch_zero(P->phat, size_t(nz) * P->plane0, s);
-    launch_reset_active(P, s);
+    ctx_prologue(c, s);
     (void)hipEventRecord(ev[1], s);
-
-    double* hs = static_cast<double*>(P->host_pinned);
-    int* hi = reinterpret_cast<int*>(hs + 16);
-    (void)hipMemcpyAsync(hi, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, s);
-    (void)hipMemcpyAsync(hs + 1, P->d_scal + 1, sizeof(double), hipMemcpyDeviceToHost, s);
-    if (hipStreamSynchronize(s) != hipSuccess) return MBP_ERR_HIP;
-    int status = MBP_OK;
-    double removed = 0.0;
-    if (hi[0]) status = MBP_ERR_NONFINITE;
-    if (status == MBP_OK && P->g.singular) {
-        const double mean_q0 = hs[1] / P->area_sum;  // area-weighted mean of fhat_0
-        removed = mean_q0 / std::sqrt(double(nz));   // volume-weighted mean of f
-        if (!(flags & MBP_PROJECT_RHS)) {
-            // compatible if the mean is at rounding level of the plane's rms
-            std::vector<double> fn(1);
-            (void)hipMemcpy(fn.data(), P->d_fnorm, sizeof(double), hipMemcpyDeviceToHost);
-            const double rms = std::sqrt(fn[0] / double(P->plane0));
-            if (std::fabs(mean_q0) > 1e-12 * (rms + 1e-300)) status = MBP_ERR_INCOMPATIBLE;
-            removed = 0.0;
-        }
-    }
-    int cycles = 0;
-    double maxratio = 0.0;
-    std::vector<int> cyc(nz, 0);
-    if (status == MBP_OK) {
-        if (!mixed && P->lds_level == 0) {
-            launch_lds_full(P, P->phat, P->fhat, P->d_act, P->d_nact, nz, maxc, rtol2, etol2, P->d_cyc,
-                            P->d_rnorm, P->d_fnorm, s);
-            std::vector<double> rn(nz), fn(nz);
-            (void)hipMemcpyAsync(cyc.data(), P->d_cyc, nz * sizeof(int), hipMemcpyDeviceToHost, s);
-            (void)hipMemcpyAsync(rn.data(), P->d_rnorm, nz * sizeof(double), hipMemcpyDeviceToHost, s);
-            (void)hipMemcpyAsync(fn.data(), P->d_fnorm, nz * sizeof(double), hipMemcpyDeviceToHost, s);
-            if (hipStreamSynchronize(s) != hipSuccess) return MBP_ERR_HIP;
-            for (int q = 0; q < nz; ++q) {
-                const double r = fn[q] > 0 ? rn[q] / fn[q] : (rn[q] > 0 ? 1e300 : 0.0);
-                maxratio = std::max(maxratio, r);
-                cycles = std::max(cycles, cyc[q]);
-            }
-            if (maxratio > rtol2) status = MBP_ERR_NOT_CONVERGED;
+    int st = MBP_OK;
+    if (hipStreamSynchronize(s) != hipSuccess) st = MBP_ERR_HIP;
+    if (st == MBP_OK) {
+        ctx_check(c);
+        if (!c.done && c.full_lds) {
+            launch_lds_full(P, P->phat, P->fhat, P->d_act, P->d_nact, P->g.nz, P->opt.max_cycles, c.rtol2,
+                            c.etol2, P->d_cyc, P->d_rnorm, P->d_fnorm, s);
         } else {
-            int nitems = nz;
-            int fused_parts = 0;  // > 0: the last V-cycle already produced the residual partials
-            for (int c = 0;; ++c) {
-                if (mixed)
-                    launch_residual_to32(P, P->phat, P->fhat, P->f32[0], P->p32[0], P->d_rnorm,
-                                         P->d_act, P->d_nact, nitems, s);
-                else if (fused_parts > 0)
-                    launch_finish(P, fused_parts, P->d_rnorm, P->d_act, P->d_nact, nitems, s);
-                else
-                    launch_residual_norm(P, P->phat, P->fhat, P->d_rnorm, P->d_act, P->d_nact, nitems, s);
-                launch_update_active(P, rtol2, etol2, retire ? 1 : 0, c, s);
-                (void)hipMemcpyAsync(hs, P->d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
-                (void)hipMemcpyAsync(hi + 1, P->d_nact, sizeof(int), hipMemcpyDeviceToHost, s);
-                if (hipStreamSynchronize(s) != hipSuccess) return MBP_ERR_HIP;
-                cycles = c;
-                if (retire) {
-                    nitems = hi[1];
-                    if (nitems == 0) break;
-                } else if (hs[1] == 0.0) {  // every mode passed
-                    maxratio = hs[0];
+            while (!c.done) {
+                ctx_test(c, s);
+                ctx_state_readback(c, s);
+                if (hipStreamSynchronize(s) != hipSuccess) {
+                    st = MBP_ERR_HIP;
                     break;
                 }
-                maxratio = hs[0];
-                if (c >= maxc) {
-                    status = MBP_ERR_NOT_CONVERGED;
-                    break;
-                }
-                if (mixed) {
-                    launch_vcycle<float>(P, P->p32[0], P->p32B[0], P->f32[0], P->d_act, P->d_nact, nitems,
-                                         false, s);
-                    launch_add_correction(P, P->phat, P->p32[0], P->d_act, P->d_nact, nitems, s);
-                } else {
-                    fused_parts = launch_vcycle<double>(P, P->phat, P->phatB, P->fhat, P->d_act, P->d_nact,
-                                                        nitems, true, s);
-                }
+                ctx_state_apply(c);
+                if (c.done) break;
+                ctx_vcycle(c, s);
             }
-            (void)hipMemcpyAsync(cyc.data(), P->d_cyc, nz * sizeof(int), hipMemcpyDeviceToHost, s);
-            if (retire) {
-                std::vector<double> rn(nz), fn(nz);
-                (void)hipMemcpyAsync(rn.data(), P->d_rnorm, nz * sizeof(double), hipMemcpyDeviceToHost, s);
-                (void)hipMemcpyAsync(fn.data(), P->d_fnorm, nz * sizeof(double), hipMemcpyDeviceToHost, s);
-                if (hipStreamSynchronize(s) != hipSuccess) return MBP_ERR_HIP;
-                maxratio = 0.0;
-                for (int q = 0; q < nz; ++q)
-                    maxratio = std::max(maxratio, fn[q] > 0 ? rn[q] / fn[q] : (rn[q] > 0 ? 1e300 : 0.0));
-            }
-            if (hipStreamSynchronize(s) != hipSuccess) return MBP_ERR_HIP;
-            if (retire)
-                for (int q = 0; q < nz; ++q) cycles = std::max(cycles, cyc[q]);
         }
     }
     (void)hipEventRecord(ev[2], s);
-    if (status == MBP_OK || status == MBP_ERR_NOT_CONVERGED) {
-        if (P->g.singular) launch_singular_fix(P, P->phat, P->d_scal + 2, s);
-        launch_inverse(P, P->phat, p, s);
-    }
+    if (st == MBP_OK) ctx_epilogue(c, s);
     (void)hipEventRecord(ev[3], s);
-    if (hipStreamSynchronize(s) != hipSuccess) return MBP_ERR_HIP;
-    if (hipGetLastError() != hipSuccess) return MBP_ERR_HIP;
-    if (info) {
-        info->status = status;
-        info->cycles = cycles;
-        info->rel_residual = std::sqrt(maxratio);
-        info->removed_mean = removed;
-        if (info->cycles_per_mode) std::memcpy(info->cycles_per_mode, cyc.data(), nz * sizeof(int));
-        float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
-        (void)hipEventElapsedTime(&t01, ev[0], ev[1]);
-        (void)hipEventElapsedTime(&t12, ev[1], ev[2]);
-        (void)hipEventElapsedTime(&t23, ev[2], ev[3]);
-        (void)hipEventElapsedTime(&t03, ev[0], ev[3]);
-        info->t_ms[0] = t01;
-        info->t_ms[1] = t12;
-        info->t_ms[2] = t23;
-        info->t_ms[3] = t03;
+    if (st == MBP_OK) st = ctx_info(c, s, info);
+    if (st == MBP_OK && info) {
+        float t[3] = {0, 0, 0}, tt = 0;
+        (void)hipEventElapsedTime(&t[0], ev[0], ev[1]);
+        (void)hipEventElapsedTime(&t[1], ev[1], ev[2]);
+        (void)hipEventElapsedTime(&t[2], ev[2], ev[3]);
+        (void)hipEventElapsedTime(&tt, ev[0], ev[3]);
+        info->t_ms[0] = t[0];
+        info->t_ms[1] = t[1];
+        info->t_ms[2] = t[2];
+        info->t_ms[3] = tt;
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
-    return status;
+    return st != MBP_OK ? st : c.status;
 }
 
 }  // namespace mbp

@@ -1,0 +1,173 @@
+"""Batched and served solves through the C ABI, checked against the oracle.
+
+The batched form (graph-replayed cycles with device-side retirement) and the
+serving loop (continuous batching on several streams with an LRU plan cache)
+must give every problem the same answer as a single solve: relative residual
+<= 1e-10 and relative error <= 1e-9 against the FP64 oracle, and agreement
+with the single solve of the same request to 1e-9 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def mbp():
+    import paper_2106_03583_amd as m
+    return m
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _mix():
+    """Uneven problems: every z pair, joined blocks, stretched faces, odd sizes."""
+    return [
+        W.box(64, 48, 8, 0.5, 0.375, 0.0625, "DD", "NN", "PP", xfactor=1.4, name="b64x48_PP"),
+        W.box(40, 36, 10, 40 / 128, 36 / 128, 10 / 128, "PP", "DD", "NN", name="b40x36_NN"),
+        W.box(70, 130, 6, 70 / 128, 130 / 128, 6 / 128, "ND", "PP", "DD", xfactor=2.0, name="b70x130_DD"),
+        W.lshape(32, 16, 1.5, 2.0),
+        W.box(96, 80, 12, 0.75, 0.625, 0.1, "DN", "NN", "ND", xfactor=1.7, yfactor=1.2, name="b96x80_ND"),
+        W.box(48, 48, 4, 0.375, 0.375, 0.03125, "NN", "NN", "DN", name="b48_DN"),
+        W.box(20, 24, 6, 20 / 128, 24 / 128, 6 / 128, "DD", "DD", "PP", name="b20x24_lds"),
+    ]
+
+
+def _check(prob, got, f, label):
+    ref = oracle.solve(prob, f)
+    fproj = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
+    res = oracle.rel_residual(prob, got, fproj)
+    err = oracle.rel_error(got, ref)
+    print(f"  {label} {prob.name}: residual={res:.2e} error={err:.2e}", flush=True)
+    assert res <= 1e-10 and err <= 1e-9, (prob.name, res, err)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_matches_oracle(torch_cuda, mbp, precision):
+    torch = torch_cuda
+    probs = _mix()
+    print(f"batch {precision} of {len(probs)}", flush=True)
+    plans = [mbp.Plan(pr, precision=precision) for pr in probs]
+    fs = [W.rhs(pr, 100 + i) for i, pr in enumerate(probs)]
+    rhs = [dev(torch, f) for f in fs]
+    out = [torch.zeros_like(r) for r in rhs]
+    infos = mbp.solve_batch(plans, rhs, out, rtol=1e-10, flags=mbp.PROJECT_RHS)
+    for pr, f, o, inf in zip(probs, fs, out, infos):
+        assert inf.status == 0 and inf.rel_residual <= 1e-10
+        _check(pr, o.cpu().numpy(), f, "batch")
+    # each item equals its single solve to the tolerance
+    for pl, r, o in zip(plans, rhs, out):
+        q = torch.zeros_like(r)
+        pl.solve(r, q, rtol=1e-10, flags=mbp.PROJECT_RHS | mbp.RETIRE)
+        assert float((q - o).norm() / q.norm()) <= 1e-9
+    for pl in plans:
+        pl.close()
+
+
+def test_batch_autotune_and_reuse(torch_cuda, mbp):
+    torch = torch_cuda
+    probs = _mix()[:5]
+    plans = [mbp.Plan(pr) for pr in probs]
+    fs = [W.rhs(pr, 200 + i) for i, pr in enumerate(probs)]
+    rhs = [dev(torch, f) for f in fs]
+    out = [torch.zeros_like(r) for r in rhs]
+    assert mbp.batch_schedule(plans) is None
+    infos = mbp.solve_batch(plans, rhs, out, flags=mbp.PROJECT_RHS | mbp.AUTOTUNE)
+    assert all(i.status == 0 for i in infos)
+    sched = mbp.batch_schedule(plans)
+    assert sched is not None and sched[0] >= 1 and sched[1] >= 1
+    # a second call reuses the tuned schedule and gives the same answers
+    out2 = [torch.zeros_like(r) for r in rhs]
+    mbp.solve_batch(plans, rhs, out2, flags=mbp.PROJECT_RHS)
+    for a, b, pr, f in zip(out, out2, probs, fs):
+        assert float((a - b).norm() / a.norm()) <= 1e-9
+        _check(pr, b.cpu().numpy(), f, "tuned")
+    for pl in plans:
+        pl.close()
+
+
+def test_batch_errors(torch_cuda, mbp):
+    torch = torch_cuda
+    good = W.box(32, 32, 4, 0.25, 0.25, 0.03125, "DD", "NN", "PP", name="g")
+    sing = W.lshape(8, 4, 1.5, 1.0)  # singular: needs projection
+    pg, ps = mbp.Plan(good), mbp.Plan(sing)
+    fg, fs = dev(torch, W.rhs(good, 1)), dev(torch, W.rhs(sing, 2))
+    og, os_ = torch.zeros_like(fg), torch.zeros_like(fs)
+    infos = mbp.solve_batch([pg, ps], [fg, fs], [og, os_], flags=0, raise_on_error=False)
+    assert infos[0].status == 0
+    assert infos[1].status == mbp.ERR_INCOMPATIBLE
+    _check(good, og.cpu().numpy(), W.rhs(good, 1), "with-failing-neighbour")
+    with pytest.raises(mbp.MBPError):
+        mbp.solve_batch([pg, pg], [fg, fg], [og, og])  # same plan twice
+    pg.close()
+    ps.close()
+
+
+def test_server_mix_equals_alone(torch_cuda, mbp):
+    """Continuous batching: requests overlap on the device; every result
+    matches the oracle and the same request solved alone."""
+    torch = torch_cuda
+    probs = _mix() + [_mix()[0], _mix()[3]]  # repeats reuse cached plans
+    fs = [W.rhs(pr, 300 + i) for i, pr in enumerate(probs)]
+    rhs = [dev(torch, f) for f in fs]
+    outs = [torch.zeros_like(r) for r in rhs]
+    torch.cuda.synchronize()
+    srv = mbp.Server(hbm_budget=2 << 30, slots=4, precision="mixed")
+    tickets = [srv.submit(pr, r, o, rtol=1e-10, flags=mbp.PROJECT_RHS) for pr, r, o in zip(probs, rhs, outs)]
+    lat = []
+    for t in tickets:
+        st, info, ms = srv.wait(t)
+        assert st == 0, st
+        lat.append(ms)
+    srv.close()
+    print(f"  latency ms p50={np.percentile(lat, 50):.2f} p99={np.percentile(lat, 99):.2f}", flush=True)
+    assert all(x > 0 for x in lat)
+    for pr, f, r, o in zip(probs, fs, rhs, outs):
+        _check(pr, o.cpu().numpy(), f, "served")
+        pl = mbp.Plan(pr, precision="mixed")
+        q = torch.zeros_like(r)
+        pl.solve(r, q, rtol=1e-10, flags=mbp.PROJECT_RHS | mbp.RETIRE)
+        pl.close()
+        assert float((q - o).norm() / q.norm()) <= 1e-9
+
+
+def test_server_budget_and_errors(torch_cuda, mbp):
+    torch = torch_cuda
+    small = W.box(48, 40, 8, 48 / 128, 40 / 128, 8 / 128, "DD", "NN", "PP", name="s")
+    other = W.box(40, 48, 6, 40 / 128, 48 / 128, 6 / 128, "NN", "DD", "NN", name="o")
+    fp = mbp.plan_check(small)["workspace_bytes"]
+    fo = mbp.plan_check(other)["workspace_bytes"]
+    # room for one plan at a time: requests wait for memory, idle plans get evicted
+    srv = mbp.Server(hbm_budget=max(fp, fo) + 1024, slots=3, precision="fp64")
+    items = []
+    for i in range(6):
+        pr = small if i % 2 == 0 else other
+        f = W.rhs(pr, 400 + i)
+        r = dev(torch, f)
+        o = torch.zeros_like(r)
+        items.append((pr, f, r, o))
+    torch.cuda.synchronize()
+    tickets = [srv.submit(pr, r, o, flags=mbp.PROJECT_RHS) for pr, f, r, o in items]
+    for t, (pr, f, r, o) in zip(tickets, items):
+        st, info, ms = srv.wait(t)
+        assert st == 0
+        _check(pr, o.cpu().numpy(), f, "budget")
+    big = W.box(256, 256, 64, 1.0, 1.0, 0.25, "DD", "DD", "PP", name="big")
+    rb = torch.zeros(big.ncells, dtype=torch.float64, device="cuda")
+    ob = torch.zeros_like(rb)
+    with pytest.raises(mbp.MBPError) as e:
+        srv.submit(big, rb, ob)
+    assert e.value.status == mbp.ERR_TOO_LARGE
+    srv.close()
