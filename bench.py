@@ -2,6 +2,8 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lshape|box|cube32]
                     [--precision fp64|mixed] [--lockstep] [--no-cpu] [--no-variants]
+    python bench.py --workload batch64 [--steps K]     # 64 uneven problems, batched form
+    python bench.py --workload serve [--requests N]    # Poisson request stream, server
 
 One step is one complete solve of the pressure-Poisson problem (Algorithm 1):
 forward z-transform, the shifted 2D multigrid solves of every mode to a
@@ -63,14 +65,20 @@ def _vcycle_bytes_per_point(precision: str, nu1: int, nu2: int) -> float:
     return ((nu1 + nu2) * 3.0 + 4.5) * w * 4.0 / 3.0
 
 
-def _traffic_record():
-    """HBM bytes per launch of the dominant kernel from the committed counter summary."""
-    path = os.path.join(HERE, "profiles", "traffic_fused_sweep_lshape_256x3x512.json")
+def _traffic_record(workload: str, precision: str):
+    """HBM bytes per launch of the dominant kernel from the committed counter summary
+    (the JSON block of profiles/traffic_fused_sweep_<workload>_<precision>.md)."""
+    names = {"lshape3x256^2x512_stretch1.5": "lshape_256x3x512", "box512x512x1024_DD_NN_NN": "box_512x512x1024"}
+    if workload not in names:
+        return None
+    path = os.path.join(HERE, "profiles", f"traffic_fused_sweep_{names[workload]}_{precision}.md")
     if not os.path.exists(path):
         return None
-    with open(path) as fh:
-        rec = json.load(fh)
-    return rec
+    text = open(path).read()
+    if "```json" not in text:
+        return None
+    block = text.split("```json", 1)[1].split("```", 1)[0]
+    return json.loads(block)
 
 
 def cpu_baseline(prob, f, budget_s: float = 20.0) -> dict:
@@ -134,12 +142,161 @@ def cpu_baseline(prob, f, budget_s: float = 20.0) -> dict:
     }
 
 
+def _device_rhs(torch, n, seed):
+    """Seeded uniform[-1, 1) rhs drawn on the device (throughput runs only)."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(int(seed))
+    return torch.rand(n, generator=g, dtype=torch.float64, device="cuda") * 2.0 - 1.0
+
+
+def _rel(torch, a, b):
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def bench_batch(args, torch, mbp):
+    """64 independent solves of uneven size: mixed batched form vs plain FP64."""
+    probs = W.config4()
+    ncells = sum(p.ncells for p in probs)
+    rhs = [_device_rhs(torch, p.ncells, 4000 + i) for i, p in enumerate(probs)]
+    t0 = time.perf_counter()
+    fast = [mbp.Plan(p, precision="mixed") for p in probs]
+    plain = [mbp.Plan(p, precision="fp64") for p in probs]
+    t_plan = time.perf_counter() - t0
+    out_f = [torch.zeros_like(r) for r in rhs]
+    out_p = [torch.zeros_like(r) for r in rhs]
+    print(f"# batch64: {len(probs)} problems, {ncells} cells, plans {t_plan:.1f} s", file=sys.stderr, flush=True)
+    # warm-up (the first call tunes the schedule), then timed calls
+    mbp.solve_batch(fast, rhs, out_f, rtol=RTOL, flags=mbp.PROJECT_RHS | mbp.AUTOTUNE)
+    for _ in range(max(0, args.warmup - 1)):
+        mbp.solve_batch(fast, rhs, out_f, rtol=RTOL, flags=mbp.PROJECT_RHS)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos = mbp.solve_batch(fast, rhs, out_f, rtol=RTOL, flags=mbp.PROJECT_RHS)
+    torch.cuda.synchronize()
+    t_fast = (time.perf_counter() - w0) / args.steps
+    sched = mbp.batch_schedule(fast)
+    # plain FP64: one solve at a time, all modes in lockstep, host-driven
+    for pl, r, o in zip(plain, rhs, out_p):
+        pl.solve(r, o, rtol=RTOL, flags=mbp.PROJECT_RHS)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for pl, r, o in zip(plain, rhs, out_p):
+        pl.solve(r, o, rtol=RTOL, flags=mbp.PROJECT_RHS)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - w0
+    # the FP64 batched form, for the breakdown
+    w0 = time.perf_counter()
+    mbp.solve_batch(plain, rhs, out_p, rtol=RTOL, flags=mbp.PROJECT_RHS)
+    torch.cuda.synchronize()
+    t_fp64_batch = time.perf_counter() - w0
+    diff = max(_rel(torch, a, b) for a, b in zip(out_f, out_p))
+    ok = all(i.status == 0 and i.rel_residual <= RTOL for i in infos)
+    for pl in fast + plain:
+        pl.close()
+    return {
+        "metric": "solves/s at 1e-10 relative residual",
+        "value": len(probs) / t_fast,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_fast * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-in-f64", "data": "synthetic (seeded, device-drawn rhs)",
+        "config": {"workload": "batch of 64 uneven boxes 64..384 x 64..384 x 64..256, all BC pairs",
+                   "cells": ncells, "form": "mixed, batched graph replay, per-mode retirement",
+                   "schedule_streams_cycles": sched},
+        "grid_points_per_s": ncells / t_fast,
+        "plain_fp64_solves_per_s": len(probs) / t_plain,
+        "fp64_batched_solves_per_s": len(probs) / t_fp64_batch,
+        "speedup_vs_plain_fp64": t_plain / t_fast,
+        "max_rel_diff_vs_plain": diff,
+        "ok": ok,
+        "plan_s": round(t_plan, 2),
+    }
+
+
+def bench_serve(args, torch, mbp):
+    """Poisson stream of requests through the server; latency p50/p99."""
+    n = args.requests
+    reqs = W.config5(count=n, rate_per_s=1.0)
+    cells = [r.problem.ncells for r in reqs]
+    rhs = [_device_rhs(torch, c, r.seed) for c, r in zip(cells, reqs)]
+    outs = [torch.zeros_like(x) for x in rhs]
+    torch.cuda.synchronize()
+    budget = int(args.server_gb * (1 << 30))
+    srv = mbp.Server(hbm_budget=budget, slots=args.slots, precision="mixed")
+
+    def closed_loop():
+        w0 = time.perf_counter()
+        ts = [srv.submit(r.problem, x, o, rtol=RTOL, flags=mbp.PROJECT_RHS) for r, x, o in zip(reqs, rhs, outs)]
+        res = [srv.wait(t) for t in ts]
+        return time.perf_counter() - w0, res
+
+    closed_loop()  # warm: builds and caches plans where the budget allows
+    t_cap, _ = closed_loop()
+    capacity = n / t_cap
+    rate = 0.7 * capacity
+    print(f"# serve: {n} requests, capacity {capacity:.1f} solves/s, replay at {rate:.1f}/s",
+          file=sys.stderr, flush=True)
+    w0 = time.perf_counter()
+    tickets = []
+    for r, x, o in zip(reqs, rhs, outs):
+        due = w0 + r.arrival_s / rate
+        while True:
+            now = time.perf_counter()
+            if now >= due:
+                break
+            time.sleep(min(0.0005, due - now))
+        tickets.append(srv.submit(r.problem, x, o, rtol=RTOL, flags=mbp.PROJECT_RHS))
+    res = [srv.wait(t) for t in tickets]
+    t_open = time.perf_counter() - w0
+    srv.close()
+    lat = np.array([ms for _, _, ms in res])
+    steady = lat[n // 10:]
+    ok = all(st == 0 for st, _, _ in res)
+    # the same trace back to back through the plain FP64 solver (plans built beforehand)
+    plans = [mbp.Plan(r.problem, precision="fp64") for r in reqs]
+    ref = [torch.zeros_like(x) for x in rhs]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for pl, x, o in zip(plans, rhs, ref):
+        pl.solve(x, o, rtol=RTOL, flags=mbp.PROJECT_RHS)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - w0
+    diff = max(_rel(torch, a, b) for a, b in zip(outs, ref))
+    for pl in plans:
+        pl.close()
+    return {
+        "metric": "solves/s at 1e-10 relative residual; p50/p99 latency",
+        "value": capacity,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": n, "warmup": n,
+        "ms_per_step": round(1e3 / capacity, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-in-f64", "data": "synthetic (seeded, device-drawn rhs)",
+        "config": {"workload": f"Poisson request stream, {n} requests, sizes log-uniform 32..512 per axis",
+                   "cells": int(sum(cells)), "slots": args.slots, "hbm_budget_gb": args.server_gb},
+        "capacity_solves_per_s": capacity,
+        "replay_rate_per_s": rate,
+        "replay_solves_per_s": n / t_open,
+        "latency_ms_p50": float(np.percentile(steady, 50)),
+        "latency_ms_p99": float(np.percentile(steady, 99)),
+        "plain_fp64_solves_per_s": n / t_plain,
+        "speedup_vs_plain_fp64": (n / t_cap) / (n / t_plain),
+        "max_rel_diff_vs_plain": diff,
+        "ok": ok,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lshape", choices=["lshape", "box", "cube32"])
+    ap.add_argument("--workload", default="lshape", choices=["lshape", "box", "cube32", "batch64", "serve"])
+    ap.add_argument("--requests", type=int, default=200, help="serve: requests in the stream")
+    ap.add_argument("--slots", type=int, default=8, help="serve: concurrent requests")
+    ap.add_argument("--server-gb", type=float, default=96.0, help="serve: plan memory budget (GiB)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--lockstep", action="store_true", help="iterate all modes until the global test passes")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -175,6 +332,10 @@ def main(argv=None):
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "ms": ms,
                           "GBs": 16 * n / (ms * 1e-3) / 1e9}), flush=True)
         return 0
+    if args.workload in ("batch64", "serve"):
+        out = (bench_batch if args.workload == "batch64" else bench_serve)(args, torch, mbp)
+        print(json.dumps(out), flush=True)
+        return 0 if out["ok"] else 1
     prob, seed, dist = _workload(args.workload)
     f = W.rhs(prob, seed, dist)
     fd = torch.from_numpy(f).cuda()
@@ -228,9 +389,9 @@ def main(argv=None):
         bpc = _bytes_per_cell(args.precision)
         achieved = bpc * cells / (avg_ms * 1e-3) / 1e9
         traffic = None
-        tr = _traffic_record()
+        tr = _traffic_record(prob.name, args.precision)
         if tr and tr.get("kernel_class") == cls and tr.get("workload") == prob.name \
-                and tr.get("precision") == args.precision:
+                and tr.get("precision") == args.precision and not args.lockstep:
             traffic = tr.get("bytes_per_launch")
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

@@ -146,9 +146,28 @@ __device__ __forceinline__ void static_for(F&& f) {
 constexpr int kTileRows = 22;               // output rows per strip (host cuts at this)
 constexpr int kLdsRows = kTileRows + 6;
 constexpr int kRowsPerWave = kLdsRows / 4;  // contiguous rows per wave
-constexpr int kCoarseRows = 16;             // coarse rows of the correction staged per strip
+constexpr int kWaveCoarse = 5;              // coarse rows of the correction staged per wave
 static_assert(kLdsRows % 4 == 0, "four waves share the strip rows");
-static_assert(kCoarseRows % 4 == 0, "four waves share the coarse rows");
+static_assert(2 * (kWaveCoarse - 2) + 1 >= kRowsPerWave, "a wave's rows fit its coarse rows");
+
+// Sum over the 64 lanes of a wave with DPP moves (no LDS round trips);
+// lane 63 ends up with the total.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum63(double v) {
+    v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]: every lane holds its quad's sum
+    v += dpp_move<0x114>(v);  // row_shr:4
+    v += dpp_move<0x118>(v);  // row_shr:8: lane 15 of each row holds the row's sum
+    v += dpp_move<0x142>(v);  // row_bcast:15
+    v += dpp_move<0x143>(v);  // row_bcast:31
+    return v;
+}
 constexpr int kNoRow = -1000000;            // row table: not a row of the strip's own block
 
 // Offset and sign of coarse value (I, J) of block b, one cell beyond a face
@@ -208,7 +227,7 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
 
     __shared__ T sp[kLdsRows][64];
     __shared__ T sf[kLdsRows][64];
-    __shared__ T sE[PRO ? kCoarseRows : 1][64];  // x-interpolated coarse correction per lane
+    __shared__ T sE[PRO ? 4 : 1][PRO ? kWaveCoarse : 1][64];  // per wave: x-interpolated coarse rows
     __shared__ double sy[kLdsRows][3][3];        // per row and column region: wm, wp, dy
     __shared__ int scol[kLdsRows][3];            // (row index + parity) & 1, or -1: no cell
     __shared__ int scy[kLdsRows];                // PRO: coarse lower row of inside rows, kNoRow else
@@ -371,7 +390,7 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
 
     // ---- loads of one mode: p and f of the wave's rows, coarse rows ----
     T lp[kRowsPerWave], lf[kRowsPerWave];
-    T leA[kCoarseRows / 4], leB[kCoarseRows / 4];
+    T leA[kWaveCoarse], leB[kWaveCoarse];
     const bool zin = args.zero_in != 0;
     auto issue_pf = [&](int q) __attribute__((always_inline)) {
         const T* __restrict__ fq = fsrc + q * plane;
@@ -388,8 +407,8 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
     auto issue_e = [&](int q, int cyb) __attribute__((always_inline)) {
         const T* __restrict__ ecq = ec + q * plane_c;
 #pragma unroll
-        for (int m = 0; m < kCoarseRows / 4; ++m) {
-            const int J = cyb + wave + 4 * m;
+        for (int m = 0; m < kWaveCoarse; ++m) {
+            const int J = cyb + m;
             leA[m] = T(0);
             leB[m] = T(0);
             if (b0 >= 0 && J >= 0 && J < ncyc) {
@@ -405,35 +424,46 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
 
     issue_pf(args.act[i0]);
     __syncthreads();  // strip tables ready
-    int cyb = kNoRow;  // first coarse row staged for the correction
+    int cyb = kNoRow;  // first coarse row the wave stages for its own rows
     if (PRO) {
-        for (int r = 0; r < nrow; ++r)
-            if (scy[r] != kNoRow) { cyb = scy[r]; break; }
+        for (int m = 0; m < kRowsPerWave; ++m) {
+            const int r = rbase + m;
+            if (r < nrow && scy[r] != kNoRow) { cyb = scy[r]; break; }
+        }
         issue_e(sq[0], cyb);
     }
 
     for (int it = i0; it < i1; ++it) {
         const int q = sq[it - i0];
         const T sig = T(ssig[it - i0]);
-        // stage this mode
-#pragma unroll
-        for (int m = 0; m < kRowsPerWave; ++m) {
-            if (rbase + m < nrow) {
-                sp[rbase + m][lane] = lp[m];
-                sf[rbase + m][lane] = lf[m];
-            }
-        }
+        // stage this mode; rows inside the block take the coarse-grid
+        // correction (bilinear, physical weights) from the wave's own staged
+        // coarse rows on the way in
         if (PRO) {
 #pragma unroll
-            for (int m = 0; m < kCoarseRows / 4; ++m) {
-                const int J = cyb + wave + 4 * m;
+            for (int m = 0; m < kWaveCoarse; ++m) {
+                const int J = cyb + m;
                 const int g = J == -1 ? 0 : (J == ncyc ? 2 : 4);
-                sE[wave + 4 * m][lane] = sgw[g][lane] * leA[m] + sgw[g + 1][lane] * leB[m];
+                sE[wave][m][lane] = sgw[g][lane] * leA[m] + sgw[g + 1][lane] * leB[m];
             }
         }
-        __syncthreads();
-        // halo rows of other blocks: correction cell by cell, before the next
-        // mode's loads take the registers
+#pragma unroll
+        for (int m = 0; m < kRowsPerWave; ++m) {
+            const int r = rbase + m;
+            if (r < nrow) {
+                T v = lp[m];
+                if (PRO) {
+                    const int cy = scy[r];
+                    if (((amask >> m) & 1u) && cy != kNoRow && cy - cyb + 1 < kWaveCoarse) {
+                        const T wy = T(swy[r]);
+                        v += wy * sE[wave][cy - cyb][lane] + (T(1) - wy) * sE[wave][cy - cyb + 1][lane];
+                    }
+                }
+                sp[r][lane] = v;
+                sf[r][lane] = lf[m];
+            }
+        }
+        // halo rows of other blocks: correction cell by cell
         if (PRO) {
             const T* __restrict__ ecq = ec + q * plane_c;
 #pragma unroll 1
@@ -441,7 +471,7 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
                 const int r = rbase + m;
                 if (!((amask >> m) & 1u)) continue;
                 const int cy = scy[r];
-                if (cy != kNoRow && cy - cyb + 1 < kCoarseRows) continue;
+                if (cy != kNoRow && cy - cyb + 1 < kWaveCoarse) continue;
                 const int k = ty0 - 3 + r;
                 T corr;
                 if (k < 0) corr = correction(aB, aBc, aip, dp, ecq, bm, cim, nym + k);
@@ -450,24 +480,11 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
                 sp[r][lane] += corr;
             }
         }
+        __syncthreads();
         // the next mode's loads fly during this mode's compute
         if (it + 1 < i1) {
             issue_pf(sq[it + 1 - i0]);
             if (PRO) issue_e(sq[it + 1 - i0], cyb);
-        }
-        // coarse-grid correction of the rows inside the block (bilinear,
-        // physical weights) from the staged coarse rows
-        if (PRO) {
-#pragma unroll
-            for (int m = 0; m < kRowsPerWave; ++m) {
-                const int r = rbase + m;
-                const int cy = scy[r < nrow ? r : 0];
-                if (((amask >> m) & 1u) && r < nrow && cy != kNoRow && cy - cyb + 1 < kCoarseRows) {
-                    const T wy = T(swy[r]);
-                    sp[r][lane] += wy * sE[cy - cyb][lane] + (T(1) - wy) * sE[cy - cyb + 1][lane];
-                }
-            }
-            __syncthreads();
         }
 
         // red on rows 1 .. nrow-2 / lanes 1 .. 62, then black on rows
@@ -526,11 +543,9 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
         }
         if (NRM) {
             // one partial pair per wave: no barrier on the way out
-            for (int o = 32; o > 0; o >>= 1) {
-                nrm += __shfl_xor(nrm, o);
-                pnr += __shfl_xor(pnr, o);
-            }
-            if (lane == 0) {
+            nrm = wave_sum63(nrm);
+            pnr = wave_sum63(pnr);
+            if (lane == 63) {
                 const long long o = 2 * (((long long)q * ntiles + tix) * 4 + wave);
                 args.part[o] = nrm;
                 args.part[o + 1] = pnr;
