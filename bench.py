@@ -78,7 +78,17 @@ def _traffic_record(workload: str, precision: str):
     if "```json" not in text:
         return None
     block = text.split("```json", 1)[1].split("```", 1)[0]
-    return json.loads(block)
+    rec = json.loads(block)
+    # counters describe one build of the sweep kernels: stale once the source changed
+    if rec.get("kernel_source_sha256") != _kernel_source_hash():
+        return None
+    return rec
+
+
+def _kernel_source_hash() -> str:
+    import hashlib
+    path = os.path.join(HERE, "paper_2106_03583_amd", "csrc", "march.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
 
 
 def cpu_baseline(prob, f, budget_s: float = 20.0) -> dict:
