@@ -105,13 +105,23 @@ typedef struct {
  *              / 2, with mu_0 the smallest non-zero eigenvalue magnitude
  *              of the coarsest plane operator (a lower bound of the fine
  *              one, so the estimate is conservative); 0 = 10 * rtol,
- *              negative = off                                    [0] */
+ *              negative = off                                    [0]
+ *   inner      MBP_MIXED: FP32 V-cycles per FP64 refinement step
+ *              (residual in FP64, correction solved in FP32, added in
+ *              FP64); 0 = default                                [2]
+ *   march      pre-smoothing form of the fused levels: 0 LDS strip
+ *              tiles, 1 register march (mbp_plan_autotune may change
+ *              it per level)                                     [0]
+ * In the mixed form max_cycles and the reported cycles count refinement
+ * steps (each one convergence test). */
 typedef struct {
     int32_t precision;
     int32_t nu1, nu2;
     int32_t max_cycles;
     int32_t flags;
     double etol;
+    int32_t inner;
+    int32_t march;
 } mbp_options;
 
 /* Per-solve report (caller-owned).
@@ -247,6 +257,29 @@ typedef struct {
 } mbp_profile_info;
 int mbp_profile_enable(mbp_plan* plan, int enable);
 int mbp_profile_read(mbp_plan* plan, mbp_profile_info* out);
+
+/* Schedule autotuner for one plan.  Runs the forward transform of rhs_dev
+ * and, for each candidate schedule, a few V-cycles of every mode on the
+ * plan's own workspace, timed with events on `stream`; the fastest
+ * candidate stays in the plan for every later solve.  Candidates: the
+ * number of workgroups a strip-form launch aims at (which sets how many
+ * modes one workgroup runs in turn) and, per fused multigrid level, the
+ * pre-smoothing form (LDS strip tiles of 22 x 58 cells, or a register
+ * march down strips of 128 x 58 cells).  All candidates run the same
+ * red-black sweeps.  Blocking; the plan must be idle.  out (optional):
+ *   wg_target  chosen workgroups per launch
+ *   levels     multigrid levels reported in form[] (at most 16)
+ *   form[l]    0 strip tiles, 1 register march
+ *   ms_default / ms_tuned  time of one V-cycle over all modes before / after
+ * Errors: MBP_ERR_INVALID, MBP_ERR_NONFINITE (rhs), MBP_ERR_HIP. */
+typedef struct {
+    int32_t wg_target;
+    int32_t levels;
+    int32_t form[16];
+    double ms_default;
+    double ms_tuned;
+} mbp_tuning;
+int mbp_plan_autotune(mbp_plan* plan, const double* rhs_dev, void* stream, mbp_tuning* out);
 
 /* Release the plan's device memory.  The caller ensures no work is in
  * flight on it.  NULL is ignored. */

@@ -40,7 +40,8 @@ class SynthDesc(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
-                ("max_cycles", C.c_int32), ("flags", C.c_int32), ("etol", C.c_double)]
+                ("max_cycles", C.c_int32), ("flags", C.c_int32), ("etol", C.c_double), ("inner", C.c_int32),
+                ("march", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -51,6 +52,11 @@ class SolveInfo(C.Structure):
 
 class ProfileInfo(C.Structure):
     _fields_ = [("launches", C.c_int64 * 2), ("total_ms", C.c_double * 2), ("cells", C.c_double * 2)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("wg_target", C.c_int32), ("levels", C.c_int32), ("form", C.c_int32 * 16),
+                ("ms_default", C.c_double), ("ms_tuned", C.c_double)]
 
 
 class PlanSummary(C.Structure):
@@ -83,6 +89,7 @@ def _load():
         "mbp_modal_shift": (I, [P, C.POINTER(D)]),
         "mbp_plan_destroy": (None, [P]),
         "mbp_profile_enable": (I, [P, I]),
+        "mbp_plan_autotune": (I, [P, VP, VP, C.POINTER(Tuning)]),
         "mbp_profile_read": (I, [P, C.POINTER(ProfileInfo)]),
         "mbp_server_create": (I, [C.c_size_t, I, C.POINTER(Options), C.POINTER(P)]),
         "mbp_server_submit": (I, [P, C.POINTER(BlockDesc), I, C.POINTER(SynthDesc), VP, VP, D, I,
@@ -106,6 +113,7 @@ EXPORTED = [
     "mbp_inverse_transform", "mbp_apply_operator", "mbp_modal_shift", "mbp_plan_destroy",
     "mbp_server_create", "mbp_server_submit", "mbp_server_poll", "mbp_server_wait",
     "mbp_server_destroy", "mbp_profile_enable", "mbp_profile_read", "mbp_batch_schedule",
+    "mbp_plan_autotune",
 ]
 
 
@@ -154,9 +162,9 @@ class _Desc:
         self.z = SynthDesc(int(problem.nz), float(problem.lz), int(problem.zbc[0]), int(problem.zbc[1]))
 
 
-def _options(precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0, etol=0.0) -> Options:
+def _options(precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0, etol=0.0, inner=0, march=0) -> Options:
     prec = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}[precision]
-    return Options(prec, nu1, nu2, max_cycles, flags, etol)
+    return Options(prec, nu1, nu2, max_cycles, flags, etol, inner, march)
 
 
 def plan_check(problem, **opts) -> dict:
@@ -214,10 +222,11 @@ class Info:
 
 
 class Plan:
-    def __init__(self, problem, precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0, etol=0.0):
+    def __init__(self, problem, precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0, etol=0.0, inner=0,
+                 march=0):
         self.problem = problem
         self._desc = _Desc(problem)
-        self._opt = _options(precision, nu1, nu2, max_cycles, flags, etol)
+        self._opt = _options(precision, nu1, nu2, max_cycles, flags, etol, inner, march)
         self._h = C.c_void_p()
         _check(lib.mbp_plan_create(self._desc.blocks, self._desc.nblocks, C.byref(self._desc.z),
                                    C.byref(self._opt), C.byref(self._h)), "mbp_plan_create")
@@ -263,6 +272,14 @@ class Plan:
         out = np.empty(self.nz, dtype=np.float64)
         _check(lib.mbp_modal_shift(self._h, out.ctypes.data_as(C.POINTER(C.c_double))), "modal_shift")
         return out
+
+    def autotune(self, rhs, stream=None) -> dict:
+        """Pick the fastest schedule for this plan by timing short runs on rhs."""
+        t = Tuning()
+        _check(lib.mbp_plan_autotune(self._h, _ptr(rhs, self.ncells), _stream(stream), C.byref(t)),
+               "mbp_plan_autotune")
+        return {"wg_target": t.wg_target, "form": list(t.form)[:t.levels], "ms_default": t.ms_default,
+                "ms_tuned": t.ms_tuned}
 
     def profile(self, enable: bool = True):
         _check(lib.mbp_profile_enable(self._h, 1 if enable else 0), "mbp_profile_enable")
@@ -316,8 +333,8 @@ def batch_schedule(plans: Sequence[Plan]):
 
 class Server:
     def __init__(self, hbm_budget: int, slots: int = 4, precision="mixed", nu1=1, nu2=1, max_cycles=60,
-                 flags=0, etol=0.0):
-        self._opt = _options(precision, nu1, nu2, max_cycles, flags, etol)
+                 flags=0, etol=0.0, inner=0):
+        self._opt = _options(precision, nu1, nu2, max_cycles, flags, etol, inner)
         self._h = C.c_void_p()
         _check(lib.mbp_server_create(int(hbm_budget), int(slots), C.byref(self._opt), C.byref(self._h)),
                "mbp_server_create")

@@ -165,6 +165,17 @@ int mbp_modal_shift(const mbp_plan* plan, double* shift_host) {
     return MBP_OK;
 }
 
+int mbp_plan_autotune(mbp_plan* plan, const double* rhs_dev, void* stream, mbp_tuning* out) {
+    if (!plan || !rhs_dev) return MBP_ERR_INVALID;
+    if (plan->busy) return MBP_ERR_BUSY;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) return MBP_ERR_INVALID;
+    plan->busy = true;
+    const int st = plan_autotune(plan, rhs_dev, static_cast<hipStream_t>(stream), out);
+    plan->busy = false;
+    return st;
+}
+
 int mbp_profile_enable(mbp_plan* plan, int enable) {
     if (!plan) return MBP_ERR_INVALID;
     plan->prof = enable != 0;

@@ -101,7 +101,10 @@ struct mbp_plan {
     void* d_ftiles_inv = nullptr;
     int64_t lds_limit = 64 * 1024;  // LDS bytes one workgroup may use
     int lvinfo = 0;               // int-pool offset: per level {plane, blk_off, tile_off, ntiles}
-    std::vector<int> mtile_off, mtile_cnt;  // fused-sweep strips per level
+    std::vector<int> mtile_off, mtile_cnt;  // fused-sweep strips per level (LDS strip form)
+    std::vector<int> rtile_off, rtile_cnt;  // taller strips of the register-march form
+    std::vector<char> use_rmarch;           // level runs its pre-smoothing as a register march
+    int wg_target = 256 * 12;               // strip-form launches: workgroups aimed at
     std::vector<char> march_ok;   // level runs the fused one-pass sweeps
     void* d_mtiles = nullptr;
     size_t mtile_bytes = 0;
@@ -261,5 +264,6 @@ void ctx_state_readback(SolveCtx& c, hipStream_t s);
 void ctx_state_apply(SolveCtx& c);              // after that readback synchronised
 void ctx_epilogue(SolveCtx& c, hipStream_t s);
 int ctx_info(SolveCtx& c, hipStream_t s, mbp_solve_info* info);  // synchronises s
+int plan_autotune(mbp_plan* P, const double* rhs, hipStream_t s, mbp_tuning* out);
 
 }  // namespace mbp

@@ -54,6 +54,7 @@ struct MArgs {
     double* part;      // NRM: per (mode, tile) partial sums
     int per;           // modes per workgroup (consecutive active items)
     int zero_in;       // the old iterate is zero: pold is not read
+    int wg_target;     // host: workgroups a launch aims at (modes per workgroup follow)
 };
 
 constexpr int kMaxModes = 8;  // most modes one workgroup runs in turn
@@ -596,6 +597,259 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     tile_sweep<T, true, false, NRM>(args);
 }
 
+// ------------------------- register march form of the sweep -------------------------
+// One wave owns a tall strip (58 output columns, up to 128 rows) and marches
+// down it with a five-row register window: each step takes row k, relaxes the
+// red cells of row k-1, the black cells of row k-2, stores row k-2 and forms
+// the residual of row k-3.  x neighbours come from DPP lane shifts, so there
+// is no LDS and no barrier; the loads of the next kRing rows are always in
+// flight.  The vertical halo is read once per strip instead of once per
+// short tile.  Rows of the strip's own block take the block's y coefficients
+// for every lane (joined blocks are congruent along their common faces).
+constexpr int kRing = 8;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_shift(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+// value of lane - 1 (0 at lane 0) and of lane + 1 (0 at lane 63)
+template <typename T>
+__device__ __forceinline__ T from_left(T v) { return dpp_shift<0x138>(v); }
+template <typename T>
+__device__ __forceinline__ T from_right(T v) { return dpp_shift<0x130>(v); }
+
+template <typename T, bool RES, bool NRM>
+__global__ void __launch_bounds__(256) k_rmarch(const MArgs<T> args, const double* __restrict__ dp) {
+    // dp: the coefficient pool, passed on its own so that uniform row
+    // coefficients are read through the scalar cache
+    const DBlock* __restrict__ aB = args.B;
+    const DBlock* __restrict__ aBc = args.Bc;
+    const int ntiles = args.ntiles;
+    const long long plane = args.plane, plane_c = args.plane_c;
+    const int lane = threadIdx.x & 63;
+    // the wave index is uniform per wave: say so, so that everything derived
+    // from the strip descriptor lives in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nact = *args.nact;
+    const long long item = (long long)xcd_remap_m(blockIdx.x, gridDim.x) * 4 + wave;
+    if (item >= (long long)ntiles * nact) return;
+    const int mi = int(item / ntiles), tix = int(item - (long long)mi * ntiles);
+    const int q = __builtin_amdgcn_readfirstlane(args.act[mi]);
+    const MTile& t = args.tiles[tix];
+    const int tb = t.b, tx0 = t.x0, tw = t.w, ty0 = t.y0, ty1 = t.y1;
+    const int bnx = t.bnx, bny = t.bny;
+    const T sig = T(args.shift[q]);
+
+    // ---- the lane's column (as in the strip form) ----
+    const int c = tx0 - 3 + lane;
+    const bool live = lane < tw + 6;
+    const int cr = c < 0 ? 0 : (c < bnx ? 1 : 2);
+    const int b0 = live ? pick3(cr, t.blk[1][0], t.blk[1][1], t.blk[1][2]) : -1;
+    const int bm = live ? pick3(cr, t.blk[0][0], t.blk[0][1], t.blk[0][2]) : -1;
+    const int bp = live ? pick3(cr, t.blk[2][0], t.blk[2][1], t.blk[2][2]) : -1;
+    const int nx0 = pick3(cr, t.nx[1][0], t.nx[1][1], t.nx[1][2]);
+    const int nxm = pick3(cr, t.nx[0][0], t.nx[0][1], t.nx[0][2]);
+    const int nxp = pick3(cr, t.nx[2][0], t.nx[2][1], t.nx[2][2]);
+    const int nym = pick3(cr, t.ny[0][0], t.ny[0][1], t.ny[0][2]);
+    const int ci = cr == 0 ? nx0 + c : (cr == 2 ? c - bnx : c);
+    const int cim = cr == 0 ? nxm + c : (cr == 2 ? c - bnx : c);
+    const int cip = cr == 0 ? nxp + c : (cr == 2 ? c - bnx : c);
+    const int off0 = b0 >= 0 ? pick3(cr, t.off[1][0], t.off[1][1], t.off[1][2]) + ci : 0;
+    const int offm = bm >= 0 ? pick3(cr, t.off[0][0], t.off[0][1], t.off[0][2]) + cim : 0;
+    const int offp = bp >= 0 ? pick3(cr, t.off[2][0], t.off[2][1], t.off[2][2]) + cip : 0;
+    const int cx0 = pick3(cr, t.cx[1][0], t.cx[1][1], t.cx[1][2]);
+    const int cxm = pick3(cr, t.cx[0][0], t.cx[0][1], t.cx[0][2]);
+    const int cxp = pick3(cr, t.cx[2][0], t.cx[2][1], t.cx[2][2]);
+    const int par0 = pick3(cr, t.par[1][0], t.par[1][1], t.par[1][2]);
+    const int parm = pick3(cr, t.par[0][0], t.par[0][1], t.par[0][2]);
+    const int parp = pick3(cr, t.par[2][0], t.par[2][1], t.par[2][2]);
+    const T xwm0 = b0 >= 0 ? T(dp[cx0 + ci]) : T(0), xwp0 = b0 >= 0 ? T(dp[cx0 + nx0 + ci]) : T(0);
+    const T xd0 = b0 >= 0 ? T(dp[cx0 + 2 * nx0 + ci]) : T(0);
+    const T xwmm = bm >= 0 ? T(dp[cxm + cim]) : T(0), xwpm = bm >= 0 ? T(dp[cxm + nxm + cim]) : T(0);
+    const T xdm = bm >= 0 ? T(dp[cxm + 2 * nxm + cim]) : T(0);
+    const T xwmp = bp >= 0 ? T(dp[cxp + cip]) : T(0), xwpp = bp >= 0 ? T(dp[cxp + nxp + cip]) : T(0);
+    const T xdp = bp >= 0 ? T(dp[cxp + 2 * nxp + cip]) : T(0);
+    // y coefficients per row region (one table per region, shared by its lanes)
+    const int ybm = t.blk[0][1] >= 0 ? 1 : (t.blk[0][0] >= 0 ? 0 : 2);
+    const int ybp = t.blk[2][1] >= 0 ? 1 : (t.blk[2][0] >= 0 ? 0 : 2);
+    const int ycy0 = t.cy[1][1], yny0 = bny;
+    const int ycym = t.cy[0][ybm], ynym = t.ny[0][ybm];
+    const int ycyp = t.cy[2][ybp], ynyp = t.ny[2][ybp];
+    const bool out_lane = lane >= 3 && lane < 3 + tw;
+    // y coefficients per column region of the rows near the block's edges:
+    // slots 0..3 hold rows y0-3 .. y0 (the rows up to the first one when the
+    // strip starts near it), slots 4..7 rows bny-1 .. bny+2
+    __shared__ T sY[4][8][3][3];
+    if (lane < 8 * 3) {
+        const int slot = lane / 3, j = lane - 3 * slot;
+        const int k = slot < 4 ? ty0 - 3 + slot : bny - 1 + (slot - 4);
+        const bool used = k >= ty0 - 3 && k <= ty1 + 2;  // rows the strip touches
+        const int rr = k < 0 ? 0 : (k >= bny ? 2 : 1);
+        const int jb = pick3(rr, t.blk[0][j], t.blk[1][j], t.blk[2][j]);
+        const int jcy = pick3(rr, t.cy[0][j], t.cy[1][j], t.cy[2][j]);
+        const int jny = pick3(rr, t.ny[0][j], t.ny[1][j], t.ny[2][j]);
+        const int lj = k < 0 ? jny + k : (k >= bny ? k - bny : k);
+        const bool ok = used && jb >= 0;
+        sY[wave][slot][j][0] = ok ? T(dp[jcy + lj]) : T(0);
+        sY[wave][slot][j][1] = ok ? T(dp[jcy + jny + lj]) : T(0);
+        sY[wave][slot][j][2] = ok ? T(dp[jcy + 2 * jny + lj]) : T(1);
+    }
+
+    const T* __restrict__ po = args.pold + q * plane;
+    const T* __restrict__ fq = args.f + q * plane;
+    T* __restrict__ pn = args.pnew + q * plane;
+    const bool zin = args.zero_in != 0;
+
+    // restriction bookkeeping (output lanes lie in the strip's block)
+    int ncx = 0, ncy = 0, bcoff = 0, I = 0, rwy = 0;
+    bool leader = false, three = false;
+    T wrx = T(0);
+    if (RES) {
+        ncx = aBc[tb].nx;
+        ncy = aBc[tb].ny;
+        bcoff = aBc[tb].off;
+        rwy = aB[tb].rwy;
+        if (out_lane) {
+            I = min(c >> 1, ncx - 1);
+            leader = c == 2 * I;
+            three = leader && (I == ncx - 1) && (bnx - 2 * I == 3);
+            wrx = T(dp[aB[tb].rwx + c]);
+        }
+    }
+
+    T rp[kRing], rf[kRing];
+    const int kbeg = ty0 - 3, kend = ty1 + 2;
+    // row k: its lane offset, or -1 where the lane's region has no block
+#define MBP_RM_OFF(k)                                                                               \
+    ((k) < 0 ? (bm >= 0 ? offm + (nym + (k)) * nxm : -1)                                             \
+             : ((k) >= bny ? (bp >= 0 ? offp + ((k) - bny) * nxp : -1) : (b0 >= 0 ? off0 + (k) * nx0 : -1)))
+    // loads are unconditional (a dead lane reads cell 0 of the plane) so that
+    // no branch joins on a value in flight; dead cells are masked at use
+#pragma unroll
+    for (int u = 0; u < kRing; ++u) {
+        const int k = kbeg + u;
+        const int o = k <= kend ? MBP_RM_OFF(k) : -1;
+        rp[u] = po[o >= 0 ? o : 0];
+        rf[u] = fq[o >= 0 ? o : 0];
+    }
+    T w4 = T(0), w3 = T(0), w2 = T(0), w1 = T(0);  // p of rows k-4 .. k-1
+    T g3 = T(0), g2 = T(0), g1 = T(0);             // f of rows k-3 .. k-1
+    double nrm = 0.0, pnr = 0.0;
+    T acc = T(0);
+    for (int k0 = kbeg; k0 <= kend; k0 += kRing) {
+#pragma unroll
+        for (int u = 0; u < kRing; ++u) {
+            // steps past the last row only relax rows that are never stored;
+            // keeping every step (and every load) unconditional leaves no
+            // branch joining on a value in flight
+            const int k = k0 + u;
+            {
+                const bool here = k <= kend && MBP_RM_OFF(k) >= 0;
+                const T p0 = (here && !zin) ? rp[u] : T(0), f0 = here ? rf[u] : T(0);
+                {
+                    const int kn = min(k + kRing, kend);
+                    const int o = MBP_RM_OFF(kn);
+                    rp[u] = po[o >= 0 ? o : 0];
+                    rf[u] = fq[o >= 0 ? o : 0];
+                }
+                // red cells of row k-1 (old black neighbours), then black cells of row k-2
+#pragma unroll
+                for (int colour = 0; colour < 2; ++colour) {
+                    const int kk = k - 1 - colour;
+                    if (kk < ty0 - 2 + colour) continue;
+                    const T v = colour == 0 ? w1 : w2;
+                    const T dn = colour == 0 ? w2 : w3;
+                    const T up = colour == 0 ? p0 : w1;
+                    const T fv = colour == 0 ? g1 : g2;
+                    const bool below = kk < 0, above = kk >= bny;
+                    const int cj = below ? ynym + kk : (above ? kk - bny : kk);
+                    // interior rows: one (scalar) table for the whole row; first
+                    // and last rows and halo rows: the lane's own block (faces
+                    // beyond may differ between joined blocks) from the wave's
+                    // table of the edge rows.  Both are read and the values
+                    // selected, so that no load goes through a generic pointer.
+                    const bool interior = kk > 0 && kk < bny - 1;
+                    const int ki = min(max(kk, 0), bny - 1);
+                    const int slot = min(max(kk <= 0 ? kk - kbeg : 4 + kk - (bny - 1), 0), 7);
+                    const T ys0 = T(dp[ycy0 + ki]), ys1 = T(dp[ycy0 + yny0 + ki]), ys2 = T(dp[ycy0 + 2 * yny0 + ki]);
+                    const T yl0 = sY[wave][slot][cr][0], yl1 = sY[wave][slot][cr][1], yl2 = sY[wave][slot][cr][2];
+                    const T ym = interior ? ys0 : yl0;
+                    const T yp = interior ? ys1 : yl1;
+                    const T yd = interior ? ys2 : yl2;
+                    T wm = xwm0, wp = xwp0, xd = xd0;
+                    int cc = ci, par = par0;
+                    bool alive = b0 >= 0;
+                    if (below) {
+                        wm = xwmm; wp = xwpm; xd = xdm; cc = cim; par = parm; alive = bm >= 0;
+                    } else if (above) {
+                        wm = xwmp; wp = xwpp; xd = xdp; cc = cip; par = parp; alive = bp >= 0;
+                    }
+                    const T xm = from_left(v), xp = from_right(v);
+                    const T nv = (fv - (wm * xm + wp * xp + ym * dn + yp * up)) / (xd + yd + sig);
+                    const bool mine = alive && ((cc + cj + par) & 1) == colour && lane >= 1 + colour &&
+                                      lane <= 62 - colour;
+                    if (colour == 0) w1 = mine ? nv : v;
+                    else w2 = mine ? nv : v;
+                }
+                // row k-2 is final
+                if (k - 2 >= ty0 && k - 2 < ty1 && out_lane) pn[off0 + (k - 2) * nx0] = w2;
+                // residual of row k-3 (rows k-4 .. k-2 are final)
+                const int kr = k - 3;
+                if ((RES || NRM) && kr >= ty0 && kr < ty1) {
+                    const T xm = from_left(w3), xp = from_right(w3);
+                    const T d = xd0 + T(dp[ycy0 + 2 * yny0 + kr]) + sig;
+                    T r = g3 - (xwm0 * xm + xwp0 * xp + T(dp[ycy0 + kr]) * w4 + T(dp[ycy0 + yny0 + kr]) * w2 +
+                                d * w3);
+                    if (!out_lane) r = T(0);
+                    if (NRM) {
+                        nrm += double(r) * double(r);
+                        pnr += out_lane ? double(w3) * double(w3) : 0.0;
+                    }
+                    if (RES) {
+                        const T rw = r * wrx * T(dp[rwy + kr]);
+                        const T r1 = from_right(rw);
+                        T sx = rw + r1;
+                        if (three) sx += from_right(r1);
+                        acc += sx;
+                        const int J = min(kr >> 1, ncy - 1);
+                        const int Jn = kr + 1 < ty1 ? min((kr + 1) >> 1, ncy - 1) : -1;
+                        if (Jn != J) {
+                            if (leader) {
+                                const long long o = q * plane_c + bcoff + (long long)J * ncx + I;
+                                args.fc[o] = acc;
+                                if (args.pc) args.pc[o] = T(0);
+                            }
+                            acc = T(0);
+                        }
+                    }
+                }
+                w4 = w3;
+                w3 = w2;
+                w2 = w1;
+                w1 = p0;
+                g3 = g2;
+                g2 = g1;
+                g1 = f0;
+            }
+        }
+    }
+#undef MBP_RM_OFF
+    if (NRM) {
+        nrm = wave_sum63(nrm);
+        pnr = wave_sum63(pnr);
+        if (lane == 63) {
+            args.part[2 * ((long long)q * ntiles + tix)] = nrm;
+            args.part[2 * ((long long)q * ntiles + tix) + 1] = pnr;
+        }
+    }
+}
+
 // ------------------------------- host side -------------------------------
 
 // Strips of one level: x ranges of at most 58 columns and y ranges of at most
@@ -718,25 +972,34 @@ static MArgs<T> margs(const mbp_plan* P, int l, const T* pold, T* pnew, const T*
     a.act = act;
     a.nact = nact;
     a.part = P->d_part;
+    a.wg_target = P->wg_target;
     return a;
 }
 
 // Modes per workgroup: enough workgroups to fill the chip several times
 // over, each reusing its strip set-up for as many modes as that allows.
-static int modes_per_wg(int ntiles, int nitems) {
-    const long long target = 256LL * 12;
-    long long per = (long long)ntiles * nitems / target;
+static int modes_per_wg(int ntiles, int nitems, int target) {
+    long long per = (long long)ntiles * nitems / std::max(1, target);
     return int(std::max(1LL, std::min<long long>(kMaxModes, per)));
 }
 
 template <typename T, bool PRO, bool RES, bool NRM>
 static void launch_march(MArgs<T> a, int nitems, hipStream_t s) {
-    a.per = modes_per_wg(a.ntiles, nitems);
+    a.per = modes_per_wg(a.ntiles, nitems, a.wg_target);
     const int groups = (nitems + a.per - 1) / a.per;
     if constexpr (PRO)
         hipLaunchKernelGGL((k_tile_corr<T, NRM>), dim3(a.ntiles, groups), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL((k_tile<T, RES, NRM>), dim3(a.ntiles, groups), dim3(256), 0, s, a);
+}
+
+template <typename T, bool RES>
+static void launch_rmarch(const mbp_plan* P, int l, MArgs<T> a, int nitems, hipStream_t s) {
+    a.tiles = reinterpret_cast<const MTile*>(P->d_mtiles) + P->rtile_off[l];
+    a.ntiles = P->rtile_cnt[l];
+    const long long work = (long long)a.ntiles * nitems;
+    const int groups = int((work + 3) / 4);
+    hipLaunchKernelGGL((k_rmarch<T, RES, false>), dim3(groups), dim3(256), 0, s, a, a.dp);
 }
 
 // Pre-smoothing sweep of level l (old -> new) fused with the residual
@@ -747,7 +1010,8 @@ void march_pre(const mbp_plan* P, int l, const T* pold, T* pnew, const T* f, T* 
                const int* act, const int* nact, int nitems, bool zero_in, hipStream_t s) {
     MArgs<T> a = margs<T>(P, l, pold, pnew, f, nullptr, fc, pc, act, nact);
     a.zero_in = zero_in ? 1 : 0;
-    launch_march<T, false, true, false>(a, nitems, s);
+    if (P->use_rmarch[l]) launch_rmarch<T, true>(P, l, a, nitems, s);
+    else launch_march<T, false, true, false>(a, nitems, s);
 }
 
 // Plain sweep (extra smoothing steps).
@@ -756,7 +1020,8 @@ void march_sweep(const mbp_plan* P, int l, const T* pold, T* pnew, const T* f, c
                  const int* nact, int nitems, bool zero_in, hipStream_t s) {
     MArgs<T> a = margs<T>(P, l, pold, pnew, f, nullptr, nullptr, nullptr, act, nact);
     a.zero_in = zero_in ? 1 : 0;
-    launch_march<T, false, false, false>(a, nitems, s);
+    if (P->use_rmarch[l]) launch_rmarch<T, false>(P, l, a, nitems, s);
+    else launch_march<T, false, false, false>(a, nitems, s);
 }
 
 // Coarse-grid correction from level l+1 (ec) fused with a post-smoothing

@@ -19,6 +19,8 @@ void options_default(mbp_options* o) {
     o->max_cycles = 60;
     o->flags = 0;
     o->etol = 0.0;
+    o->inner = 2;
+    o->march = 0;
 }
 
 // Hyperbolic-tangent face clustering (Sec. 3.1, Table 2 caption).  Two-sided:
@@ -255,6 +257,15 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
         if (P->opt.nu1 < 0 || P->opt.nu2 < 0 || P->opt.nu1 + P->opt.nu2 < 1 || P->opt.nu1 > 8 ||
             P->opt.nu2 > 8 || P->opt.max_cycles < 1) {
             if (err) *err = "bad smoothing counts or max_cycles";
+            return MBP_ERR_INVALID;
+        }
+        if (P->opt.inner == 0) P->opt.inner = 2;
+        if (P->opt.inner < 1 || P->opt.inner > 8) {
+            if (err) *err = "bad inner cycle count";
+            return MBP_ERR_INVALID;
+        }
+        if (P->opt.march != 0 && P->opt.march != 1) {
+            if (err) *err = "bad pre-smoothing form";
             return MBP_ERR_INVALID;
         }
     } else {

@@ -87,6 +87,8 @@ std::string describe(const mbp_block_desc* blocks, int nblocks, const mbp_synth_
     put(&opt.nu2, sizeof(opt.nu2));
     put(&opt.max_cycles, sizeof(opt.max_cycles));
     put(&opt.etol, sizeof(opt.etol));
+    put(&opt.inner, sizeof(opt.inner));
+    put(&opt.march, sizeof(opt.march));
     return k;
 }
 

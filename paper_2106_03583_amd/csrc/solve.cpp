@@ -89,24 +89,39 @@ Layout layout(const mbp_plan* P, size_t ftile_bytes, size_t mtile_bytes, int npa
 
 constexpr int kMarchSeg = 22;  // rows per fused-sweep strip (the LDS tile height)
 
-// Fused-sweep strips of every level (host tables); fills march_ok.
+// Fused-sweep strips of every level (host tables); fills march_ok.  Two
+// sets per level: short strips for the LDS form, tall ones for the
+// register march; both live in one descriptor array.
+constexpr int kRMarchSeg = 128;  // rows per register-march strip
+
 void plan_march_tables(mbp_plan* P, std::vector<unsigned char>& bytes) {
     P->march_ok.assign(P->nlev, 0);
     P->mtile_off.assign(P->nlev, 0);
     P->mtile_cnt.assign(P->nlev, 0);
+    P->rtile_off.assign(P->nlev, 0);
+    P->rtile_cnt.assign(P->nlev, 0);
+    P->use_rmarch.assign(P->nlev, 0);
     bytes.clear();
     int off = 0;
     for (int l = 0; l < P->nlev; ++l) {
         P->march_ok[l] = march_level_ok(P, l) ? 1 : 0;
         if (!P->march_ok[l]) continue;
-        std::vector<unsigned char> b;
-        int cnt = 0;
-        march_build_tiles_bytes(P, l, kMarchSeg, b, &cnt);
-        P->mtile_off[l] = off;
-        P->mtile_cnt[l] = cnt;
-        off += cnt;
-        bytes.insert(bytes.end(), b.begin(), b.end());
+        for (int set = 0; set < 2; ++set) {
+            std::vector<unsigned char> b;
+            int cnt = 0;
+            march_build_tiles_bytes(P, l, set == 0 ? kMarchSeg : kRMarchSeg, b, &cnt);
+            (set == 0 ? P->mtile_off : P->rtile_off)[l] = off;
+            (set == 0 ? P->mtile_cnt : P->rtile_cnt)[l] = cnt;
+            off += cnt;
+            bytes.insert(bytes.end(), b.begin(), b.end());
+        }
+        P->use_rmarch[l] = char(P->opt.march);  // the autotuner may change it per level
     }
+}
+
+static int partial_count(const mbp_plan* P) {
+    if (P->mtile_cnt.empty()) return 0;
+    return std::max(4 * P->mtile_cnt[0], P->rtile_cnt[0]);
 }
 
 size_t plan_device_bytes(const mbp_plan* P) {
@@ -116,14 +131,14 @@ size_t plan_device_bytes(const mbp_plan* P) {
     const int W = fft_columns_per_wg(P);
     size_t nt = 0;
     for (int b = 0; b < P->g.nb; ++b) nt += (size_t(P->g.nx[b]) * P->g.ny[b] + W - 1) / W;
-    return layout(&tmp, nt * 32, mt.size(), tmp.mtile_cnt.empty() ? 0 : 4 * tmp.mtile_cnt[0]).total;
+    return layout(&tmp, nt * 32, mt.size(), partial_count(&tmp)).total;
 }
 
 int plan_device_init(mbp_plan* P) {
     std::vector<unsigned char> ftf, fti, mt;
     fft_build_tiles(P, ftf, fti, &P->fft_ntiles);
     plan_march_tables(P, mt);
-    Layout L = layout(P, ftf.size(), mt.size(), 4 * P->mtile_cnt[0]);
+    Layout L = layout(P, ftf.size(), mt.size(), partial_count(P));
     void* mem = nullptr;
     if (hipMalloc(&mem, L.total) != hipSuccess) {
         (void)hipGetLastError();
@@ -331,8 +346,11 @@ void ctx_vcycle(SolveCtx& c, hipStream_t s) {
     mbp_plan* P = c.P;
     const bool zero = c.cycles == 0 && !c.warm;
     if (c.mixed) {
-        launch_vcycle<float>(P, P->p32[0], P->p32B[0], P->f32[0], P->d_act, P->d_nact, c.nitems, false, true,
-                             s);
+        // refinement step: the FP32 correction equation is solved by `inner`
+        // V-cycles from zero, then the correction is added in FP64
+        for (int k = 0; k < P->opt.inner; ++k)
+            launch_vcycle<float>(P, P->p32[0], P->p32B[0], P->f32[0], P->d_act, P->d_nact, c.nitems, false,
+                                 k == 0, s);
         launch_add_correction(P, P->phat, P->p32[0], P->d_act, P->d_nact, c.nitems, s);
     } else {
         c.fused_parts = launch_vcycle<double>(P, P->phat, P->phatB, P->fhat, P->d_act, P->d_nact, c.nitems,

@@ -282,3 +282,45 @@ def test_full_size_lshape(torch_cuda, mbp, precision):
 def test_full_size_box(torch_cuda, mbp, precision):
     print(f"full-size box {precision}", flush=True)
     _full_size_case(torch_cuda, mbp, W.config3(), W.CONFIG_SEEDS[3], W.CONFIG_DIST[3], precision, [0, 1, 1023])
+
+
+# ---------------------------------------------------------------------------
+# Schedules: the register-march pre-smoothing form and the plan autotuner must
+# leave the answer unchanged.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("prob", _global_problems(), ids=lambda p: p.name)
+def test_register_march_form(torch_cuda, mbp, prob, precision):
+    torch = torch_cuda
+    print(f"register march {prob.name} {precision}", flush=True)
+    f = W.rhs(prob, 33)
+    ref = oracle.solve(prob, f)
+    fproj = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
+    plan = mbp.Plan(prob, precision=precision, march=1)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.PROJECT_RHS | mbp.RETIRE)
+    got = host(p)
+    res = oracle.rel_residual(prob, got, fproj)
+    err = oracle.rel_error(got, ref)
+    print(f"  {info} residual={res:.2e} error={err:.2e}", flush=True)
+    assert info.status == 0 and res <= 1e-10 and err <= 1e-9
+    plan.close()
+
+
+@pytest.mark.parametrize("prob", [W.lshape(96, 6, 1.5, 1.0), _global_problems()[2]], ids=lambda p: p.name)
+def test_plan_autotune(torch_cuda, mbp, prob):
+    torch = torch_cuda
+    f = W.rhs(prob, 35)
+    fd = dev(torch, f)
+    plan = mbp.Plan(prob)
+    t = plan.autotune(fd)
+    print(f"  tuning {prob.name}: {t}", flush=True)
+    assert t["ms_tuned"] <= t["ms_default"] + 1e-9
+    assert t["wg_target"] > 0 and all(x in (0, 1) for x in t["form"])
+    p = torch.zeros_like(fd)
+    info = plan.solve(fd, p, rtol=1e-10, flags=mbp.PROJECT_RHS | mbp.RETIRE)
+    ref = oracle.solve(prob, f)
+    assert info.status == 0
+    assert oracle.rel_error(host(p), ref) <= 1e-9
+    plan.close()
