@@ -160,6 +160,25 @@ __device__ __forceinline__ double dpp_move(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// a / d by a hardware reciprocal refined with Newton-Raphson steps and one
+// residual correction of the quotient (d is a nonzero diagonal of moderate
+// magnitude here; within an ulp or two of the rounded quotient).
+__device__ __forceinline__ double div_nr(double a, double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    const double q = a * r;
+    return fma(fma(-d, q, a), r, q);
+}
+__device__ __forceinline__ float div_nr(float a, float d) {
+    float r = __builtin_amdgcn_rcpf(d);
+    r = fmaf(r, fmaf(-d, r, 1.0f), r);
+    const float q = a * r;
+    return fmaf(fmaf(-d, q, a), r, q);
+}
+
 __device__ __forceinline__ double wave_sum63(double v) {
     v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
     v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]: every lane holds its quad's sum
@@ -489,30 +508,43 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
         }
 
         // red on rows 1 .. nrow-2 / lanes 1 .. 62, then black on rows
-        // 2 .. nrow-3 / lanes 2 .. 61 (the valid region shrinks)
+        // 2 .. nrow-3 / lanes 2 .. 61 (the valid region shrinks).  Colours
+        // alternate down a column (the block parities keep the checkerboard
+        // across joined faces), so of two consecutive rows each lane relaxes
+        // exactly one: rows go in pairs with every lane busy.
 #pragma unroll
         for (int colour = 0; colour < 2; ++colour) {
             if (lane >= 1 + colour && lane <= 62 - colour) {
 #pragma unroll
-                for (int m = 0; m < kRowsPerWave; ++m) {
-                    const int r = rbase + m;
-                    if (!((amask >> m) & 1u) || r < 1 + colour || r > nrow - 2 - colour) continue;
+                for (int m = 0; m < kRowsPerWave; m += 2) {
+                    bool mine[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int mm = m + h;
+                        const int r = rbase + mm;
+                        mine[h] = false;
+                        if (mm < kRowsPerWave && ((amask >> mm) & 1u) && r >= 1 + colour && r <= nrow - 2 - colour) {
+                            const int k = ty0 - 3 + r;
+                            const int sc = scol[r][cr];
+                            const int cc = k < 0 ? cim : (k >= bny ? cip : ci);
+                            mine[h] = sc >= 0 && ((cc + sc) & 1) == colour;
+                        }
+                    }
+                    if (!mine[0] && !mine[1]) continue;
+                    const int r = rbase + m + (mine[0] ? 0 : 1);
                     const int k = ty0 - 3 + r;
-                    const int sc = scol[r][cr];
                     const bool below = k < 0, above = k >= bny;
-                    const int cc = below ? cim : (above ? cip : ci);
-                    if (sc < 0 || ((cc + sc) & 1) != colour) continue;
                     T wm = xwm0, wp = xwp0, xd = xd0;
                     if (below || above) {
-                        const int h = below ? 0 : 1;
-                        wm = sxc[h][0][lane];
-                        wp = sxc[h][1][lane];
-                        xd = sxc[h][2][lane];
+                        const int hh = below ? 0 : 1;
+                        wm = sxc[hh][0][lane];
+                        wp = sxc[hh][1][lane];
+                        xd = sxc[hh][2][lane];
                     }
                     const T d = xd + T(sy[r][cr][2]) + sig;
                     const T off = wm * sp[r][lane - 1] + wp * sp[r][lane + 1] + T(sy[r][cr][0]) * sp[r - 1][lane] +
                                   T(sy[r][cr][1]) * sp[r + 1][lane];
-                    sp[r][lane] = (sf[r][lane] - off) / d;
+                    sp[r][lane] = div_nr(sf[r][lane] - off, d);
                 }
             }
             __syncthreads();
@@ -586,9 +618,9 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
 }
 
 // Sweep kernels.  The correction form holds more state per lane; it is
-// capped at three waves per SIMD, the others keep the compiler's choice.
+// capped at three waves per SIMD, the others at four.
 template <typename T, bool RES, bool NRM>
-__global__ void __launch_bounds__(256) k_tile(const MArgs<T> args) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_tile(const MArgs<T> args) {
     tile_sweep<T, false, RES, NRM>(args);
 }
 
