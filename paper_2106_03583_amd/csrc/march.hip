@@ -444,6 +444,30 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
 
     issue_pf(args.act[i0]);
     __syncthreads();  // strip tables ready
+    // Rows go in pairs (m, m + 1): colours alternate down a column (the block
+    // parities keep the checkerboard across joined faces), so of a pair each
+    // lane relaxes at most one row per colour.  relax: pairs with a cell of
+    // the colour; pick: that cell is in the second row.  Red covers rows
+    // 1 .. nrow-2 / lanes 1 .. 62, black rows 2 .. nrow-3 / lanes 2 .. 61
+    // (the valid region shrinks).
+    constexpr int kPairs = (kRowsPerWave + 1) / 2;
+    unsigned relax[2] = {0u, 0u}, pick[2] = {0u, 0u};
+#pragma unroll
+    for (int colour = 0; colour < 2; ++colour) {
+        if (lane < 1 + colour || lane > 62 - colour) continue;
+#pragma unroll
+        for (int m = 0; m < kRowsPerWave; ++m) {
+            const int r = rbase + m;
+            if (!((amask >> m) & 1u) || r < 1 + colour || r > nrow - 2 - colour) continue;
+            const int k = ty0 - 3 + r;
+            const int sc = scol[r][cr];
+            const int cc = k < 0 ? cim : (k >= bny ? cip : ci);
+            if (sc >= 0 && ((cc + sc) & 1) == colour && !((relax[colour] >> (m >> 1)) & 1u)) {
+                relax[colour] |= 1u << (m >> 1);
+                if (m & 1) pick[colour] |= 1u << (m >> 1);
+            }
+        }
+    }
     int cyb = kNoRow;  // first coarse row the wave stages for its own rows
     if (PRO) {
         for (int m = 0; m < kRowsPerWave; ++m) {
@@ -507,48 +531,71 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
             if (PRO) issue_e(sq[it + 1 - i0], cyb);
         }
 
-        // red on rows 1 .. nrow-2 / lanes 1 .. 62, then black on rows
-        // 2 .. nrow-3 / lanes 2 .. 61 (the valid region shrinks).  Colours
-        // alternate down a column (the block parities keep the checkerboard
-        // across joined faces), so of two consecutive rows each lane relaxes
-        // exactly one: rows go in pairs with every lane busy.
+        // One red-black sweep over the pairs chosen above.  Cells of one
+        // colour never neighbour each other, so in FP32 the reads of the next
+        // row pair are issued before the current pair's value is written and
+        // LDS latency overlaps the arithmetic of the previous pair.  FP64 runs
+        // one pair at a time: two pairs in flight do not fit its register
+        // budget next to the next mode's prefetched loads.
+        static_assert(kPairs == 4, "the FP32 sweep is written out for four row pairs");
+#define MBP_PAIR_LOAD(P, pi)                                                                       \
+    {                                                                                              \
+        const int rr_ = max(min(rbase + 2 * (pi) + int((pick[colour] >> (pi)) & 1u), kLdsRows - 2), 1) + zr; \
+        const int k_ = ty0 - 3 + rr_;                                                              \
+        P.wm = xwm0;                                                                               \
+        P.wp = xwp0;                                                                               \
+        T xd_ = xd0;                                                                               \
+        if (k_ < 0 || k_ >= bny) {                                                                 \
+            const int hh_ = k_ < 0 ? 0 : 1;                                                        \
+            P.wm = sxc[hh_][0][la];                                                                \
+            P.wp = sxc[hh_][1][la];                                                                \
+            xd_ = sxc[hh_][2][la];                                                                 \
+        }                                                                                          \
+        P.d = xd_ + T(sy[rr_][cr][2]) + sig;                                                       \
+        P.y0 = T(sy[rr_][cr][0]);                                                                  \
+        P.y1 = T(sy[rr_][cr][1]);                                                                  \
+        P.pl = sp[rr_][la - 1];                                                                    \
+        P.pr = sp[rr_][la + 1];                                                                    \
+        P.pd = sp[rr_ - 1][la];                                                                    \
+        P.pu = sp[rr_ + 1][la];                                                                    \
+        P.f = sf[rr_][la];                                                                         \
+    }
+#define MBP_PAIR_DONE(P, pi)                                                                       \
+    {                                                                                              \
+        const T off_ = P.wm * P.pl + P.wp * P.pr + P.y0 * P.pd + P.y1 * P.pu;                     \
+        const T v_ = div_nr(P.f - off_, P.d);                                                      \
+        if ((relax[colour] >> (pi)) & 1u) sp[rbase + 2 * (pi) + int((pick[colour] >> (pi)) & 1u)][lane] = v_; \
+    }
 #pragma unroll
         for (int colour = 0; colour < 2; ++colour) {
-            if (lane >= 1 + colour && lane <= 62 - colour) {
+            const int la = min(max(lane, 1), 62);
+            // an opaque zero: the coefficient reads stay inside the mode loop
+            // instead of being hoisted into registers for every pair
+            int zr;
+            asm volatile("v_mov_b32 %0, 0" : "=v"(zr));
+            if constexpr (sizeof(T) == 4) {
+                struct { T wm, wp, d, y0, y1, pl, pr, pd, pu, f; } A, B;
+                MBP_PAIR_LOAD(A, 0)
+                MBP_PAIR_LOAD(B, 1)
+                MBP_PAIR_DONE(A, 0)
+                MBP_PAIR_LOAD(A, 2)
+                MBP_PAIR_DONE(B, 1)
+                MBP_PAIR_LOAD(B, 3)
+                MBP_PAIR_DONE(A, 2)
+                MBP_PAIR_DONE(B, 3)
+            } else {
 #pragma unroll
-                for (int m = 0; m < kRowsPerWave; m += 2) {
-                    bool mine[2];
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int mm = m + h;
-                        const int r = rbase + mm;
-                        mine[h] = false;
-                        if (mm < kRowsPerWave && ((amask >> mm) & 1u) && r >= 1 + colour && r <= nrow - 2 - colour) {
-                            const int k = ty0 - 3 + r;
-                            const int sc = scol[r][cr];
-                            const int cc = k < 0 ? cim : (k >= bny ? cip : ci);
-                            mine[h] = sc >= 0 && ((cc + sc) & 1) == colour;
-                        }
-                    }
-                    if (!mine[0] && !mine[1]) continue;
-                    const int r = rbase + m + (mine[0] ? 0 : 1);
-                    const int k = ty0 - 3 + r;
-                    const bool below = k < 0, above = k >= bny;
-                    T wm = xwm0, wp = xwp0, xd = xd0;
-                    if (below || above) {
-                        const int hh = below ? 0 : 1;
-                        wm = sxc[hh][0][lane];
-                        wp = sxc[hh][1][lane];
-                        xd = sxc[hh][2][lane];
-                    }
-                    const T d = xd + T(sy[r][cr][2]) + sig;
-                    const T off = wm * sp[r][lane - 1] + wp * sp[r][lane + 1] + T(sy[r][cr][0]) * sp[r - 1][lane] +
-                                  T(sy[r][cr][1]) * sp[r + 1][lane];
-                    sp[r][lane] = div_nr(sf[r][lane] - off, d);
+                for (int pi = 0; pi < kPairs; ++pi) {
+                    if (!((relax[colour] >> pi) & 1u)) continue;
+                    struct { T wm, wp, d, y0, y1, pl, pr, pd, pu, f; } A;
+                    MBP_PAIR_LOAD(A, pi)
+                    MBP_PAIR_DONE(A, pi)
                 }
             }
             __syncthreads();
         }
+#undef MBP_PAIR_LOAD
+#undef MBP_PAIR_DONE
 
         // store, residual (weighted for the restriction, squared for the norm)
         double nrm = 0.0, pnr = 0.0;

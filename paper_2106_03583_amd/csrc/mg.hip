@@ -649,7 +649,7 @@ __device__ LdsView<T> lds_view(const LdsArgs& a, unsigned char* raw) {
 
 // One V-cycle on levels L.. of every active mode: f_L in, p_L out (from 0).
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_lds_vcycle(LdsArgs a, T* __restrict__ pL, const T* __restrict__ fL, long long planeL,
              const double* __restrict__ shift, const int* __restrict__ act,
              const int* __restrict__ nact) {
@@ -683,7 +683,7 @@ __device__ double lds_block_sum(double x, double* red) {
 // Whole solve of one mode in LDS (the plane's full hierarchy fits): iterate
 // V-cycles until ||r_q||^2 <= rtol2 ||f_q||^2 or maxc cycles; each mode stops
 // on its own (early retirement).
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_lds_full(LdsArgs a, double* __restrict__ p0, const double* __restrict__ f0, long long plane,
            const double* __restrict__ shift, const double* __restrict__ sabs,
            const int* __restrict__ act, const int* __restrict__ nact, int maxc, double rtol2,
@@ -736,6 +736,10 @@ k_lds_full(LdsArgs a, double* __restrict__ p0, const double* __restrict__ f0, lo
 }
 
 // ================================ launchers ================================
+
+// Threads of an LDS-resident workgroup: one workgroup holds a whole CU's LDS,
+// so it brings its own waves to hide the latency of its sweeps.
+static int lds_threads(int64_t plane) { return plane >= 4096 ? 1024 : plane >= 1024 ? 512 : 256; }
 
 static LdsArgs lds_args(const mbp_plan* P, int L) {
     LdsArgs a{};
@@ -839,7 +843,7 @@ int launch_vcycle(const mbp_plan* P, T* p0, T* p0B, T* f0, const int* act, const
         LdsArgs a = lds_args(P, L);
         const size_t bytes = size_t(is32 ? P->lds_bytes32 : P->lds_bytes64);
         set_lds(reinterpret_cast<const void*>(k_lds_vcycle<T>), bytes);
-        hipLaunchKernelGGL(k_lds_vcycle<T>, dim3(nitems), dim3(256), bytes, s, a, P_(L), F_(L),
+        hipLaunchKernelGGL(k_lds_vcycle<T>, dim3(nitems), dim3(lds_threads(P->levels[L].plane)), bytes, s, a, P_(L), F_(L),
                            (long long)P->levels[L].plane, P->d_shift, act, nact);
     }
     int nparts = 0;
@@ -909,7 +913,7 @@ void launch_lds_full(const mbp_plan* P, double* p, const double* f, const int* a
     LdsArgs a = lds_args(P, 0);
     const size_t bytes = size_t(P->lds_bytes64);
     set_lds(reinterpret_cast<const void*>(k_lds_full), bytes);
-    hipLaunchKernelGGL(k_lds_full, dim3(nitems), dim3(256), bytes, s, a, p, f,
+    hipLaunchKernelGGL(k_lds_full, dim3(nitems), dim3(lds_threads(P->plane0)), bytes, s, a, p, f,
                        (long long)P->plane0, P->d_shift, P->d_sabs, act, nact, maxc, rtol2, etol2, cyc,
                        rnorm, fnorm);
 }
