@@ -120,7 +120,16 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
     for (int i = 0; i < count && status == MBP_OK; ++i) ctx_check(cx[i]);
 
     // problems whose whole hierarchy fits in LDS: one launch each; the
-    // others run their first cycle (from zero) eagerly
+    // others run their first cycle (from zero) eagerly, unless they all take
+    // the grouped form, whose captured cycles do not depend on the iterate
+    bool all_grouped = true;
+    int inner0 = -1;
+    for (int i = 0; i < count; ++i) {
+        const SolveCtx& c = cx[i];
+        if (c.done || c.full_lds) continue;
+        if (inner0 < 0) inner0 = c.P->opt.inner;
+        all_grouped = all_grouped && group_ok(c) && c.P->opt.inner == inner0;
+    }
     if (status == MBP_OK) {
         fork(s, S);
         for (int i = 0; i < count; ++i) {
@@ -133,6 +142,7 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
                 c.done = true;
                 continue;
             }
+            if (all_grouped) continue;
             ctx_test(c, st[i % S]);
             ctx_vcycle(c, st[i % S]);
         }
@@ -141,6 +151,8 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
 
     // captured cycles, replayed until every problem is done
     Graph G;
+    void* table = nullptr;  // stage tables of the grouped form
+    size_t table_bytes = 0;
     size_t trial = 0;
     BatchTune cur = trials.empty() ? tune : trials[0];
     double best_cost = 1e300;
@@ -161,18 +173,66 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
                          modes * 4 < G.modes * 3;
         if (recapture) {
             G.reset();
+            // grouped form: every unfinished problem is a mixed strip V-cycle
+            // with the same inner cycle count
+            bool grouped = true;
+            for (int i : act)
+                grouped = grouped && group_ok(cx[i]) && cx[i].P->opt.inner == cx[act[0]].P->opt.inner;
+            std::vector<GStage> stages;
+            if (grouped) {
+                std::vector<SolveCtx*> cs;
+                int maxL = 0;
+                for (int i : act) {
+                    cs.push_back(&cx[i]);
+                    maxL = std::max(maxL, cx[i].P->lds_level32);
+                }
+                GroupBlob gb;
+                stages.push_back(group_res32(gb, cs));
+                stages.push_back(group_finish(gb, cs));
+                stages.push_back(group_update(gb, cs));
+                for (int k = 0; k < cx[act[0]].P->opt.inner; ++k) {
+                    for (int l = 0; l < maxL; ++l) stages.push_back(group_march32(gb, cs, l, false, k == 0));
+                    stages.push_back(group_lds32(gb, cs));
+                    for (int l = maxL - 1; l >= 0; --l) stages.push_back(group_march32(gb, cs, l, true, false));
+                }
+                stages.push_back(group_addcorr(gb, cs));
+                if (gb.host.size() > table_bytes) {
+                    if (table) (void)hipFree(table);
+                    table = nullptr;
+                    table_bytes = 0;
+                    if (hipMalloc(&table, gb.host.size()) != hipSuccess) {
+                        fail(MBP_ERR_NOMEM);
+                        break;
+                    }
+                    table_bytes = gb.host.size();
+                }
+                if (hipMemcpy(table, gb.host.data(), gb.host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+                    fail(MBP_ERR_HIP);
+                    break;
+                }
+            }
             if (hipStreamBeginCapture(st[0], hipStreamCaptureModeThreadLocal) != hipSuccess) {
                 fail(MBP_ERR_HIP);
                 break;
             }
-            fork(st[0], Sc);
-            for (int it = 0; it < cur.chunk; ++it)
-                for (size_t a = 0; a < act.size(); ++a) {
-                    SolveCtx& c = cx[act[a]];
-                    ctx_test(c, st[a % Sc]);
-                    ctx_vcycle(c, st[a % Sc]);
-                }
-            join(st[0], Sc);
+            if (grouped) {
+                const unsigned char* dev = static_cast<const unsigned char*>(table);
+                for (int it = 0; it < cur.chunk; ++it)
+                    for (const GStage& g : stages) {
+                        if (g.kind == G_PRE32 || g.kind == G_POST32) group_launch_march(g, dev, st[0]);
+                        else group_launch_mg(g, dev, st[0]);
+                    }
+                for (int i : act) cx[i].cycles += cur.chunk;
+            } else {
+                fork(st[0], Sc);
+                for (int it = 0; it < cur.chunk; ++it)
+                    for (size_t a = 0; a < act.size(); ++a) {
+                        SolveCtx& c = cx[act[a]];
+                        ctx_test(c, st[a % Sc]);
+                        ctx_vcycle(c, st[a % Sc]);
+                    }
+                join(st[0], Sc);
+            }
             if (hipStreamEndCapture(st[0], &G.g) != hipSuccess ||
                 hipGraphInstantiate(&G.e, G.g, nullptr, nullptr, 0) != hipSuccess) {
                 (void)hipGetLastError();
@@ -216,6 +276,7 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
         for (int i : act) ctx_state_apply(cx[i]);
     }
     G.reset();
+    if (table) (void)hipFree(table);
     if (trial > 0 && trial < trials.size()) {
         // the batch finished before every candidate ran: keep the best seen
         std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -6,6 +6,7 @@
 #include <array>
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -265,5 +266,79 @@ void ctx_state_apply(SolveCtx& c);              // after that readback synchroni
 void ctx_epilogue(SolveCtx& c, hipStream_t s);
 int ctx_info(SolveCtx& c, hipStream_t s, mbp_solve_info* info);  // synchronises s
 int plan_autotune(mbp_plan* P, const double* rhs, hipStream_t s, mbp_tuning* out);
+
+// ---- grouped launches: one launch runs one stage of the refinement step for
+//      many problems.  Workgroups [wg0, next entry's wg0) belong to job `job`;
+//      a workgroup's local index splits into (bx, by) with gx columns. ----
+struct GEnt {
+    int wg0, gx, job, pad;
+};
+enum GKind { G_RES32 = 0, G_FINISH, G_UPDATE, G_PRE32, G_LDS32, G_POST32, G_ADDCORR };
+struct GStage {
+    int kind = 0;
+    int wgs = 0;            // workgroups of the launch
+    int nent = 0;
+    size_t ent_off = 0;     // byte offsets in the table image
+    size_t job_off = 0;
+    size_t lds = 0;         // dynamic LDS bytes (LDS-resident stage)
+    int threads = 256;
+};
+// Host image of the tables of every stage; uploaded once per capture.
+struct GroupBlob {
+    std::vector<unsigned char> host;
+    size_t add(const void* src, size_t bytes) {
+        const size_t off = (host.size() + 255) & ~size_t(255);
+        host.resize(off + bytes);
+        if (bytes) std::memcpy(host.data() + off, src, bytes);
+        return off;
+    }
+};
+// Stage record for jobs with (gx, gy) workgroups each; empty jobs are skipped.
+template <typename Job>
+GStage group_build(GroupBlob& gb, int kind, const std::vector<Job>& jobs, const std::vector<int>& gx,
+                   const std::vector<int>& gy) {
+    std::vector<GEnt> ents;
+    long long wg = 0;
+    for (size_t i = 0; i < jobs.size(); ++i) {
+        const long long n = (long long)gx[i] * gy[i];
+        if (n <= 0) continue;
+        ents.push_back(GEnt{int(wg), gx[i], int(i), 0});
+        wg += n;
+    }
+    GStage st;
+    st.kind = kind;
+    st.wgs = int(wg);
+    st.nent = int(ents.size());
+    st.ent_off = gb.add(ents.data(), ents.size() * sizeof(GEnt));
+    st.job_off = gb.add(jobs.data(), jobs.size() * sizeof(Job));
+    return st;
+}
+// Job of this workgroup in a grouped launch, and its (bx, by) inside the job.
+__device__ __forceinline__ int group_locate(const GEnt* __restrict__ e, int n, int& bx, int& by) {
+    const int g = blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (e[mid].wg0 <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const int local = g - e[lo].wg0;
+    bx = local % e[lo].gx;
+    by = local / e[lo].gx;
+    return e[lo].job;
+}
+// A problem joins the grouped form when every level above its LDS-resident
+// ones runs the strip kernels (mixed precision, one pre- and one post-sweep).
+bool group_ok(const SolveCtx& c);
+// Stage tables for the problems `cs` (phase 1, host only) ...
+GStage group_res32(GroupBlob& gb, const std::vector<SolveCtx*>& cs);
+GStage group_finish(GroupBlob& gb, const std::vector<SolveCtx*>& cs);
+GStage group_update(GroupBlob& gb, const std::vector<SolveCtx*>& cs);
+GStage group_lds32(GroupBlob& gb, const std::vector<SolveCtx*>& cs);
+GStage group_addcorr(GroupBlob& gb, const std::vector<SolveCtx*>& cs);
+GStage group_march32(GroupBlob& gb, const std::vector<SolveCtx*>& cs, int level, bool post, bool zero0);
+// ... and their launches from the uploaded image (phase 2, capturable).
+void group_launch_mg(const GStage& st, const unsigned char* dev, hipStream_t s);
+void group_launch_march(const GStage& st, const unsigned char* dev, hipStream_t s);
 
 }  // namespace mbp

@@ -231,7 +231,7 @@ __device__ __forceinline__ int block_at(const DBlock* __restrict__ B, int tb, in
 }
 
 template <typename T, bool PRO, bool RES, bool NRM>
-__device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
+__device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) {
     // argument fields as scalars (no reference to the argument block survives)
     const DBlock* __restrict__ aB = args.B;
     const DBlock* __restrict__ aBc = args.Bc;
@@ -259,9 +259,9 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
     __shared__ double ssig[kMaxModes];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tix = xcd_remap_m(blockIdx.x, ntiles);
+    const int tix = xcd_remap_m(bx, ntiles);
     const int nact = *args.nact;
-    const int i0 = blockIdx.y * per;
+    const int i0 = by * per;
     const int i1 = min(i0 + per, nact);
     if (i0 >= i1) return;
     const MTile& t = args.tiles[tix];
@@ -668,12 +668,22 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args) {
 // capped at three waves per SIMD, the others at four.
 template <typename T, bool RES, bool NRM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_tile(const MArgs<T> args) {
-    tile_sweep<T, false, RES, NRM>(args);
+    tile_sweep<T, false, RES, NRM>(args, blockIdx.x, blockIdx.y);
 }
 
 template <typename T, bool NRM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_tile_corr(const MArgs<T> args) {
-    tile_sweep<T, true, false, NRM>(args);
+    tile_sweep<T, true, false, NRM>(args, blockIdx.x, blockIdx.y);
+}
+
+// The FP32 pre- (restricting) or post- (correcting) sweep of one level for
+// many problems in one launch.
+template <bool PRO>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PRO ? 3 : 4)))
+k_tile_group(const GEnt* __restrict__ e, int n, const MArgs<float>* __restrict__ jobs) {
+    int bx, by;
+    const int j = group_locate(e, n, bx, by);
+    tile_sweep<float, PRO, !PRO, false>(jobs[j], bx, by);
 }
 
 // ------------------------- register march form of the sweep -------------------------
@@ -1125,5 +1135,46 @@ template void march_post<double>(const mbp_plan*, int, const double*, double*, c
                                  const double*, bool, const int*, const int*, int, hipStream_t);
 template void march_post<float>(const mbp_plan*, int, const float*, float*, const float*, const float*,
                                 bool, const int*, const int*, int, hipStream_t);
+
+bool group_ok(const SolveCtx& c) {
+    const mbp_plan* P = c.P;
+    if (!c.mixed || c.full_lds || P->opt.nu1 != 1 || P->opt.nu2 != 1) return false;
+    for (int l = 0; l < P->lds_level32; ++l)
+        if (!P->march_ok[l] || P->use_rmarch[l] || P->p32B[l] == nullptr) return false;
+    return true;
+}
+
+// Level `level` of every problem that has it above its LDS-resident levels:
+// pre-sweep A -> B with the restriction into level + 1, or correction from
+// level + 1 with the post-sweep B -> A (the buffers of the strip V-cycle).
+GStage group_march32(GroupBlob& gb, const std::vector<SolveCtx*>& cs, int level, bool post, bool zero0) {
+    std::vector<MArgs<float>> jobs;
+    std::vector<int> gx, gy;
+    for (const SolveCtx* c : cs) {
+        const mbp_plan* P = c->P;
+        if (level >= P->lds_level32) continue;
+        const int l = level;
+        MArgs<float> a = post ? margs<float>(P, l, P->p32B[l], P->p32[l], P->f32[l], P->p32[l + 1], nullptr,
+                                             nullptr, P->d_act, P->d_nact)
+                              : margs<float>(P, l, P->p32[l], P->p32B[l], P->f32[l], nullptr, P->f32[l + 1],
+                                             nullptr, P->d_act, P->d_nact);
+        a.zero_in = post ? 0 : ((l == 0 ? zero0 : true) ? 1 : 0);
+        a.per = modes_per_wg(a.ntiles, c->nitems, a.wg_target);
+        jobs.push_back(a);
+        gx.push_back(a.ntiles);
+        gy.push_back((c->nitems + a.per - 1) / a.per);
+    }
+    return group_build(gb, post ? G_POST32 : G_PRE32, jobs, gx, gy);
+}
+
+void group_launch_march(const GStage& st, const unsigned char* dev, hipStream_t s) {
+    if (st.wgs <= 0) return;
+    const GEnt* e = reinterpret_cast<const GEnt*>(dev + st.ent_off);
+    const MArgs<float>* j = reinterpret_cast<const MArgs<float>*>(dev + st.job_off);
+    if (st.kind == G_POST32)
+        hipLaunchKernelGGL(k_tile_group<true>, dim3(st.wgs), dim3(256), 0, s, e, st.nent, j);
+    else if (st.kind == G_PRE32)
+        hipLaunchKernelGGL(k_tile_group<false>, dim3(st.wgs), dim3(256), 0, s, e, st.nent, j);
+}
 
 }  // namespace mbp

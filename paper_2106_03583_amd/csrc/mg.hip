@@ -235,23 +235,35 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 
 // Per-tile partial sums of the squared finest-level residual of each mode;
 // mode == 1 also writes r as float32 (the refinement rhs) and zeroes e32.
+struct ResJob {
+    const DBlock* B;
+    const int4* tiles;
+    int ntiles;
+    const double* dp;
+    const double* p;
+    const double* f;
+    long long plane;
+    const double* shift;
+    const int* act;
+    const int* nact;
+    double* part;
+    float* r32;
+    float* e32;
+};
+
 template <int MODE>
-__global__ void __launch_bounds__(256)
-k_residual(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntiles,
-           const double* __restrict__ dp, const double* __restrict__ p,
-           const double* __restrict__ f, long long plane, const double* __restrict__ shift,
-           const int* __restrict__ act, const int* __restrict__ nact, double* __restrict__ part,
-           float* __restrict__ r32, float* __restrict__ e32) {
+__device__ __forceinline__ void residual_body(const ResJob& J, int bx, int item) {
     __shared__ double scratch[8];
-    const int item = blockIdx.y;
-    if (item >= *nact) return;
-    const int q = act[item];
-    const int tix = xcd_remap_mg(blockIdx.x, ntiles);
-    const int4 t = tiles[tix];
+    if (item >= *J.nact) return;
+    const DBlock* __restrict__ B = J.B;
+    const int q = J.act[item];
+    const int ntiles = J.ntiles;
+    const int tix = xcd_remap_mg(bx, ntiles);
+    const int4 t = J.tiles[tix];
     const DBlock b = B[t.x];
-    const double* pq = p + q * plane;
-    const double* fq = f + q * plane;
-    const double sig = shift[q];
+    const double* __restrict__ pq = J.p + q * J.plane;
+    const double* __restrict__ fq = J.f + q * J.plane;
+    const double sig = J.shift[q];
     const int i = t.y + threadIdx.x;
     double acc = 0.0, pacc = 0.0;
     if (i < b.nx) {
@@ -259,21 +271,26 @@ k_residual(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int nti
             const int j = t.z + r;
             if (j >= b.ny) break;
             const long long c = b.off + j * b.nx + i;
-            const double res = fq[c] - apply_at(pq, B, b, dp, i, j, sig);
+            const double res = fq[c] - apply_at(pq, B, b, J.dp, i, j, sig);
             acc += res * res;
             pacc += pq[c] * pq[c];
             if (MODE == 1) {
-                r32[q * plane + c] = float(res);
-                e32[q * plane + c] = 0.0f;
+                J.r32[q * J.plane + c] = float(res);
+                J.e32[q * J.plane + c] = 0.0f;
             }
         }
     }
     const double s = block_sum(acc, scratch);
     const double sp = block_sum(pacc, scratch);
     if (threadIdx.x == 0 && threadIdx.y == 0) {
-        part[2 * ((long long)q * ntiles + tix)] = s;
-        part[2 * ((long long)q * ntiles + tix) + 1] = sp;
+        J.part[2 * ((long long)q * ntiles + tix)] = s;
+        J.part[2 * ((long long)q * ntiles + tix) + 1] = sp;
     }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_residual(const ResJob J) {
+    residual_body<MODE>(J, blockIdx.x, blockIdx.y);
 }
 
 // Per-tile partial sums of fhat_q^2.
@@ -304,53 +321,93 @@ k_sumsq(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntiles
 
 // Deterministic per-mode reduction of the tile partial pairs (one workgroup
 // per item): out[q] = sum of first entries, out2[q] (optional) of seconds.
-__global__ void __launch_bounds__(256)
-k_finish(const double* __restrict__ part, int ntiles, const int* __restrict__ act,
-         const int* __restrict__ nact, double* __restrict__ out, double* __restrict__ out2) {
+struct FinJob {
+    const double* part;
+    int ntiles;
+    const int* act;
+    const int* nact;
+    double* out;
+    double* out2;
+};
+
+__device__ __forceinline__ void finish_body(const FinJob& J, int item) {
     __shared__ double scratch[8];
-    const int item = blockIdx.x;
-    if (act && item >= *nact) return;
-    const int q = act ? act[item] : item;
+    if (J.act && item >= *J.nact) return;
+    const int q = J.act ? J.act[item] : item;
+    const int ntiles = J.ntiles;
     double acc = 0.0, acc2 = 0.0;
     for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
-        acc += part[2 * ((long long)q * ntiles + t)];
-        acc2 += part[2 * ((long long)q * ntiles + t) + 1];
+        acc += J.part[2 * ((long long)q * ntiles + t)];
+        acc2 += J.part[2 * ((long long)q * ntiles + t) + 1];
     }
     const double s = block_sum(acc, scratch);
     const double s2 = block_sum(acc2, scratch);
     if (threadIdx.x == 0) {
-        out[q] = s;
-        if (out2) out2[q] = s2;
+        J.out[q] = s;
+        if (J.out2) J.out2[q] = s2;
     }
 }
 
-__global__ void __launch_bounds__(256)
-k_addcorr(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntiles,
-          double* __restrict__ p, const float* __restrict__ e, long long plane,
-          const int* __restrict__ act, const int* __restrict__ nact) {
-    const int item = blockIdx.y;
-    if (item >= *nact) return;
-    const int q = act[item];
-    const int4 t = tiles[xcd_remap_mg(blockIdx.x, ntiles)];
-    const DBlock b = B[t.x];
+__global__ void __launch_bounds__(256) k_finish(const FinJob J) { finish_body(J, blockIdx.x); }
+
+struct AddJob {
+    const DBlock* B;
+    const int4* tiles;
+    int ntiles;
+    double* p;
+    const float* e;
+    long long plane;
+    const int* act;
+    const int* nact;
+};
+
+__device__ __forceinline__ void addcorr_body(const AddJob& J, int bx, int item) {
+    if (item >= *J.nact) return;
+    const int q = J.act[item];
+    const int4 t = J.tiles[xcd_remap_mg(bx, J.ntiles)];
+    const DBlock b = J.B[t.x];
     const int i = t.y + threadIdx.x;
     if (i >= b.nx) return;
     for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
         const int j = t.z + r;
         if (j >= b.ny) break;
-        const long long c = q * plane + b.off + j * b.nx + i;
-        p[c] += double(e[c]);
+        const long long c = q * J.plane + b.off + j * b.nx + i;
+        J.p[c] += double(J.e[c]);
     }
 }
+
+__global__ void __launch_bounds__(256) k_addcorr(const AddJob J) { addcorr_body(J, blockIdx.x, blockIdx.y); }
 
 // Convergence bookkeeping after a residual evaluation (single workgroup):
 // ratio_q = ||r_q||^2 / ||f_q||^2.  scal[0] = max ratio over the active list.
 // With retirement, converged modes record the cycle count and leave the list.
-__global__ void __launch_bounds__(1024)
-k_update(int nz, const double* __restrict__ rnorm, const double* __restrict__ fnorm,
-         const double* __restrict__ pnorm, const double* __restrict__ sabs, double rtol2, double etol2,
-         int retire, int maxc, int* __restrict__ act, int* __restrict__ nact, int* __restrict__ cyc,
-         double* __restrict__ scal, int* __restrict__ state) {
+struct UpdJob {
+    int nz;
+    const double* rnorm;
+    const double* fnorm;
+    const double* pnorm;
+    const double* sabs;
+    double rtol2, etol2;
+    int retire, maxc;
+    int* act;
+    int* nact;
+    int* cyc;
+    double* scal;
+    int* state;
+};
+
+__device__ __forceinline__ void update_body(const UpdJob& J) {
+    const double* __restrict__ rnorm = J.rnorm;
+    const double* __restrict__ fnorm = J.fnorm;
+    const double* __restrict__ pnorm = J.pnorm;
+    const double* __restrict__ sabs = J.sabs;
+    const double rtol2 = J.rtol2, etol2 = J.etol2;
+    const int retire = J.retire, maxc = J.maxc;
+    int* __restrict__ act = J.act;
+    int* __restrict__ nact = J.nact;
+    int* __restrict__ cyc = J.cyc;
+    double* __restrict__ scal = J.scal;
+    int* __restrict__ state = J.state;
     // state[0]: non-finite rhs, state[1]: cycle counter, state[2]: max cycles reached
     __shared__ int keep[4096];
     __shared__ double mx[16];
@@ -393,6 +450,8 @@ k_update(int nz, const double* __restrict__ rnorm, const double* __restrict__ fn
         state[1] = cycle + 1;
     }
 }
+
+__global__ void __launch_bounds__(1024) k_update(const UpdJob J) { update_body(J); }
 
 __global__ void k_zero64(double* p, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -649,24 +708,38 @@ __device__ LdsView<T> lds_view(const LdsArgs& a, unsigned char* raw) {
 
 // One V-cycle on levels L.. of every active mode: f_L in, p_L out (from 0).
 template <typename T>
-__global__ void __launch_bounds__(1024)
-k_lds_vcycle(LdsArgs a, T* __restrict__ pL, const T* __restrict__ fL, long long planeL,
-             const double* __restrict__ shift, const int* __restrict__ act,
-             const int* __restrict__ nact) {
+struct LdsJob {
+    LdsArgs a;
+    T* pL;
+    const T* fL;
+    long long planeL;
+    const double* shift;
+    const int* act;
+    const int* nact;
+};
+
+template <typename T>
+__device__ __forceinline__ void lds_vcycle_body(const LdsJob<T>& J, int item) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int item = blockIdx.x;
-    if (item >= *nact) return;
-    const int q = act[item];
+    if (item >= *J.nact) return;
+    const LdsArgs a = J.a;
+    const long long planeL = J.planeL;
+    const int q = J.act[item];
     LdsView<T> v = lds_view<T>(a, lds_raw);
     T* p = lds_p(a, v, a.L);
     T* f = p + planeL;
     for (long long c = threadIdx.x; c < planeL; c += blockDim.x) {
-        f[c] = fL[q * planeL + c];
+        f[c] = J.fL[q * planeL + c];
         p[c] = T(0);
     }
     __syncthreads();
-    lds_vcycle(a, v, shift[q]);
-    for (long long c = threadIdx.x; c < planeL; c += blockDim.x) pL[q * planeL + c] = p[c];
+    lds_vcycle(a, v, J.shift[q]);
+    for (long long c = threadIdx.x; c < planeL; c += blockDim.x) J.pL[q * planeL + c] = p[c];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_lds_vcycle(const LdsJob<T> J) {
+    lds_vcycle_body<T>(J, blockIdx.x);
 }
 
 __device__ double lds_block_sum(double x, double* red) {
@@ -843,8 +916,8 @@ int launch_vcycle(const mbp_plan* P, T* p0, T* p0B, T* f0, const int* act, const
         LdsArgs a = lds_args(P, L);
         const size_t bytes = size_t(is32 ? P->lds_bytes32 : P->lds_bytes64);
         set_lds(reinterpret_cast<const void*>(k_lds_vcycle<T>), bytes);
-        hipLaunchKernelGGL(k_lds_vcycle<T>, dim3(nitems), dim3(lds_threads(P->levels[L].plane)), bytes, s, a, P_(L), F_(L),
-                           (long long)P->levels[L].plane, P->d_shift, act, nact);
+        const LdsJob<T> J{a, P_(L), F_(L), (long long)P->levels[L].plane, P->d_shift, act, nact};
+        hipLaunchKernelGGL(k_lds_vcycle<T>, dim3(nitems), dim3(lds_threads(P->levels[L].plane)), bytes, s, J);
     }
     int nparts = 0;
     for (int l = L - 1; l >= 0; --l) {
@@ -903,8 +976,8 @@ void launch_norm_from_rhs(const mbp_plan* P, int nitems, hipStream_t s) {
 
 void launch_finish(const mbp_plan* P, int nparts, double* out, const int* act, const int* nact,
                    int nitems, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, P->d_part, nparts, act, nact, out,
-                       P->d_pnorm);
+    const FinJob F{P->d_part, nparts, act, nact, out, P->d_pnorm};
+    hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, F);
 }
 
 void launch_lds_full(const mbp_plan* P, double* p, const double* f, const int* act, const int* nact,
@@ -921,29 +994,28 @@ void launch_lds_full(const mbp_plan* P, double* p, const double* f, const int* a
 void launch_residual_norm(const mbp_plan* P, const double* p, const double* f, double* rnorm,
                           const int* act, const int* nact, int nitems, hipStream_t s) {
     const Level& L = P->levels[0];
-    hipLaunchKernelGGL(k_residual<0>, dim3(L.ntiles, nitems), dim3(kTileX, kRowsPerPass), 0, s,
-                       P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, f,
-                       (long long)L.plane, P->d_shift, act, nact, P->d_part, nullptr, nullptr);
-    hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, P->d_part, L.ntiles, act, nact, rnorm,
-                       P->d_pnorm);
+    const ResJob J{P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, f,
+                   (long long)L.plane, P->d_shift, act, nact, P->d_part, nullptr, nullptr};
+    hipLaunchKernelGGL(k_residual<0>, dim3(L.ntiles, nitems), dim3(kTileX, kRowsPerPass), 0, s, J);
+    const FinJob F{P->d_part, L.ntiles, act, nact, rnorm, P->d_pnorm};
+    hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, F);
 }
 
 void launch_residual_to32(const mbp_plan* P, const double* p, const double* f, float* r32, float* e32,
                           double* rnorm, const int* act, const int* nact, int nitems, hipStream_t s) {
     const Level& L = P->levels[0];
-    hipLaunchKernelGGL(k_residual<1>, dim3(L.ntiles, nitems), dim3(kTileX, kRowsPerPass), 0, s,
-                       P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, f,
-                       (long long)L.plane, P->d_shift, act, nact, P->d_part, r32, e32);
-    hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, P->d_part, L.ntiles, act, nact, rnorm,
-                       P->d_pnorm);
+    const ResJob J{P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, f,
+                   (long long)L.plane, P->d_shift, act, nact, P->d_part, r32, e32};
+    hipLaunchKernelGGL(k_residual<1>, dim3(L.ntiles, nitems), dim3(kTileX, kRowsPerPass), 0, s, J);
+    const FinJob F{P->d_part, L.ntiles, act, nact, rnorm, P->d_pnorm};
+    hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, F);
 }
 
 void launch_add_correction(const mbp_plan* P, double* p, const float* e32, const int* act,
                            const int* nact, int nitems, hipStream_t s) {
     const Level& L = P->levels[0];
-    hipLaunchKernelGGL(k_addcorr, dim3(L.ntiles, nitems), dim3(kTileX, kRowsPerPass), 0, s,
-                       P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, p, e32,
-                       (long long)L.plane, act, nact);
+    const AddJob J{P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, p, e32, (long long)L.plane, act, nact};
+    hipLaunchKernelGGL(k_addcorr, dim3(L.ntiles, nitems), dim3(kTileX, kRowsPerPass), 0, s, J);
 }
 
 void launch_plane_norm(const mbp_plan* P, const double* f, double* out, hipStream_t s) {
@@ -951,15 +1023,15 @@ void launch_plane_norm(const mbp_plan* P, const double* f, double* out, hipStrea
     hipLaunchKernelGGL(k_sumsq, dim3(L.ntiles, P->g.nz), dim3(kTileX, kRowsPerPass), 0, s,
                        P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, f, (long long)L.plane,
                        P->d_part);
-    hipLaunchKernelGGL(k_finish, dim3(P->g.nz), dim3(256), 0, s, P->d_part, L.ntiles, nullptr, nullptr,
-                       out, nullptr);
+    const FinJob F{P->d_part, L.ntiles, nullptr, nullptr, out, nullptr};
+    hipLaunchKernelGGL(k_finish, dim3(P->g.nz), dim3(256), 0, s, F);
 }
 
 void launch_update_active(const mbp_plan* P, double rtol2, double etol2, int retire, int maxc,
                           hipStream_t s) {
-    hipLaunchKernelGGL(k_update, dim3(1), dim3(1024), 0, s, P->g.nz, P->d_rnorm, P->d_fnorm, P->d_pnorm,
-                       P->d_sabs, rtol2, etol2, retire, maxc, P->d_act, P->d_nact, P->d_cyc, P->d_scal,
-                       P->d_flag);
+    const UpdJob J{P->g.nz, P->d_rnorm, P->d_fnorm, P->d_pnorm, P->d_sabs, rtol2, etol2,
+                   retire, maxc, P->d_act, P->d_nact, P->d_cyc, P->d_scal, P->d_flag};
+    hipLaunchKernelGGL(k_update, dim3(1), dim3(1024), 0, s, J);
 }
 
 void launch_reset_active(const mbp_plan* P, hipStream_t s) {
@@ -992,6 +1064,155 @@ void launch_apply3d(const mbp_plan* P, const double* p, double* out, hipStream_t
     hipLaunchKernelGGL(k_apply3d, dim3(L.ntiles, P->g.nz), dim3(kTileX, kRowsPerPass), 0, s,
                        P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, out,
                        P->g.nz, 1.0 / (P->g.dz * P->g.dz), int(P->g.zkind));
+}
+
+// ============================ grouped launches ============================
+// The same stage for many problems in one launch: each workgroup finds its
+// job in the entry table and runs the single-problem body with its own
+// (bx, by).  Jobs sit in device memory, uploaded before the launches are
+// recorded.
+
+__global__ void __launch_bounds__(256) k_residual32_group(const GEnt* __restrict__ e, int n,
+                                                          const ResJob* __restrict__ jobs) {
+    int bx, by;
+    const int j = group_locate(e, n, bx, by);
+    residual_body<1>(jobs[j], bx, by);
+}
+
+__global__ void __launch_bounds__(256) k_finish_group(const GEnt* __restrict__ e, int n,
+                                                      const FinJob* __restrict__ jobs) {
+    int bx, by;
+    const int j = group_locate(e, n, bx, by);
+    finish_body(jobs[j], bx);
+}
+
+__global__ void __launch_bounds__(1024) k_update_group(const GEnt* __restrict__ e, int n,
+                                                       const UpdJob* __restrict__ jobs) {
+    int bx, by;
+    const int j = group_locate(e, n, bx, by);
+    update_body(jobs[j]);
+}
+
+__global__ void __launch_bounds__(256) k_addcorr_group(const GEnt* __restrict__ e, int n,
+                                                       const AddJob* __restrict__ jobs) {
+    int bx, by;
+    const int j = group_locate(e, n, bx, by);
+    addcorr_body(jobs[j], bx, by);
+}
+
+__global__ void __launch_bounds__(1024) k_lds_vcycle_group(const GEnt* __restrict__ e, int n,
+                                                           const LdsJob<float>* __restrict__ jobs) {
+    int bx, by;
+    const int j = group_locate(e, n, bx, by);
+    lds_vcycle_body<float>(jobs[j], bx);
+}
+
+GStage group_res32(GroupBlob& gb, const std::vector<SolveCtx*>& cs) {
+    std::vector<ResJob> jobs;
+    std::vector<int> gx, gy;
+    for (const SolveCtx* c : cs) {
+        const mbp_plan* P = c->P;
+        const Level& L = P->levels[0];
+        jobs.push_back(ResJob{P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, P->phat,
+                              P->fhat, (long long)L.plane, P->d_shift, P->d_act, P->d_nact, P->d_part,
+                              P->f32[0], P->p32[0]});
+        gx.push_back(L.ntiles);
+        gy.push_back(c->nitems);
+    }
+    return group_build(gb, G_RES32, jobs, gx, gy);
+}
+
+GStage group_finish(GroupBlob& gb, const std::vector<SolveCtx*>& cs) {
+    std::vector<FinJob> jobs;
+    std::vector<int> gx, gy;
+    for (const SolveCtx* c : cs) {
+        const mbp_plan* P = c->P;
+        jobs.push_back(FinJob{P->d_part, P->levels[0].ntiles, P->d_act, P->d_nact, P->d_rnorm, P->d_pnorm});
+        gx.push_back(c->nitems);
+        gy.push_back(1);
+    }
+    return group_build(gb, G_FINISH, jobs, gx, gy);
+}
+
+GStage group_update(GroupBlob& gb, const std::vector<SolveCtx*>& cs) {
+    std::vector<UpdJob> jobs;
+    std::vector<int> gx, gy;
+    for (const SolveCtx* c : cs) {
+        const mbp_plan* P = c->P;
+        jobs.push_back(UpdJob{P->g.nz, P->d_rnorm, P->d_fnorm, P->d_pnorm, P->d_sabs, c->rtol2, c->etol2,
+                              c->retire ? 1 : 0, P->opt.max_cycles, P->d_act, P->d_nact, P->d_cyc, P->d_scal,
+                              P->d_flag});
+        gx.push_back(1);
+        gy.push_back(1);
+    }
+    GStage st = group_build(gb, G_UPDATE, jobs, gx, gy);
+    st.threads = 1024;
+    return st;
+}
+
+GStage group_addcorr(GroupBlob& gb, const std::vector<SolveCtx*>& cs) {
+    std::vector<AddJob> jobs;
+    std::vector<int> gx, gy;
+    for (const SolveCtx* c : cs) {
+        const mbp_plan* P = c->P;
+        const Level& L = P->levels[0];
+        jobs.push_back(AddJob{P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->phat, P->p32[0],
+                              (long long)L.plane, P->d_act, P->d_nact});
+        gx.push_back(L.ntiles);
+        gy.push_back(c->nitems);
+    }
+    return group_build(gb, G_ADDCORR, jobs, gx, gy);
+}
+
+GStage group_lds32(GroupBlob& gb, const std::vector<SolveCtx*>& cs) {
+    std::vector<LdsJob<float>> jobs;
+    std::vector<int> gx, gy;
+    size_t bytes = 0;
+    for (const SolveCtx* c : cs) {
+        const mbp_plan* P = c->P;
+        const int L = P->lds_level32;
+        jobs.push_back(LdsJob<float>{lds_args(P, L), P->p32[L], P->f32[L], (long long)P->levels[L].plane,
+                                     P->d_shift, P->d_act, P->d_nact});
+        gx.push_back(c->nitems);
+        gy.push_back(1);
+        bytes = std::max(bytes, size_t(P->lds_bytes32));
+    }
+    GStage st = group_build(gb, G_LDS32, jobs, gx, gy);
+    st.lds = bytes;
+    st.threads = 1024;
+    set_lds(reinterpret_cast<const void*>(k_lds_vcycle_group), bytes);
+    return st;
+}
+
+void group_launch_mg(const GStage& st, const unsigned char* dev, hipStream_t s) {
+    if (st.wgs <= 0) return;
+    const GEnt* e = reinterpret_cast<const GEnt*>(dev + st.ent_off);
+    const void* j = dev + st.job_off;
+    const dim3 tile(kTileX, kRowsPerPass);
+    switch (st.kind) {
+        case G_RES32:
+            hipLaunchKernelGGL(k_residual32_group, dim3(st.wgs), tile, 0, s, e, st.nent,
+                               reinterpret_cast<const ResJob*>(j));
+            break;
+        case G_FINISH:
+            hipLaunchKernelGGL(k_finish_group, dim3(st.wgs), dim3(256), 0, s, e, st.nent,
+                               reinterpret_cast<const FinJob*>(j));
+            break;
+        case G_UPDATE:
+            hipLaunchKernelGGL(k_update_group, dim3(st.wgs), dim3(1024), 0, s, e, st.nent,
+                               reinterpret_cast<const UpdJob*>(j));
+            break;
+        case G_ADDCORR:
+            hipLaunchKernelGGL(k_addcorr_group, dim3(st.wgs), tile, 0, s, e, st.nent,
+                               reinterpret_cast<const AddJob*>(j));
+            break;
+        case G_LDS32:
+            hipLaunchKernelGGL(k_lds_vcycle_group, dim3(st.wgs), dim3(st.threads), st.lds, s, e, st.nent,
+                               reinterpret_cast<const LdsJob<float>*>(j));
+            break;
+        default:
+            break;
+    }
 }
 
 }  // namespace mbp
