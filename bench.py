@@ -4,6 +4,8 @@
                     [--precision fp64|mixed] [--lockstep] [--no-cpu] [--no-variants]
     python bench.py --workload batch64 [--steps K]     # 64 uneven problems, batched form
     python bench.py --workload serve [--requests N]    # Poisson request stream, server
+    python bench.py --transform-compare                # z transform: LDS FFT vs dense matrix product
+    python bench.py --copy-calibrate                   # 1 GiB copies (scale for HBM byte counters)
 
 One step is one complete solve of the pressure-Poisson problem (Algorithm 1):
 forward z-transform, the shifted 2D multigrid solves of every mode to a
@@ -298,6 +300,45 @@ def bench_serve(args, torch, mbp):
     }
 
 
+def transform_compare(torch, mbp):
+    """The z transform of a 256 x 256 plane stack two ways: the LDS FFT kernel
+    (DCT-II, forward) and a dense nz x nz matrix times the [nz, plane] field in
+    FP64 (a library GEMM on the matrix cores).  Both move the same 16 B per
+    cell; the matrix form also spends 2 nz flops per cell."""
+    cols = 256 * 256
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn, reps=10):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    rows = []
+    for nz in (64, 96, 128, 192, 256, 512, 1024):
+        g = torch.Generator(device="cuda").manual_seed(nz)
+        T = torch.randn(nz, nz, dtype=torch.float64, device="cuda", generator=g)
+        X = torch.randn(nz, cols, dtype=torch.float64, device="cuda", generator=g)
+        Y = torch.empty_like(X)
+        t_gemm = timed(lambda: torch.matmul(T, X, out=Y))
+        prob = W.box(256, 256, nz, 1.0, 1.0, 1.0, "DD", "NN", "NN")
+        plan = mbp.Plan(prob, precision="fp64")
+        f = X.reshape(-1)
+        fh = torch.empty_like(f)
+        t_fft = timed(lambda: plan.forward(f, fh))
+        plan.close()
+        rows.append({"nz": nz, "cells": nz * cols, "fft_ms": round(t_fft, 4), "gemm_ms": round(t_gemm, 4),
+                     "fft_GBs": round(16 * nz * cols / (t_fft * 1e-3) / 1e9, 1),
+                     "gemm_TFLOPs": round(2.0 * nz * nz * cols / (t_gemm * 1e-3) / 1e12, 1),
+                     "fft_over_gemm": round(t_fft / t_gemm, 3)})
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,6 +354,9 @@ def main(argv=None):
     ap.add_argument("--no-variants", action="store_true", help="skip the short runs of the other forms")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="only run five 1 GiB device-to-device copies (scale for HBM byte counters)")
+    ap.add_argument("--transform-compare", action="store_true",
+                    help="only time the z transform as the LDS FFT kernel and as a dense FP64 matrix "
+                         "product (library GEMM) for several nz")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -341,6 +385,10 @@ def main(argv=None):
         ms = a.elapsed_time(b) / 5
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "ms": ms,
                           "GBs": 16 * n / (ms * 1e-3) / 1e9}), flush=True)
+        return 0
+    if args.transform_compare:
+        for row in transform_compare(torch, mbp):
+            print(json.dumps(row), flush=True)
         return 0
     if args.workload in ("batch64", "serve"):
         out = (bench_batch if args.workload == "batch64" else bench_serve)(args, torch, mbp)
