@@ -264,7 +264,7 @@ int mbp_profile_read(mbp_plan* plan, mbp_profile_info* out);
  * candidate stays in the plan for every later solve.  Candidates: the
  * number of workgroups a strip-form launch aims at (which sets how many
  * modes one workgroup runs in turn) and, per fused multigrid level, the
- * pre-smoothing form (LDS strip tiles of 22 x 58 cells, or a register
+ * pre-smoothing form (LDS strip tiles of 26 x 58 cells, or a register
  * march down strips of 128 x 58 cells).  All candidates run the same
  * red-black sweeps.  Blocking; the plan must be idle.  out (optional):
  *   wg_target  chosen workgroups per launch

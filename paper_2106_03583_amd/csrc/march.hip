@@ -1,6 +1,6 @@
 // Fused one-pass smoothing kernels for the global-memory multigrid levels.
 //
-// A workgroup owns a strip of one block: up to 58 output columns and 22
+// A workgroup owns a strip of one block: up to 58 output columns and 26
 // output rows, held in LDS with three halo columns and rows on every side
 // (rows and columns of neighbouring blocks across joined faces).  One
 // launch runs a whole red-black Gauss-Seidel sweep out of place (old -> new
@@ -144,10 +144,10 @@ __device__ __forceinline__ void static_for(F&& f) {
 // coarse correction rows) are issued before the current mode is relaxed, so
 // they are in flight during its compute.  p and f are staged in LDS.  Phases per mode: stage p (+ correction), red, black, store with the
 // residual, restriction / norm.
-constexpr int kTileRows = 22;               // output rows per strip (host cuts at this)
+constexpr int kTileRows = 26;               // output rows per strip (host cuts at this)
 constexpr int kLdsRows = kTileRows + 6;
 constexpr int kRowsPerWave = kLdsRows / 4;  // contiguous rows per wave
-constexpr int kWaveCoarse = 5;              // coarse rows of the correction staged per wave
+constexpr int kWaveCoarse = 6;              // coarse rows of the correction staged per wave
 static_assert(kLdsRows % 4 == 0, "four waves share the strip rows");
 static_assert(2 * (kWaveCoarse - 2) + 1 >= kRowsPerWave, "a wave's rows fit its coarse rows");
 
@@ -469,10 +469,25 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) 
         }
     }
     int cyb = kNoRow;  // first coarse row the wave stages for its own rows
+    // per row of the wave (mode-invariant): fmask, the correction comes from
+    // the staged coarse rows, crow (3 bits a row) the first of its two;
+    // hmask, the correction is summed cell by cell (halo rows of other blocks)
+    unsigned fmask = 0u, hmask = 0u, crow = 0u;
     if (PRO) {
         for (int m = 0; m < kRowsPerWave; ++m) {
             const int r = rbase + m;
             if (r < nrow && scy[r] != kNoRow) { cyb = scy[r]; break; }
+        }
+        for (int m = 0; m < kRowsPerWave; ++m) {
+            const int r = rbase + m;
+            if (r >= nrow || !((amask >> m) & 1u)) continue;
+            const int cy = scy[r];
+            if (cy != kNoRow && cy - cyb + 1 < kWaveCoarse) {
+                fmask |= 1u << m;
+                crow |= unsigned(cy - cyb) << (3 * m);
+            } else {
+                hmask |= 1u << m;
+            }
         }
         issue_e(sq[0], cyb);
     }
@@ -491,31 +506,29 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) 
                 sE[wave][m][lane] = sgw[g][lane] * leA[m] + sgw[g + 1][lane] * leB[m];
             }
         }
+        int zr = 0;
+        if (PRO) asm volatile("v_mov_b32 %0, 0" : "=v"(zr));  // keeps swy reads per mode
 #pragma unroll
         for (int m = 0; m < kRowsPerWave; ++m) {
             const int r = rbase + m;
             if (r < nrow) {
                 T v = lp[m];
-                if (PRO) {
-                    const int cy = scy[r];
-                    if (((amask >> m) & 1u) && cy != kNoRow && cy - cyb + 1 < kWaveCoarse) {
-                        const T wy = T(swy[r]);
-                        v += wy * sE[wave][cy - cyb][lane] + (T(1) - wy) * sE[wave][cy - cyb + 1][lane];
-                    }
+                if (PRO && ((fmask >> m) & 1u)) {
+                    const int c0 = int((crow >> (3 * m)) & 7u);
+                    const T wy = T(swy[r + zr]);
+                    v += wy * sE[wave][c0][lane] + (T(1) - wy) * sE[wave][c0 + 1][lane];
                 }
                 sp[r][lane] = v;
                 sf[r][lane] = lf[m];
             }
         }
         // halo rows of other blocks: correction cell by cell
-        if (PRO) {
+        if (PRO && hmask) {
             const T* __restrict__ ecq = ec + q * plane_c;
 #pragma unroll 1
             for (int m = 0; m < kRowsPerWave; ++m) {
+                if (!((hmask >> m) & 1u)) continue;
                 const int r = rbase + m;
-                if (!((amask >> m) & 1u)) continue;
-                const int cy = scy[r];
-                if (cy != kNoRow && cy - cyb + 1 < kWaveCoarse) continue;
                 const int k = ty0 - 3 + r;
                 T corr;
                 if (k < 0) corr = correction(aB, aBc, aip, dp, ecq, bm, cim, nym + k);
@@ -537,7 +550,6 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) 
         // LDS latency overlaps the arithmetic of the previous pair.  FP64 runs
         // one pair at a time: two pairs in flight do not fit its register
         // budget next to the next mode's prefetched loads.
-        static_assert(kPairs == 4, "the FP32 sweep is written out for four row pairs");
 #define MBP_PAIR_LOAD(P, pi)                                                                       \
     {                                                                                              \
         const int rr_ = max(min(rbase + 2 * (pi) + int((pick[colour] >> (pi)) & 1u), kLdsRows - 2), 1) + zr; \
@@ -574,15 +586,19 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) 
             int zr;
             asm volatile("v_mov_b32 %0, 0" : "=v"(zr));
             if constexpr (sizeof(T) == 4) {
+                // two slots: pair pi loads into slot pi & 1 while pair pi - 1
+                // finishes from the other
                 struct { T wm, wp, d, y0, y1, pl, pr, pd, pu, f; } A, B;
                 MBP_PAIR_LOAD(A, 0)
-                MBP_PAIR_LOAD(B, 1)
-                MBP_PAIR_DONE(A, 0)
-                MBP_PAIR_LOAD(A, 2)
-                MBP_PAIR_DONE(B, 1)
-                MBP_PAIR_LOAD(B, 3)
-                MBP_PAIR_DONE(A, 2)
-                MBP_PAIR_DONE(B, 3)
+#pragma unroll
+                for (int pi = 1; pi <= kPairs; ++pi) {
+                    if (pi < kPairs) {
+                        if (pi & 1) MBP_PAIR_LOAD(B, pi)
+                        else MBP_PAIR_LOAD(A, pi)
+                    }
+                    if ((pi - 1) & 1) MBP_PAIR_DONE(B, pi - 1)
+                    else MBP_PAIR_DONE(A, pi - 1)
+                }
             } else {
 #pragma unroll
                 for (int pi = 0; pi < kPairs; ++pi) {
@@ -665,14 +681,16 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) 
 }
 
 // Sweep kernels.  The correction form holds more state per lane; it is
-// capped at three waves per SIMD, the others at four.
+// capped at three waves per SIMD in FP32 and two in FP64 (which then needs
+// no spills), the others at four.
 template <typename T, bool RES, bool NRM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_tile(const MArgs<T> args) {
     tile_sweep<T, false, RES, NRM>(args, blockIdx.x, blockIdx.y);
 }
 
 template <typename T, bool NRM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_tile_corr(const MArgs<T> args) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3)))
+k_tile_corr(const MArgs<T> args) {
     tile_sweep<T, true, false, NRM>(args, blockIdx.x, blockIdx.y);
 }
 

@@ -87,7 +87,7 @@ Layout layout(const mbp_plan* P, size_t ftile_bytes, size_t mtile_bytes, int npa
 
 }  // namespace
 
-constexpr int kMarchSeg = 22;  // rows per fused-sweep strip (the LDS tile height)
+constexpr int kMarchSeg = 26;  // rows per fused-sweep strip (the LDS tile height)
 
 // Fused-sweep strips of every level (host tables); fills march_ok.  Two
 // sets per level: short strips for the LDS form, tall ones for the
