@@ -468,6 +468,15 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) 
             }
         }
     }
+    // pairs whose red cell is an output cell of this lane
+    unsigned red_out = 0u;
+    if (PRO && NRM && lane >= 3 && lane < 3 + tw) {
+#pragma unroll
+        for (int pi = 0; pi < kPairs; ++pi) {
+            const int r = rbase + 2 * pi + int((pick[0] >> pi) & 1u);
+            if (((relax[0] >> pi) & 1u) && r >= 3 && ty0 - 3 + r < ty1) red_out |= 1u << pi;
+        }
+    }
     int cyb = kNoRow;  // first coarse row the wave stages for its own rows
     // per row of the wave (mode-invariant): fmask, the correction comes from
     // the staged coarse rows, crow (3 bits a row) the first of its two;
@@ -506,8 +515,10 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) 
                 sE[wave][m][lane] = sgw[g][lane] * leA[m] + sgw[g + 1][lane] * leB[m];
             }
         }
+        // an opaque zero (correcting sweep): its per-row table reads (swy, sy)
+        // stay inside the mode loop instead of being hoisted into registers
         int zr = 0;
-        if (PRO) asm volatile("v_mov_b32 %0, 0" : "=v"(zr));  // keeps swy reads per mode
+        if (PRO) asm volatile("v_mov_b32 %0, 0" : "=v"(zr));
 #pragma unroll
         for (int m = 0; m < kRowsPerWave; ++m) {
             const int r = rbase + m;
@@ -545,14 +556,15 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) 
         }
 
         // One red-black sweep over the pairs chosen above.  Cells of one
-        // colour never neighbour each other, so in FP32 the reads of the next
-        // row pair are issued before the current pair's value is written and
-        // LDS latency overlaps the arithmetic of the previous pair.  FP64 runs
-        // one pair at a time: two pairs in flight do not fit its register
-        // budget next to the next mode's prefetched loads.
+        // colour never neighbour each other, so the reads of the next row
+        // pair are issued before the current pair's value is written and LDS
+        // latency overlaps the arithmetic of the previous pair.  The FP64
+        // restricting sweep runs one pair at a time: two pairs in flight do
+        // not fit its register budget (four waves per SIMD) next to the next
+        // mode's prefetched loads.
 #define MBP_PAIR_LOAD(P, pi)                                                                       \
     {                                                                                              \
-        const int rr_ = max(min(rbase + 2 * (pi) + int((pick[colour] >> (pi)) & 1u), kLdsRows - 2), 1) + zr; \
+        const int rr_ = max(min(rbase + 2 * (pi) + int((pick[colour] >> (pi)) & 1u), kLdsRows - 2), 1) + zc; \
         const int k_ = ty0 - 3 + rr_;                                                              \
         P.wm = xwm0;                                                                               \
         P.wp = xwp0;                                                                               \
@@ -581,11 +593,10 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) 
 #pragma unroll
         for (int colour = 0; colour < 2; ++colour) {
             const int la = min(max(lane, 1), 62);
-            // an opaque zero: the coefficient reads stay inside the mode loop
-            // instead of being hoisted into registers for every pair
-            int zr;
-            asm volatile("v_mov_b32 %0, 0" : "=v"(zr));
-            if constexpr (sizeof(T) == 4) {
+            // the same for the coefficient reads of every pair
+            int zc;
+            asm volatile("v_mov_b32 %0, 0" : "=v"(zc));
+            if constexpr (sizeof(T) == 4 || PRO) {
                 // two slots: pair pi loads into slot pi & 1 while pair pi - 1
                 // finishes from the other
                 struct { T wm, wp, d, y0, y1, pl, pr, pd, pu, f; } A, B;
@@ -613,7 +624,12 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) 
 #undef MBP_PAIR_LOAD
 #undef MBP_PAIR_DONE
 
-        // store, residual (weighted for the restriction, squared for the norm)
+        // store, residual (weighted for the restriction, squared for the
+        // norm).  The black cells were relaxed last, each solving its own
+        // equation with the final red neighbours, so their residual is zero up
+        // to rounding: the correcting sweep's norm evaluates only the red cell
+        // of each row pair.  (The restricting sweep evaluates every cell: its
+        // register budget has no room for the pair bookkeeping.)
         double nrm = 0.0, pnr = 0.0;
         T wres[kRowsPerWave];
 #pragma unroll
@@ -624,17 +640,28 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) 
             if (r >= 3 && k < ty1 && out_lane) {
                 const T pc = sp[r][lane];
                 pnew[q * plane + roff[m]] = pc;
-                if (RES || NRM) {
+                if (NRM) pnr += double(pc) * double(pc);
+                if (!PRO && (RES || NRM)) {
                     const T d = xd0 + T(sy[r][1][2]) + sig;
                     const T res = sf[r][lane] - (xwm0 * sp[r][lane - 1] + xwp0 * sp[r][lane + 1] +
-                                           T(sy[r][1][0]) * sp[r - 1][lane] + T(sy[r][1][1]) * sp[r + 1][lane] +
-                                           d * pc);
-                    if (NRM) {
-                        nrm += double(res) * double(res);
-                        pnr += double(pc) * double(pc);
-                    }
+                                                 T(sy[r][1][0]) * sp[r - 1][lane] + T(sy[r][1][1]) * sp[r + 1][lane] +
+                                                 d * pc);
+                    if (NRM) nrm += double(res) * double(res);
                     if (RES) wres[m] = res * wrx * T(swy[r]);
                 }
+            }
+        }
+        if (PRO && NRM) {
+#pragma unroll
+            for (int pi = 0; pi < kPairs; ++pi) {
+                if (!((red_out >> pi) & 1u)) continue;
+                const int r = rbase + 2 * pi + int((pick[0] >> pi) & 1u) + zr;
+                const T pc = sp[r][lane];
+                const T d = xd0 + T(sy[r][1][2]) + sig;
+                const T res = sf[r][lane] - (xwm0 * sp[r][lane - 1] + xwp0 * sp[r][lane + 1] +
+                                             T(sy[r][1][0]) * sp[r - 1][lane] + T(sy[r][1][1]) * sp[r + 1][lane] +
+                                             d * pc);
+                nrm += double(res) * double(res);
             }
         }
         if (NRM) {
