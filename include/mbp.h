@@ -220,12 +220,19 @@ int mbp_solve(mbp_plan* plan, const double* rhs_dev, double* p_dev, double rtol,
  * MBP_AUTOTUNE (default 4 streams, 4 cycles).  Stream-ordered on `stream`
  * at entry and exit; the call returns after the results are read back.
  * Returns MBP_OK if every item converged, else the first failing item's
- * status; infos (optional, count entries) hold the per-item reports. */
+ * status; infos (optional, count entries) hold the per-item reports.
+ * Grouped form: when every unfinished item is a mixed-precision plan whose
+ * levels above the LDS-resident ones all run the strip kernels (one pre- and
+ * one post-smoothing sweep) with the same inner cycle count, each stage of
+ * the refinement step is one launch across all items (the stream count is
+ * then unused). */
 int mbp_solve_batch(mbp_plan* const* plans, const double* const* rhs_dev, double* const* p_dev,
                     int count, double rtol, int flags, void* stream, mbp_solve_info* infos);
 
 /* Schedule the batch autotuner chose for this plan set: MBP_OK with the
- * stream count and cycles per replay, or MBP_PENDING if none is cached. */
+ * stream count and cycles per replay, or MBP_PENDING if none is cached.
+ * streams is 0 when every replay of the last batch of this plan set ran in
+ * the grouped form. */
 int mbp_batch_schedule(mbp_plan* const* plans, int count, int* streams, int* cycles_per_replay);
 
 /* Building blocks of the solve, exposed for checking and for callers that

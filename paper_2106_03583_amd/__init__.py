@@ -320,7 +320,8 @@ def solve_batch(plans: Sequence[Plan], rhs: Sequence, p: Sequence, rtol=1e-10, f
 
 
 def batch_schedule(plans: Sequence[Plan]):
-    """(streams, cycles per replay) the batch autotuner chose for this plan set, or None."""
+    """(streams, cycles per replay) the batch autotuner chose for this plan set, or None.
+    streams is 0 when every replay of the set's last batch ran in the grouped form."""
     n = len(plans)
     hs = (C.c_void_p * n)(*[pl.handle.value for pl in plans])
     a, b = C.c_int(), C.c_int()

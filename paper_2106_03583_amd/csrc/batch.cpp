@@ -24,6 +24,7 @@ namespace {
 struct BatchTune {
     int streams = 4;
     int chunk = 4;
+    bool grouped = false;  // every replay of the set's last batch ran in the grouped form
 };
 
 std::mutex g_tune_mu;
@@ -151,6 +152,7 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
 
     // captured cycles, replayed until every problem is done
     Graph G;
+    int captures = 0, grouped_captures = 0;
     void* table = nullptr;  // stage tables of the grouped form
     size_t table_bytes = 0;
     size_t trial = 0;
@@ -215,7 +217,9 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
                 fail(MBP_ERR_HIP);
                 break;
             }
+            ++captures;
             if (grouped) {
+                ++grouped_captures;
                 const unsigned char* dev = static_cast<const unsigned char*>(table);
                 for (int it = 0; it < cur.chunk; ++it)
                     for (const GStage& g : stages) {
@@ -277,10 +281,12 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
     }
     G.reset();
     if (table) (void)hipFree(table);
-    if (trial > 0 && trial < trials.size()) {
-        // the batch finished before every candidate ran: keep the best seen
+    {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[sig] = best;
+        // the batch finished before every candidate ran: keep the best seen
+        if (trial > 0 && trial < trials.size()) g_tune[sig] = best;
+        auto it = g_tune.find(sig);
+        if (it != g_tune.end()) it->second.grouped = captures > 0 && grouped_captures == captures;
     }
 
     // epilogue and results
@@ -307,7 +313,7 @@ int batch_tuning(mbp_plan* const* plans, int count, int* streams, int* chunk) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(batch_signature(plans, count));
     if (it == g_tune.end()) return MBP_PENDING;
-    *streams = it->second.streams;
+    *streams = it->second.grouped ? 0 : it->second.streams;
     *chunk = it->second.chunk;
     return MBP_OK;
 }
