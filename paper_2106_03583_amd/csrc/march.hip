@@ -65,78 +65,6 @@ __device__ __forceinline__ int xcd_remap_m(int g, int n) {
     return x * per + min(x, rem) + l;
 }
 
-template <typename T>
-__device__ __forceinline__ T shfl_up1(T v) { return __shfl_up(v, 1); }
-template <typename T>
-__device__ __forceinline__ T shfl_dn1(T v) { return __shfl_down(v, 1); }
-
-// Geometry of one of the (up to three) blocks a lane's column visits.
-struct ColBlk {
-    int id, off, nx, ny, par, cx, cy;
-};
-
-__device__ __forceinline__ ColBlk colblk(const DBlock* __restrict__ B, int id) {
-    ColBlk c{};
-    c.id = id;
-    if (id >= 0) {
-        const DBlock& d = B[id];
-        c.off = d.off; c.nx = d.nx; c.ny = d.ny; c.par = d.par; c.cx = d.cx; c.cy = d.cy;
-    }
-    return c;
-}
-
-// Coarse correction at fine cell (ci, cj) of block `fb` (prolong_at, inlined
-// here with the coarse block table of the next level).
-template <typename T>
-__device__ __forceinline__ T coarse_at(const T* __restrict__ pl, const DBlock* __restrict__ B, int b,
-                                       int I, int J) {
-    T s = T(1);
-    const DBlock* bb = &B[b];
-    if (J < 0) {
-        if (bb->nbr[YM] >= 0) { bb = &B[bb->nbr[YM]]; J = bb->ny - 1; }
-        else { if (bb->bc[YM] == MBP_DIRICHLET) s = -s; J = 0; }
-    } else if (J >= bb->ny) {
-        if (bb->nbr[YP] >= 0) { bb = &B[bb->nbr[YP]]; J = 0; }
-        else { if (bb->bc[YP] == MBP_DIRICHLET) s = -s; J = bb->ny - 1; }
-    }
-    if (I < 0) {
-        if (bb->nbr[XM] >= 0) { bb = &B[bb->nbr[XM]]; I = bb->nx - 1; }
-        else { if (bb->bc[XM] == MBP_DIRICHLET) s = -s; I = 0; }
-    } else if (I >= bb->nx) {
-        if (bb->nbr[XP] >= 0) { bb = &B[bb->nbr[XP]]; I = 0; }
-        else { if (bb->bc[XP] == MBP_DIRICHLET) s = -s; I = bb->nx - 1; }
-    }
-    return s * pl[bb->off + J * bb->nx + I];
-}
-
-template <typename T>
-__device__ __forceinline__ T correction(const DBlock* __restrict__ B, const DBlock* __restrict__ Bc,
-                                       const int* __restrict__ ip, const double* __restrict__ dp,
-                                       const T* __restrict__ ecq, int fb, int ci, int cj) {
-    const DBlock& d = B[fb];
-    const int cx = ip[d.pcx + ci], cy = ip[d.pcy + cj];
-    const T wx = T(dp[d.pwx + ci]), wy = T(dp[d.pwy + cj]);
-    // one corner at a time: this path is rare and must stay light on registers
-    T acc = T(0);
-#pragma unroll 1
-    for (int corner = 0; corner < 4; ++corner) {
-        const int dx = corner & 1, dy = corner >> 1;
-        const T w = (dx ? T(1) - wx : wx) * (dy ? T(1) - wy : wy);
-        acc += w * coarse_at(ecq, Bc, fb, cx + dx, cy + dy);
-    }
-    return acc;
-}
-
-// Compile-time loop: the body gets a constant index, so per-thread arrays
-// indexed by it stay in registers.
-template <int I, int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-    if constexpr (I < N) {
-        f(std::integral_constant<int, I>{});
-        static_for<I + 1, N>(f);
-    }
-}
-
 // ------------------------- LDS tile form of the sweep -------------------------
 // A workgroup owns one strip (rows y0-3 .. y1+2, 64 columns) and runs the
 // sweep for up to kMaxModes modes of it in turn.  The strip geometry (row
@@ -191,7 +119,8 @@ __device__ __forceinline__ double wave_sum63(double v) {
 constexpr int kNoRow = -1000000;            // row table: not a row of the strip's own block
 
 // Offset and sign of coarse value (I, J) of block b, one cell beyond a face
-// allowed: y first (neighbour or mirror), then x, as coarse_at reads it.
+// allowed: y first (neighbour or mirror), then x, as the prolongation
+// resolves a coarse value beyond a face.
 template <typename T>
 __device__ __forceinline__ int coarse_addr(const DBlock* __restrict__ B, int b, int I, int J, T& sign) {
     T s = T(1);
@@ -255,6 +184,8 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) 
     __shared__ int sgo[PRO ? 6 : 1][64];         // PRO: coarse column A, B offsets: ghost row below,
     __shared__ T sgw[PRO ? 6 : 1][64];           //      ghost row above, inside rows; weights with signs
     __shared__ T sxc[2][3][64];                  // x coefficients of the halo rows below / above
+    __shared__ int shA[PRO ? 2 : 1][3][4][64];   // PRO: halo rows of other blocks below / above:
+    __shared__ T shW[PRO ? 2 : 1][3][4][64];     //      coarse offsets and signed weights per corner
     __shared__ int sq[kMaxModes];
     __shared__ double ssig[kMaxModes];
 
@@ -405,6 +336,43 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) 
         sgo[2 * wave][lane] = sgo[2 * wave + 1][lane] = 0;
         sgw[2 * wave][lane] = sgw[2 * wave + 1][lane] = T(0);
     }
+    // correction of the halo rows that lie in other blocks: the four coarse
+    // offsets and signed bilinear weights of every such cell, resolved once
+    // (the same rules as the cell-by-cell correction)
+    if (PRO) {
+        for (int e = threadIdx.x; e < 2 * 3 * 64; e += blockDim.x) {
+            const int side = e / 192, j = (e / 64) % 3, ln = e % 64;
+            const int r = side == 0 ? j : nrow - 3 + j;
+            const int k = ty0 - 3 + r;
+            const int cl = tx0 - 3 + ln;
+            const int crl = cl < 0 ? 0 : (cl < bnx ? 1 : 2);
+            int fb = -1, fi = 0, fj = 0;
+            if (ln < tw + 6 && (side == 0 ? k < 0 : k >= bny)) {
+                const int rr = side == 0 ? 0 : 2;
+                fb = pick3(crl, t.blk[rr][0], t.blk[rr][1], t.blk[rr][2]);
+                const int fnx = pick3(crl, t.nx[rr][0], t.nx[rr][1], t.nx[rr][2]);
+                const int fny = pick3(crl, t.ny[rr][0], t.ny[rr][1], t.ny[rr][2]);
+                fi = crl == 0 ? fnx + cl : (crl == 2 ? cl - bnx : cl);
+                fj = side == 0 ? fny + k : k - bny;
+            }
+            if (fb >= 0) {
+                const DBlock& d = aB[fb];
+                const int cx = aip[d.pcx + fi], cy = aip[d.pcy + fj];
+                const T wx = T(dp[d.pwx + fi]), wy = T(dp[d.pwy + fj]);
+                for (int c = 0; c < 4; ++c) {
+                    const int dx = c & 1, dy = c >> 1;
+                    T sg;
+                    shA[side][j][c][ln] = coarse_addr(aBc, fb, cx + dx, cy + dy, sg);
+                    shW[side][j][c][ln] = sg * (dx ? T(1) - wx : wx) * (dy ? T(1) - wy : wy);
+                }
+            } else {
+                for (int c = 0; c < 4; ++c) {
+                    shA[side][j][c][ln] = 0;
+                    shW[side][j][c][ln] = T(0);
+                }
+            }
+        }
+    }
     const bool out_lane = lane >= 3 && lane < 3 + tw;
     const T wrx = (RES && out_lane) ? T(dp[aB[tb].rwx + c]) : T(0);
 
@@ -533,18 +501,20 @@ __device__ __forceinline__ void tile_sweep(const MArgs<T> args, int bx, int by) 
                 sf[r][lane] = lf[m];
             }
         }
-        // halo rows of other blocks: correction cell by cell
+        // halo rows of other blocks: four corners each from the offset table
+        // (all loads of a wave's rows issued together)
         if (PRO && hmask) {
             const T* __restrict__ ecq = ec + q * plane_c;
-#pragma unroll 1
+#pragma unroll
             for (int m = 0; m < kRowsPerWave; ++m) {
                 if (!((hmask >> m) & 1u)) continue;
                 const int r = rbase + m;
                 const int k = ty0 - 3 + r;
-                T corr;
-                if (k < 0) corr = correction(aB, aBc, aip, dp, ecq, bm, cim, nym + k);
-                else if (k >= bny) corr = correction(aB, aBc, aip, dp, ecq, bp, cip, k - bny);
-                else corr = correction(aB, aBc, aip, dp, ecq, b0, ci, k);
+                const int side = k < 0 ? 0 : 1;
+                const int j = min(max(side == 0 ? r : r - (nrow - 3), 0), 2);
+                T corr = T(0);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) corr += shW[side][j][c][lane] * ecq[shA[side][j][c][lane]];
                 sp[r][lane] += corr;
             }
         }
