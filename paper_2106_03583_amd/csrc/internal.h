@@ -105,7 +105,7 @@ struct mbp_plan {
     std::vector<int> mtile_off, mtile_cnt;  // fused-sweep strips per level (LDS strip form)
     std::vector<int> rtile_off, rtile_cnt;  // taller strips of the register-march form
     std::vector<char> use_rmarch;           // level runs its pre-smoothing as a register march
-    int wg_target = 256 * 12;               // strip-form launches: workgroups aimed at
+    int wg_target = 256 * 3;               // strip-form launches: workgroups aimed at
     std::vector<char> march_ok;   // level runs the fused one-pass sweeps
     void* d_mtiles = nullptr;
     size_t mtile_bytes = 0;

@@ -57,7 +57,7 @@ struct MArgs {
     int wg_target;     // host: workgroups a launch aims at (modes per workgroup follow)
 };
 
-constexpr int kMaxModes = 8;  // most modes one workgroup runs in turn
+constexpr int kMaxModes = 16;  // most modes one workgroup runs in turn
 
 __device__ __forceinline__ int xcd_remap_m(int g, int n) {
     int x = g & 7, l = g >> 3;

@@ -57,11 +57,11 @@ int plan_autotune(mbp_plan* P, const double* rhs, hipStream_t s, mbp_tuning* out
     (void)hipEventCreate(&b);
     const int reps = 3;
     std::fill(P->use_rmarch.begin(), P->use_rmarch.end(), 0);
-    P->wg_target = 256 * 12;
+    P->wg_target = 256 * 3;
     const float t_default = time_cycles(c, s, a, b, reps);
     float best = t_default;
     // workgroups per launch (sets the modes each workgroup runs in turn)
-    for (int target : {256 * 6, 256 * 24}) {
+    for (int target : {256 * 1, 256 * 12}) {
         const int keep = P->wg_target;
         P->wg_target = target;
         const float t = time_cycles(c, s, a, b, reps);
