@@ -52,6 +52,7 @@ struct Level {
     int tile_off = 0;             // first tile in the tile table
     int64_t lds_off = 0;          // element offset of this level in the LDS image
     bool oddwrap = false;         // some block needs the two extra smoothing colours
+    int dp_begin = 0, ip_begin = 0;  // first entries of this level's tables in the pools
 };
 
 struct Geometry {
@@ -89,6 +90,7 @@ struct mbp_plan {
     int nlev = 0;
     int lds_level = 0;            // first level handled by the LDS-resident kernel (FP64)
     int lds_level32 = 0;          // same for FP32 V-cycles
+    int dp_levels_end = 0, ip_levels_end = 0;  // pool entries of all level tables
     int64_t lds_bytes64 = 0, lds_bytes32 = 0;
     int coarse_n = 0;             // cells of the coarsest plane
     std::vector<double> lambda;   // Table-1 eigenvalues
@@ -224,6 +226,8 @@ void launch_residual_norm(const mbp_plan* P, const double* p, const double* f, d
 void launch_residual_to32(const mbp_plan* P, const double* p, const double* f, float* r32,
                           float* e32, double* rnorm, const int* act, const int* nact, int nitems,
                           hipStream_t s);
+// FP32 finest guess the refinement residual must zero (nullptr: none).
+float* fp32_guess_to_zero(const mbp_plan* P);
 void launch_add_correction(const mbp_plan* P, double* p, const float* e32, const int* act,
                            const int* nact, int nitems, hipStream_t s);
 void launch_plane_norm(const mbp_plan* P, const double* f, double* out, hipStream_t s);

@@ -234,7 +234,7 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 }
 
 // Per-tile partial sums of the squared finest-level residual of each mode;
-// mode == 1 also writes r as float32 (the refinement rhs) and zeroes e32.
+// mode == 1 also writes r as float32 (the refinement rhs) and, if given, zeroes e32.
 struct ResJob {
     const DBlock* B;
     const int4* tiles;
@@ -276,7 +276,7 @@ __device__ __forceinline__ void residual_body(const ResJob& J, int bx, int item)
             pacc += pq[c] * pq[c];
             if (MODE == 1) {
                 J.r32[q * J.plane + c] = float(res);
-                J.e32[q * J.plane + c] = 0.0f;
+                if (J.e32) J.e32[q * J.plane + c] = 0.0f;
             }
         }
     }
@@ -547,13 +547,18 @@ struct LdsArgs {
     const double* cwr;
     const double* cmu;
     int nc;
+    int dpb, dpn, ipb, ipn;  // pool ranges of the tables of levels L.. (copied into LDS)
+    const double* cdp;   // in the kernel: the copies, indexed like the pools
+    const int* cip;
 };
 
 template <typename T>
 struct LdsView {
     T* base;             // LDS image: per level l >= L: p (plane) then f (plane)
     double* ctmp;        // coarse temp (nc doubles)
-    double* red;         // reduction scratch
+    double* red;         // reduction scratch (16 doubles)
+    double* tdp;         // copy of the levels' coefficient / transfer tables
+    int* tip;            //   and index tables
 };
 
 template <typename T>
@@ -576,14 +581,14 @@ __device__ void lds_smooth(const LdsArgs& a, T* p, const T* f, const DBlock* B, 
                 const int j = h / hx;
                 const int i = 2 * (h - j * hx) + ((colour + j + b.par) & 1);
                 if (i >= b.nx) continue;
-                p[b.off + j * b.nx + i] = gs_value(p, f, B, b, a.dp, i, j, sig);
+                p[b.off + j * b.nx + i] = gs_value(p, f, B, b, a.cdp, i, j, sig);
             }
         } else {
             const int cnt = b.nx * b.ny;
             for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
                 const int j = c / b.nx, i = c - j * b.nx;
                 if (colour_of(b, i, j) != colour) continue;
-                p[b.off + c] = gs_value(p, f, B, b, a.dp, i, j, sig);
+                p[b.off + c] = gs_value(p, f, B, b, a.cdp, i, j, sig);
             }
         }
         // cells of one colour are never neighbours, also across blocks
@@ -598,7 +603,7 @@ __device__ void lds_smooth(const LdsArgs& a, T* p, const T* f, const DBlock* B, 
                 for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
                     const int j = c / b.nx, i = c - j * b.nx;
                     if (colour_of(b, i, j) != extra) continue;
-                    p[b.off + c] = gs_value(p, f, B, b, a.dp, i, j, sig);
+                    p[b.off + c] = gs_value(p, f, B, b, a.cdp, i, j, sig);
                 }
             }
             __syncthreads();
@@ -615,7 +620,7 @@ __device__ void lds_restrict(const LdsArgs& a, const T* pf, const T* ff, T* pc, 
         const int cnt = bc.nx * bc.ny;
         for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
             const int J = c / bc.nx, I = c - J * bc.nx;
-            fc[bc.off + c] = restrict_at(pf, ff, Bf, bf, a.dp, a.ip, I, J, sig);
+            fc[bc.off + c] = restrict_at(pf, ff, Bf, bf, a.cdp, a.cip, I, J, sig);
             pc[bc.off + c] = T(0);
         }
     }
@@ -629,7 +634,7 @@ __device__ void lds_prolong(const LdsArgs& a, const T* pc, T* pf, const DBlock* 
         const int cnt = bf.nx * bf.ny;
         for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
             const int j = c / bf.nx, i = c - j * bf.nx;
-            pf[bf.off + c] += prolong_at(pc, Bc, bf, bi, a.dp, a.ip, i, j);
+            pf[bf.off + c] += prolong_at(pc, Bc, bf, bi, a.cdp, a.cip, i, j);
         }
     }
     __syncthreads();
@@ -703,7 +708,19 @@ __device__ LdsView<T> lds_view(const LdsArgs& a, unsigned char* raw) {
     long long bytes = (e * (long long)sizeof(T) + 15) & ~15LL;
     v.ctmp = reinterpret_cast<double*>(raw + bytes);
     v.red = v.ctmp + ((a.nc + 1) & ~1);
+    v.tdp = v.red + 16;
+    v.tip = reinterpret_cast<int*>(v.tdp + a.dpn);
     return v;
+}
+
+// Copy the level tables into LDS and point the stencil routines at the copies
+// (the pointers are rebased so that pool offsets index them directly).
+template <typename T>
+__device__ __forceinline__ void lds_tables(LdsArgs& a, const LdsView<T>& v) {
+    for (int t = threadIdx.x; t < a.dpn; t += blockDim.x) v.tdp[t] = a.dp[a.dpb + t];
+    for (int t = threadIdx.x; t < a.ipn; t += blockDim.x) v.tip[t] = a.ip[a.ipb + t];
+    a.cdp = v.tdp - a.dpb;
+    a.cip = v.tip - a.ipb;
 }
 
 // One V-cycle on levels L.. of every active mode: f_L in, p_L out (from 0).
@@ -722,10 +739,11 @@ template <typename T>
 __device__ __forceinline__ void lds_vcycle_body(const LdsJob<T>& J, int item) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     if (item >= *J.nact) return;
-    const LdsArgs a = J.a;
+    LdsArgs a = J.a;
     const long long planeL = J.planeL;
     const int q = J.act[item];
     LdsView<T> v = lds_view<T>(a, lds_raw);
+    lds_tables(a, v);
     T* p = lds_p(a, v, a.L);
     T* f = p + planeL;
     for (long long c = threadIdx.x; c < planeL; c += blockDim.x) {
@@ -767,6 +785,7 @@ k_lds_full(LdsArgs a, double* __restrict__ p0, const double* __restrict__ f0, lo
     if (item >= *nact) return;
     const int q = act[item];
     LdsView<double> v = lds_view<double>(a, lds_raw);
+    lds_tables(a, v);
     double* p = v.base;
     double* f = p + plane;
     const DBlock* B = a.Ball + a.ip[a.lvinfo + 1];
@@ -789,7 +808,7 @@ k_lds_full(LdsArgs a, double* __restrict__ p0, const double* __restrict__ f0, lo
             const int cnt = b.nx * b.ny;
             for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
                 const int j = k / b.nx, i = k - j * b.nx;
-                const double r = f[b.off + k] - apply_at(p, B, b, a.dp, i, j, sig);
+                const double r = f[b.off + k] - apply_at(p, B, b, a.cdp, i, j, sig);
                 rs += r * r;
                 ps += p[b.off + k] * p[b.off + k];
             }
@@ -829,6 +848,10 @@ static LdsArgs lds_args(const mbp_plan* P, int L) {
     a.cwr = P->d_cwr;
     a.cmu = P->d_cmu;
     a.nc = P->coarse_n;
+    a.dpb = P->levels[L].dp_begin;
+    a.dpn = P->dp_levels_end - a.dpb;
+    a.ipb = P->levels[L].ip_begin;
+    a.ipn = P->ip_levels_end - a.ipb;
     return a;
 }
 
@@ -1107,6 +1130,16 @@ __global__ void __launch_bounds__(1024) k_lds_vcycle_group(const GEnt* __restric
     lds_vcycle_body<float>(jobs[j], bx);
 }
 
+// The FP32 V-cycle reads its finest initial guess only on the generic
+// (non-strip) finest level: the strip sweeps and the LDS-resident kernel start
+// from zero without reading it.  Only then must the guess be zeroed.
+float* fp32_guess_to_zero(const mbp_plan* P) {
+    const int nu1 = P->opt.nu1, nu2 = P->opt.nu2;
+    const bool fused_ok = ((nu1 + nu2) % 2 == 0) && nu1 >= 1 && nu2 >= 1;
+    const bool strip0 = fused_ok && P->march_ok[0] && P->p32B[0] != nullptr;
+    return (P->lds_level32 == 0 || strip0) ? nullptr : P->p32[0];
+}
+
 GStage group_res32(GroupBlob& gb, const std::vector<SolveCtx*>& cs) {
     std::vector<ResJob> jobs;
     std::vector<int> gx, gy;
@@ -1115,7 +1148,7 @@ GStage group_res32(GroupBlob& gb, const std::vector<SolveCtx*>& cs) {
         const Level& L = P->levels[0];
         jobs.push_back(ResJob{P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, P->phat,
                               P->fhat, (long long)L.plane, P->d_shift, P->d_act, P->d_nact, P->d_part,
-                              P->f32[0], P->p32[0]});
+                              P->f32[0], fp32_guess_to_zero(P)});
         gx.push_back(L.ntiles);
         gy.push_back(c->nitems);
     }

@@ -366,6 +366,8 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
     for (int l = 0; l < P->nlev; ++l) {
         Level& L = P->levels[l];
         L.blk_off = int(P->hblk.size());
+        L.dp_begin = int(P->hdbl.size());
+        L.ip_begin = int(P->hint.size());
         // colour parity: a breadth-first walk makes joined neighbours differ
         std::vector<int> par(nb, -1);
         for (int s = 0; s < nb; ++s) {
@@ -505,6 +507,9 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
         L.ntiles = int(P->htiles.size()) - L.tile_off;
     }
 
+    P->dp_levels_end = int(P->hdbl.size());
+    P->ip_levels_end = int(P->hint.size());
+
     // ---- finest-plane areas (compatibility projection, gauge) ----
     {
         const Level& L = P->levels[0];
@@ -588,10 +593,14 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
     //      (p and rhs of every level) fits the LDS budget ----
     {
         const int64_t budget = P->lds_limit;
+        // p and f of every level from L0, the coarse temporary and reduction
+        // scratch, and a copy of those levels' coefficient / transfer tables
         auto need = [&](int L0, int64_t elem) {
             int64_t e = 0;
             for (int l = L0; l < P->nlev; ++l) e += 2 * P->levels[l].plane;
-            return e * elem + int64_t(P->coarse_n) * 8 + 1024;
+            const int64_t tables = int64_t(P->dp_levels_end - P->levels[L0].dp_begin) * 8 +
+                                   int64_t(P->ip_levels_end - P->levels[L0].ip_begin) * 4;
+            return e * elem + int64_t(P->coarse_n) * 8 + 1024 + tables;
         };
         P->lds_level = P->nlev - 1;
         for (int l = P->nlev - 1; l >= 0; --l)

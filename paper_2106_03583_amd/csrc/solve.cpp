@@ -331,7 +331,7 @@ void ctx_test(SolveCtx& c, hipStream_t s) {
     mbp_plan* P = c.P;
     const bool zero = c.cycles == 0 && !c.warm;  // p = 0: the residual is f itself
     if (c.mixed)
-        launch_residual_to32(P, P->phat, P->fhat, P->f32[0], P->p32[0], P->d_rnorm, P->d_act, P->d_nact,
+        launch_residual_to32(P, P->phat, P->fhat, P->f32[0], fp32_guess_to_zero(P), P->d_rnorm, P->d_act, P->d_nact,
                              c.nitems, s);
     else if (zero)
         launch_norm_from_rhs(P, c.nitems, s);
