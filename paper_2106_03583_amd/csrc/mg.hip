@@ -350,10 +350,11 @@ __device__ __forceinline__ void finish_body(const FinJob& J, int item) {
 
 __global__ void __launch_bounds__(256) k_finish(const FinJob J) { finish_body(J, blockIdx.x); }
 
+// p += e on the whole plane of every active mode: an elementwise pass, so a
+// workgroup takes a contiguous chunk of one mode's plane (coalesced, no tiles).
+constexpr int kAddChunk = 2048;  // plane cells per workgroup (8 per thread)
+
 struct AddJob {
-    const DBlock* B;
-    const int4* tiles;
-    int ntiles;
     double* p;
     const float* e;
     long long plane;
@@ -361,22 +362,20 @@ struct AddJob {
     const int* nact;
 };
 
-__device__ __forceinline__ void addcorr_body(const AddJob& J, int bx, int item) {
+__device__ __forceinline__ void addcorr_body(const AddJob& J, int chunk, int item) {
     if (item >= *J.nact) return;
-    const int q = J.act[item];
-    const int4 t = J.tiles[xcd_remap_mg(bx, J.ntiles)];
-    const DBlock b = J.B[t.x];
-    const int i = t.y + threadIdx.x;
-    if (i >= b.nx) return;
-    for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
-        const int j = t.z + r;
-        if (j >= b.ny) break;
-        const long long c = q * J.plane + b.off + j * b.nx + i;
-        J.p[c] += double(J.e[c]);
+    const long long base = (long long)J.act[item] * J.plane;
+    const long long c0 = (long long)chunk * kAddChunk + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kAddChunk / 256; ++k) {
+        const long long c = c0 + k * 256;
+        if (c < J.plane) J.p[base + c] += double(J.e[base + c]);
     }
 }
 
 __global__ void __launch_bounds__(256) k_addcorr(const AddJob J) { addcorr_body(J, blockIdx.x, blockIdx.y); }
+
+static int add_chunks(long long plane) { return int((plane + kAddChunk - 1) / kAddChunk); }
 
 // Convergence bookkeeping after a residual evaluation (single workgroup):
 // ratio_q = ||r_q||^2 / ||f_q||^2.  scal[0] = max ratio over the active list.
@@ -1037,8 +1036,8 @@ void launch_residual_to32(const mbp_plan* P, const double* p, const double* f, f
 void launch_add_correction(const mbp_plan* P, double* p, const float* e32, const int* act,
                            const int* nact, int nitems, hipStream_t s) {
     const Level& L = P->levels[0];
-    const AddJob J{P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, p, e32, (long long)L.plane, act, nact};
-    hipLaunchKernelGGL(k_addcorr, dim3(L.ntiles, nitems), dim3(kTileX, kRowsPerPass), 0, s, J);
+    const AddJob J{p, e32, (long long)L.plane, act, nact};
+    hipLaunchKernelGGL(k_addcorr, dim3(add_chunks(L.plane), nitems), dim3(256), 0, s, J);
 }
 
 void launch_plane_norm(const mbp_plan* P, const double* f, double* out, hipStream_t s) {
@@ -1189,9 +1188,8 @@ GStage group_addcorr(GroupBlob& gb, const std::vector<SolveCtx*>& cs) {
     for (const SolveCtx* c : cs) {
         const mbp_plan* P = c->P;
         const Level& L = P->levels[0];
-        jobs.push_back(AddJob{P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->phat, P->p32[0],
-                              (long long)L.plane, P->d_act, P->d_nact});
-        gx.push_back(L.ntiles);
+        jobs.push_back(AddJob{P->phat, P->p32[0], (long long)L.plane, P->d_act, P->d_nact});
+        gx.push_back(add_chunks(L.plane));
         gy.push_back(c->nitems);
     }
     return group_build(gb, G_ADDCORR, jobs, gx, gy);
@@ -1236,7 +1234,7 @@ void group_launch_mg(const GStage& st, const unsigned char* dev, hipStream_t s) 
                                reinterpret_cast<const UpdJob*>(j));
             break;
         case G_ADDCORR:
-            hipLaunchKernelGGL(k_addcorr_group, dim3(st.wgs), tile, 0, s, e, st.nent,
+            hipLaunchKernelGGL(k_addcorr_group, dim3(st.wgs), dim3(256), 0, s, e, st.nent,
                                reinterpret_cast<const AddJob*>(j));
             break;
         case G_LDS32:
