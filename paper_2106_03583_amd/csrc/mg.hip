@@ -235,6 +235,8 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 
 // Per-tile partial sums of the squared finest-level residual of each mode;
 // mode == 1 also writes r as float32 (the refinement rhs) and, if given, zeroes e32.
+constexpr int kResModes = 8;  // most items one residual workgroup runs in turn
+
 struct ResJob {
     const DBlock* B;
     const int4* tiles;
@@ -249,40 +251,68 @@ struct ResJob {
     double* part;
     float* r32;
     float* e32;
+    int per;             // items per workgroup
 };
 
+// Items per residual workgroup: enough workgroups to fill the chip several
+// times over, the rest of the items run in turn.
+static int res_per(int ntiles, int nitems) {
+    const long long per = (long long)ntiles * nitems / 2048;
+    return int(std::max(1LL, std::min<long long>(kResModes, per)));
+}
+
 template <int MODE>
-__device__ __forceinline__ void residual_body(const ResJob& J, int bx, int item) {
-    __shared__ double scratch[8];
-    if (item >= *J.nact) return;
+__device__ __forceinline__ void residual_body(const ResJob& J, int bx, int by) {
+    // a workgroup runs one tile for `per` consecutive active items; per-wave
+    // sums wait in LDS and one barrier at the end publishes every item's pair
+    __shared__ double red[kResModes][kRowsPerPass][2];
+    const int n = *J.nact;
+    const int i0 = by * J.per, i1 = min(i0 + J.per, n);
+    if (i0 >= i1) return;
     const DBlock* __restrict__ B = J.B;
-    const int q = J.act[item];
     const int ntiles = J.ntiles;
     const int tix = xcd_remap_mg(bx, ntiles);
     const int4 t = J.tiles[tix];
     const DBlock b = B[t.x];
-    const double* __restrict__ pq = J.p + q * J.plane;
-    const double* __restrict__ fq = J.f + q * J.plane;
-    const double sig = J.shift[q];
     const int i = t.y + threadIdx.x;
-    double acc = 0.0, pacc = 0.0;
-    if (i < b.nx) {
-        for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
-            const int j = t.z + r;
-            if (j >= b.ny) break;
-            const long long c = b.off + j * b.nx + i;
-            const double res = fq[c] - apply_at(pq, B, b, J.dp, i, j, sig);
-            acc += res * res;
-            pacc += pq[c] * pq[c];
-            if (MODE == 1) {
-                J.r32[q * J.plane + c] = float(res);
-                if (J.e32) J.e32[q * J.plane + c] = 0.0f;
+    for (int it = i0; it < i1; ++it) {
+        const int q = J.act[it];
+        const double* __restrict__ pq = J.p + q * J.plane;
+        const double* __restrict__ fq = J.f + q * J.plane;
+        const double sig = J.shift[q];
+        double acc = 0.0, pacc = 0.0;
+        if (i < b.nx) {
+            for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
+                const int j = t.z + r;
+                if (j >= b.ny) break;
+                const long long c = b.off + j * b.nx + i;
+                const double res = fq[c] - apply_at(pq, B, b, J.dp, i, j, sig);
+                acc += res * res;
+                pacc += pq[c] * pq[c];
+                if (MODE == 1) {
+                    J.r32[q * J.plane + c] = float(res);
+                    if (J.e32) J.e32[q * J.plane + c] = 0.0f;
+                }
             }
         }
+        for (int o = 32; o > 0; o >>= 1) {  // one wave is one row group (blockDim.x = 64)
+            acc += __shfl_xor(acc, o);
+            pacc += __shfl_xor(pacc, o);
+        }
+        if (threadIdx.x == 0) {
+            red[it - i0][threadIdx.y][0] = acc;
+            red[it - i0][threadIdx.y][1] = pacc;
+        }
     }
-    const double s = block_sum(acc, scratch);
-    const double sp = block_sum(pacc, scratch);
-    if (threadIdx.x == 0 && threadIdx.y == 0) {
+    __syncthreads();
+    const int lane = threadIdx.x + threadIdx.y * blockDim.x;
+    if (lane < i1 - i0) {
+        double s = 0.0, sp = 0.0;
+        for (int w = 0; w < kRowsPerPass; ++w) {
+            s += red[lane][w][0];
+            sp += red[lane][w][1];
+        }
+        const int q = J.act[i0 + lane];
         J.part[2 * ((long long)q * ntiles + tix)] = s;
         J.part[2 * ((long long)q * ntiles + tix) + 1] = sp;
     }
@@ -1016,9 +1046,10 @@ void launch_lds_full(const mbp_plan* P, double* p, const double* f, const int* a
 void launch_residual_norm(const mbp_plan* P, const double* p, const double* f, double* rnorm,
                           const int* act, const int* nact, int nitems, hipStream_t s) {
     const Level& L = P->levels[0];
+    const int per = res_per(L.ntiles, nitems);
     const ResJob J{P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, f,
-                   (long long)L.plane, P->d_shift, act, nact, P->d_part, nullptr, nullptr};
-    hipLaunchKernelGGL(k_residual<0>, dim3(L.ntiles, nitems), dim3(kTileX, kRowsPerPass), 0, s, J);
+                   (long long)L.plane, P->d_shift, act, nact, P->d_part, nullptr, nullptr, per};
+    hipLaunchKernelGGL(k_residual<0>, dim3(L.ntiles, (nitems + per - 1) / per), dim3(kTileX, kRowsPerPass), 0, s, J);
     const FinJob F{P->d_part, L.ntiles, act, nact, rnorm, P->d_pnorm};
     hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, F);
 }
@@ -1026,9 +1057,10 @@ void launch_residual_norm(const mbp_plan* P, const double* p, const double* f, d
 void launch_residual_to32(const mbp_plan* P, const double* p, const double* f, float* r32, float* e32,
                           double* rnorm, const int* act, const int* nact, int nitems, hipStream_t s) {
     const Level& L = P->levels[0];
+    const int per = res_per(L.ntiles, nitems);
     const ResJob J{P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, f,
-                   (long long)L.plane, P->d_shift, act, nact, P->d_part, r32, e32};
-    hipLaunchKernelGGL(k_residual<1>, dim3(L.ntiles, nitems), dim3(kTileX, kRowsPerPass), 0, s, J);
+                   (long long)L.plane, P->d_shift, act, nact, P->d_part, r32, e32, per};
+    hipLaunchKernelGGL(k_residual<1>, dim3(L.ntiles, (nitems + per - 1) / per), dim3(kTileX, kRowsPerPass), 0, s, J);
     const FinJob F{P->d_part, L.ntiles, act, nact, rnorm, P->d_pnorm};
     hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, F);
 }
@@ -1145,11 +1177,12 @@ GStage group_res32(GroupBlob& gb, const std::vector<SolveCtx*>& cs) {
     for (const SolveCtx* c : cs) {
         const mbp_plan* P = c->P;
         const Level& L = P->levels[0];
+        const int per = res_per(L.ntiles, c->nitems);
         jobs.push_back(ResJob{P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, P->phat,
                               P->fhat, (long long)L.plane, P->d_shift, P->d_act, P->d_nact, P->d_part,
-                              P->f32[0], fp32_guess_to_zero(P)});
+                              P->f32[0], fp32_guess_to_zero(P), per});
         gx.push_back(L.ntiles);
-        gy.push_back(c->nitems);
+        gy.push_back((c->nitems + per - 1) / per);
     }
     return group_build(gb, G_RES32, jobs, gx, gy);
 }
