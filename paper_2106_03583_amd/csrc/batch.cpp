@@ -62,6 +62,57 @@ struct Graph {
     }
 };
 
+// Streams and events of one batch call, kept for later calls on the same
+// device (creating them costs about as much as a small problem's cycle).
+struct StreamSet {
+    int dev = -1;
+    hipStream_t st[kMaxStreams] = {};
+    hipEvent_t ev_join[kMaxStreams] = {};
+    hipEvent_t ev_fork = nullptr, t0 = nullptr, t1 = nullptr;
+};
+std::mutex g_pool_mu;
+std::vector<StreamSet*> g_pool;
+
+StreamSet* acquire_streams() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        for (size_t i = 0; i < g_pool.size(); ++i)
+            if (g_pool[i]->dev == dev) {
+                StreamSet* p = g_pool[i];
+                g_pool.erase(g_pool.begin() + long(i));
+                return p;
+            }
+    }
+    StreamSet* p = new StreamSet;
+    p->dev = dev;
+    bool ok = true;
+    for (int k = 0; k < kMaxStreams; ++k) {
+        ok = ok && hipStreamCreateWithFlags(&p->st[k], hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&p->ev_join[k], hipEventDisableTiming) == hipSuccess;
+    }
+    ok = ok && hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreate(&p->t0) == hipSuccess && hipEventCreate(&p->t1) == hipSuccess;
+    if (!ok) {
+        for (int k = 0; k < kMaxStreams; ++k) {
+            if (p->st[k]) (void)hipStreamDestroy(p->st[k]);
+            if (p->ev_join[k]) (void)hipEventDestroy(p->ev_join[k]);
+        }
+        if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+        if (p->t0) (void)hipEventDestroy(p->t0);
+        if (p->t1) (void)hipEventDestroy(p->t1);
+        delete p;
+        return nullptr;
+    }
+    return p;
+}
+
+void release_streams(StreamSet* p) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_pool.push_back(p);
+}
+
 }  // namespace
 
 int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const* p, int count,
@@ -86,15 +137,11 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
         trials = {{4, 4}, {1, 4}, {8, 4}, {2, 4}, {4, 2}, {4, 8}};
 
     // streams: [0] is the capture origin; all of them are forked from s
-    hipStream_t st[kMaxStreams];
-    hipEvent_t ev_fork, ev_join[kMaxStreams], t0, t1;
-    for (int k = 0; k < kMaxStreams; ++k) {
-        if (hipStreamCreateWithFlags(&st[k], hipStreamNonBlocking) != hipSuccess) return MBP_ERR_HIP;
-        (void)hipEventCreateWithFlags(&ev_join[k], hipEventDisableTiming);
-    }
-    (void)hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
-    (void)hipEventCreate(&t0);
-    (void)hipEventCreate(&t1);
+    StreamSet* ss = acquire_streams();
+    if (!ss) return MBP_ERR_HIP;
+    hipStream_t* st = ss->st;
+    hipEvent_t* ev_join = ss->ev_join;
+    hipEvent_t ev_fork = ss->ev_fork, t0 = ss->t0, t1 = ss->t1;
     auto fork = [&](hipStream_t from, int S) {
         (void)hipEventRecord(ev_fork, from);
         for (int k = 0; k < S; ++k)
@@ -155,6 +202,7 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
     int captures = 0, grouped_captures = 0;
     void* table = nullptr;  // stage tables of the grouped form
     size_t table_bytes = 0;
+    StateJob* sjobs = nullptr;  // state records the captured graph copies to the host
     size_t trial = 0;
     BatchTune cur = trials.empty() ? tune : trials[0];
     double best_cost = 1e300;
@@ -213,6 +261,19 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
                     break;
                 }
             }
+            {
+                std::vector<StateJob> sj;
+                for (int i : act) sj.push_back(ctx_state_job(cx[i]));
+                if (!sjobs && hipMalloc(reinterpret_cast<void**>(&sjobs), size_t(count) * sizeof(StateJob)) != hipSuccess) {
+                    sjobs = nullptr;
+                    fail(MBP_ERR_NOMEM);
+                    break;
+                }
+                if (hipMemcpy(sjobs, sj.data(), sj.size() * sizeof(StateJob), hipMemcpyHostToDevice) != hipSuccess) {
+                    fail(MBP_ERR_HIP);
+                    break;
+                }
+            }
             if (hipStreamBeginCapture(st[0], hipStreamCaptureModeThreadLocal) != hipSuccess) {
                 fail(MBP_ERR_HIP);
                 break;
@@ -237,6 +298,8 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
                     }
                 join(st[0], Sc);
             }
+            // every problem's state record to the host, once per replay
+            launch_state_gather(sjobs, int(act.size()), st[0]);
             if (hipStreamEndCapture(st[0], &G.g) != hipSuccess ||
                 hipGraphInstantiate(&G.e, G.g, nullptr, nullptr, 0) != hipSuccess) {
                 (void)hipGetLastError();
@@ -253,7 +316,6 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
             break;
         }
         (void)hipEventRecord(t1, s);
-        for (int i : act) ctx_state_readback(cx[i], s);
         if (hipStreamSynchronize(s) != hipSuccess) {
             fail(MBP_ERR_HIP);
             break;
@@ -298,13 +360,8 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
         if (r != MBP_OK) fail(r);
         else if (cx[i].status != MBP_OK) fail(cx[i].status);
     }
-    for (int k = 0; k < kMaxStreams; ++k) {
-        (void)hipStreamDestroy(st[k]);
-        (void)hipEventDestroy(ev_join[k]);
-    }
-    (void)hipEventDestroy(ev_fork);
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
+    if (sjobs) (void)hipFree(sjobs);
+    release_streams(ss);
     return status;
 }
 
