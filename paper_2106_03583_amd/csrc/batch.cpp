@@ -1,12 +1,15 @@
 // Batched solves: many independent problems (each with all of its modes)
-// driven together.  After the prologue and one eager cycle, the cycles of
-// every unfinished problem are captured into one HIP graph, one branch per
-// stream, and replayed chunk by chunk: inside a replay the device runs the
-// convergence test and retires converged modes (and so finished problems,
-// whose kernels then exit at once); the host reads the active counts after
-// each replay and re-captures when the set has shrunk enough to pay off.
+// driven together.  After the prologue (and, unless the grouped form runs,
+// one eager cycle), the cycles of every unfinished problem are captured into
+// one HIP graph and replayed chunk by chunk: inside a replay the device runs
+// the convergence test and retires converged modes (and so finished
+// problems, whose kernels then exit at once); the host reads the active
+// counts after each replay and re-captures when the set has shrunk enough to
+// pay off.  Two graph shapes: the grouped form (mixed precision, strip
+// levels only) launches each stage of the refinement step once for all
+// problems; otherwise each problem's kernels form one branch per stream.
 // The number of streams and the cycles per replay come from a small online
-// autotuner, cached per batch signature.
+// autotuner, cached per batch signature; streams and events are pooled.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -202,7 +205,6 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
     int captures = 0, grouped_captures = 0;
     void* table = nullptr;  // stage tables of the grouped form
     size_t table_bytes = 0;
-    StateJob* sjobs = nullptr;  // state records the captured graph copies to the host
     size_t trial = 0;
     BatchTune cur = trials.empty() ? tune : trials[0];
     double best_cost = 1e300;
@@ -261,19 +263,6 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
                     break;
                 }
             }
-            {
-                std::vector<StateJob> sj;
-                for (int i : act) sj.push_back(ctx_state_job(cx[i]));
-                if (!sjobs && hipMalloc(reinterpret_cast<void**>(&sjobs), size_t(count) * sizeof(StateJob)) != hipSuccess) {
-                    sjobs = nullptr;
-                    fail(MBP_ERR_NOMEM);
-                    break;
-                }
-                if (hipMemcpy(sjobs, sj.data(), sj.size() * sizeof(StateJob), hipMemcpyHostToDevice) != hipSuccess) {
-                    fail(MBP_ERR_HIP);
-                    break;
-                }
-            }
             if (hipStreamBeginCapture(st[0], hipStreamCaptureModeThreadLocal) != hipSuccess) {
                 fail(MBP_ERR_HIP);
                 break;
@@ -298,8 +287,6 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
                     }
                 join(st[0], Sc);
             }
-            // every problem's state record to the host, once per replay
-            launch_state_gather(sjobs, int(act.size()), st[0]);
             if (hipStreamEndCapture(st[0], &G.g) != hipSuccess ||
                 hipGraphInstantiate(&G.e, G.g, nullptr, nullptr, 0) != hipSuccess) {
                 (void)hipGetLastError();
@@ -316,6 +303,7 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
             break;
         }
         (void)hipEventRecord(t1, s);
+        for (int i : act) ctx_state_readback(cx[i], s);
         if (hipStreamSynchronize(s) != hipSuccess) {
             fail(MBP_ERR_HIP);
             break;
@@ -360,7 +348,6 @@ int solve_batch(mbp_plan* const* plans, const double* const* rhs, double* const*
         if (r != MBP_OK) fail(r);
         else if (cx[i].status != MBP_OK) fail(cx[i].status);
     }
-    if (sjobs) (void)hipFree(sjobs);
     release_streams(ss);
     return status;
 }

@@ -267,17 +267,6 @@ void ctx_test(SolveCtx& c, hipStream_t s);      // residual norms + convergence 
 void ctx_vcycle(SolveCtx& c, hipStream_t s);    // one V-cycle of the active modes
 void ctx_state_readback(SolveCtx& c, hipStream_t s);
 void ctx_state_apply(SolveCtx& c);              // after that readback synchronised
-// Device-side form of ctx_state_readback for many problems: one kernel copies
-// each problem's state into its pinned host record (same layout).
-struct StateJob {
-    const double* scal;
-    const int* flag;
-    const int* nact;
-    double* hs;  // pinned: scal[0], scal[1]
-    int* hi;     // pinned: flag[0..3], nact
-};
-StateJob ctx_state_job(const SolveCtx& c);
-void launch_state_gather(const StateJob* jobs_dev, int n, hipStream_t s);
 void ctx_epilogue(SolveCtx& c, hipStream_t s);
 int ctx_info(SolveCtx& c, hipStream_t s, mbp_solve_info* info);  // synchronises s
 int plan_autotune(mbp_plan* P, const double* rhs, hipStream_t s, mbp_tuning* out);

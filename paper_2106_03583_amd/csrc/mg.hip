@@ -1120,23 +1120,6 @@ void launch_apply3d(const mbp_plan* P, const double* p, double* out, hipStream_t
                        P->g.nz, 1.0 / (P->g.dz * P->g.dz), int(P->g.zkind));
 }
 
-// State records of many problems into their pinned host buffers (one thread
-// per problem), so one launch replaces three small copies per problem.
-__global__ void __launch_bounds__(64) k_state_gather(const StateJob* __restrict__ jobs, int n) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    if (i >= n) return;
-    const StateJob J = jobs[i];
-    J.hs[0] = J.scal[0];
-    J.hs[1] = J.scal[1];
-    for (int k = 0; k < 4; ++k) J.hi[k] = J.flag[k];
-    J.hi[4] = *J.nact;
-}
-
-void launch_state_gather(const StateJob* jobs_dev, int n, hipStream_t s) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_state_gather, dim3((n + 63) / 64), dim3(64), 0, s, jobs_dev, n);
-}
-
 // ============================ grouped launches ============================
 // The same stage for many problems in one launch: each workgroup finds its
 // job in the entry table and runs the single-problem body with its own

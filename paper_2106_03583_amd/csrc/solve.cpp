@@ -366,11 +366,6 @@ void ctx_state_readback(SolveCtx& c, hipStream_t s) {
     (void)hipMemcpyAsync(pin_i(P) + 4, P->d_nact, sizeof(int), hipMemcpyDeviceToHost, s);
 }
 
-StateJob ctx_state_job(const SolveCtx& c) {
-    mbp_plan* P = c.P;
-    return StateJob{P->d_scal, P->d_flag, P->d_nact, pin_d(P) + kPinScal, pin_i(P)};
-}
-
 // After the readback synchronised: stop when every mode retired (retiring
 // form) or every mode passed (lockstep), or when the cycle budget ran out.
 void ctx_state_apply(SolveCtx& c) {
