@@ -1243,7 +1243,12 @@ GStage group_lds32(GroupBlob& gb, const std::vector<SolveCtx*>& cs) {
     }
     GStage st = group_build(gb, G_LDS32, jobs, gx, gy);
     st.lds = bytes;
-    st.threads = 1024;
+    // as many workgroups per CU as the largest image allows (at most four;
+    // the kernel's register use caps a CU at 16 of its waves), and the
+    // waves split between them
+    const int64_t per_cu = cs.empty() ? 1 : cs[0]->P->lds_limit;
+    const int wgs_per_cu = int(std::min<int64_t>(4, std::max<int64_t>(1, per_cu / int64_t(std::max<size_t>(bytes, 1)))));
+    st.threads = wgs_per_cu >= 4 ? 256 : wgs_per_cu >= 2 ? 512 : 1024;
     set_lds(reinterpret_cast<const void*>(k_lds_vcycle_group), bytes);
     return st;
 }

@@ -590,9 +590,15 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
     }
 
     // ---- LDS-resident levels: the smallest index whose remaining hierarchy
-    //      (p and rhs of every level) fits the LDS budget ----
+    //      (p and rhs of every level) fits the LDS budget.  The FP64 V-cycle
+    //      may take a workgroup's whole budget.  The FP32 one (mixed
+    //      precision, run for many modes and problems at once) is kept to a
+    //      quarter of it: most of its phases keep few lanes busy, so its
+    //      throughput comes from four workgroups sharing a CU, not from
+    //      one more LDS-resident level ----
     {
         const int64_t budget = P->lds_limit;
+        const int64_t budget32 = std::max<int64_t>(budget / 4, 16 * 1024);
         // p and f of every level from L0, the coarse temporary and reduction
         // scratch, and a copy of those levels' coefficient / transfer tables
         auto need = [&](int L0, int64_t elem) {
@@ -607,7 +613,7 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
             if (need(l, 8) <= budget) P->lds_level = l;
         P->lds_level32 = P->nlev - 1;
         for (int l = P->nlev - 1; l >= 0; --l)
-            if (need(l, 4) <= budget) P->lds_level32 = l;
+            if (need(l, 4) <= budget32) P->lds_level32 = l;
         P->lds_bytes64 = need(P->lds_level, 8);
         P->lds_bytes32 = need(P->lds_level32, 4);
         if (P->lds_bytes64 > budget) {
