@@ -318,6 +318,19 @@ GStage group_build(GroupBlob& gb, int kind, const std::vector<Job>& jobs, const 
     return st;
 }
 // Job of this workgroup in a grouped launch, and its (bx, by) inside the job.
+// A record every lane of the wave read from the same address: say so, so
+// that what is computed from it stays in scalar registers.
+template <typename R>
+__device__ __forceinline__ R wave_uniform(const R& v) {
+    static_assert(sizeof(R) % 4 == 0, "whole 32-bit words");
+    R out;
+    const int* src = reinterpret_cast<const int*>(&v);
+    int* dst = reinterpret_cast<int*>(&out);
+#pragma unroll
+    for (int k = 0; k < int(sizeof(R) / 4); ++k) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+    return out;
+}
+
 __device__ __forceinline__ int group_locate(const GEnt* __restrict__ e, int n, int& bx, int& by) {
     const int g = blockIdx.x;
     int lo = 0, hi = n - 1;

@@ -261,6 +261,9 @@ static int res_per(int ntiles, int nitems) {
     return int(std::max(1LL, std::min<long long>(kResModes, per)));
 }
 
+constexpr int kResRows = kTileY / kRowsPerPass;  // consecutive rows per thread
+static_assert(kTileY % kRowsPerPass == 0, "whole row groups per tile");
+
 template <int MODE>
 __device__ __forceinline__ void residual_body(const ResJob& J, int bx, int by) {
     // a workgroup runs one tile for `per` consecutive active items; per-wave
@@ -270,29 +273,65 @@ __device__ __forceinline__ void residual_body(const ResJob& J, int bx, int by) {
     const int i0 = by * J.per, i1 = min(i0 + J.per, n);
     if (i0 >= i1) return;
     const DBlock* __restrict__ B = J.B;
+    const double* __restrict__ dp = J.dp;
     const int ntiles = J.ntiles;
     const int tix = xcd_remap_mg(bx, ntiles);
-    const int4 t = J.tiles[tix];
-    const DBlock b = B[t.x];
+    const int4 t = wave_uniform(J.tiles[tix]);
+    const DBlock b = wave_uniform(B[t.x]);
+    // each thread owns kResRows consecutive rows of one column; its loads use
+    // indices clamped into the block, so all of them can be in flight at once
+    // (lanes past the block's edge compute values that are never used)
     const int i = t.y + threadIdx.x;
+    // a wave is one row group (blockDim.x = 64): its rows and their
+    // coefficients are wave-uniform and live in scalar registers
+    const int j0 = t.z + __builtin_amdgcn_readfirstlane(threadIdx.y) * kResRows;
+    const int ic = min(i, b.nx - 1);
+    const int im = max(ic - 1, 0), ip = min(ic + 1, b.nx - 1);
+    const double cxm = dp[b.cx + ic], cxp = dp[b.cx + b.nx + ic], dx = dp[b.cx + 2 * b.nx + ic];
+    int jr[kResRows + 2];
+    double cym[kResRows], cyp[kResRows], dy[kResRows];
+#pragma unroll
+    for (int k = 0; k < kResRows + 2; ++k) jr[k] = min(max(j0 - 1 + k, 0), b.ny - 1) * b.nx;
+#pragma unroll
+    for (int k = 0; k < kResRows; ++k) {
+        const int j = min(j0 + k, b.ny - 1);
+        cym[k] = dp[b.cy + j];
+        cyp[k] = dp[b.cy + b.ny + j];
+        dy[k] = dp[b.cy + 2 * b.ny + j];
+    }
     for (int it = i0; it < i1; ++it) {
         const int q = J.act[it];
-        const double* __restrict__ pq = J.p + q * J.plane;
-        const double* __restrict__ fq = J.f + q * J.plane;
+        const double* __restrict__ pl = J.p + q * J.plane;
+        const double* __restrict__ pq = pl + b.off;
+        const double* __restrict__ fq = J.f + q * J.plane + b.off;
         const double sig = J.shift[q];
+        double pc[kResRows + 2], xm[kResRows], xp[kResRows], fv[kResRows];
+#pragma unroll
+        for (int k = 0; k < kResRows + 2; ++k) pc[k] = pq[jr[k] + ic];
+#pragma unroll
+        for (int k = 0; k < kResRows; ++k) {
+            xm[k] = pq[jr[k + 1] + im];
+            xp[k] = pq[jr[k + 1] + ip];
+            fv[k] = fq[jr[k + 1] + ic];
+        }
         double acc = 0.0, pacc = 0.0;
-        if (i < b.nx) {
-            for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
-                const int j = t.z + r;
-                if (j >= b.ny) break;
-                const long long c = b.off + j * b.nx + i;
-                const double res = fq[c] - apply_at(pq, B, b, J.dp, i, j, sig);
-                acc += res * res;
-                pacc += pq[c] * pq[c];
-                if (MODE == 1) {
-                    J.r32[q * J.plane + c] = float(res);
-                    if (J.e32) J.e32[q * J.plane + c] = 0.0f;
-                }
+#pragma unroll
+        for (int k = 0; k < kResRows; ++k) {
+            const int j = j0 + k;
+            if (i >= b.nx || j >= b.ny) continue;
+            double vxm = xm[k], vxp = xp[k], vym = pc[k], vyp = pc[k + 2];
+            // cells on the block's edge take their neighbours by the face rules
+            if (i == 0 || i == b.nx - 1 || j == 0 || j == b.ny - 1)
+                neighbours(pl, B, b, i, j, vxm, vxp, vym, vyp);
+            const double c = pc[k + 1];
+            const double d = dx + dy[k] + sig;
+            const double res = fv[k] - (cxm * vxm + cxp * vxp + cym[k] * vym + cyp[k] * vyp + d * c);
+            acc += res * res;
+            pacc += c * c;
+            if (MODE == 1) {
+                const long long o = q * J.plane + b.off + j * b.nx + i;
+                J.r32[o] = float(res);
+                if (J.e32) J.e32[o] = 0.0f;
             }
         }
         for (int o = 32; o > 0; o >>= 1) {  // one wave is one row group (blockDim.x = 64)
@@ -601,7 +640,7 @@ template <typename T>
 __device__ void lds_smooth(const LdsArgs& a, T* p, const T* f, const DBlock* B, T sig, int colour) {
     bool any_odd = false;
     for (int bi = 0; bi < a.nb; ++bi) {
-        const DBlock b = B[bi];
+        const DBlock b = wave_uniform(B[bi]);
         any_odd |= b.oddwrap != 0;
         if (b.oddwrap == 0) {
             const int hx = (b.nx + 1) >> 1;
@@ -626,7 +665,7 @@ __device__ void lds_smooth(const LdsArgs& a, T* p, const T* f, const DBlock* B, 
     if (any_odd && colour == 1) {  // the two extra colours of odd periodic wraps
         for (int extra = 2; extra < 4; ++extra) {
             for (int bi = 0; bi < a.nb; ++bi) {
-                const DBlock b = B[bi];
+                const DBlock b = wave_uniform(B[bi]);
                 if (b.oddwrap == 0) continue;
                 const int cnt = b.nx * b.ny;
                 for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
@@ -644,8 +683,8 @@ template <typename T>
 __device__ void lds_restrict(const LdsArgs& a, const T* pf, const T* ff, T* pc, T* fc,
                              const DBlock* Bf, const DBlock* Bc, T sig) {
     for (int bi = 0; bi < a.nb; ++bi) {
-        const DBlock bc = Bc[bi];
-        const DBlock bf = Bf[bi];
+        const DBlock bc = wave_uniform(Bc[bi]);
+        const DBlock bf = wave_uniform(Bf[bi]);
         const int cnt = bc.nx * bc.ny;
         for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
             const int J = c / bc.nx, I = c - J * bc.nx;
@@ -659,7 +698,7 @@ __device__ void lds_restrict(const LdsArgs& a, const T* pf, const T* ff, T* pc, 
 template <typename T>
 __device__ void lds_prolong(const LdsArgs& a, const T* pc, T* pf, const DBlock* Bf, const DBlock* Bc) {
     for (int bi = 0; bi < a.nb; ++bi) {
-        const DBlock bf = Bf[bi];
+        const DBlock bf = wave_uniform(Bf[bi]);
         const int cnt = bf.nx * bf.ny;
         for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
             const int j = c / bf.nx, i = c - j * bf.nx;
