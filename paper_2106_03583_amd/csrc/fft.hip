@@ -37,7 +37,50 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-__device__ __forceinline__ double2 ld2(const double* t, int k) { return make_double2(t[2 * k], t[2 * k + 1]); }
+// The transform tables are never written while a kernel runs: reading them
+// through the constant address space marks the loads invariant, so they may
+// move ahead of the stores of earlier results and stay in flight together.
+typedef __attribute__((address_space(4))) const double ctab_t;
+__device__ __forceinline__ double2 ld2(const double* t, int k) {
+    const ctab_t* c = (const ctab_t*)t;
+    return make_double2(c[2 * k], c[2 * k + 1]);
+}
+
+// a / b for 0 <= a < 2^22 and 1 <= b < 2^12, from the float reciprocal rb of
+// b: the float quotient is within one of the true one, and the remainder
+// test corrects it.
+__device__ __forceinline__ int div_small(int a, int b, float rb) {
+    int q = int(float(a) * rb);
+    const int r = a - q * b;
+    if (r < 0) --q;
+    else if (r >= b) ++q;
+    return q;
+}
+
+// cos and sin of 2 pi t / R for the odd radices with closed-form butterflies
+template <int R>
+struct Roots;
+template <>
+struct Roots<3> {
+    static constexpr double c[3] = {1.0, -0.5, -0.5};
+    static constexpr double s[3] = {0.0, 0.86602540378443864676, -0.86602540378443864676};
+};
+template <>
+struct Roots<5> {
+    static constexpr double c[5] = {1.0, 0.30901699437494742410, -0.80901699437494742410,
+                                    -0.80901699437494742410, 0.30901699437494742410};
+    static constexpr double s[5] = {0.0, 0.95105651629515357212, 0.58778525229247312917,
+                                    -0.58778525229247312917, -0.95105651629515357212};
+};
+template <>
+struct Roots<7> {
+    static constexpr double c[7] = {1.0, 0.62348980185873353053, -0.22252093395631440429,
+                                    -0.90096886790241912624, -0.90096886790241912624,
+                                    -0.22252093395631440429, 0.62348980185873353053};
+    static constexpr double s[7] = {0.0, 0.78183148246802980871, 0.97492791218182360702,
+                                    0.43388373911755812048, -0.43388373911755812048,
+                                    -0.97492791218182360702, -0.78183148246802980871};
+};
 
 // XCD-aware mapping: workgroups are dispatched round-robin over the 8 XCDs;
 // give each XCD one contiguous range of tiles so neighbouring tiles share an L2.
@@ -84,6 +127,37 @@ __device__ __forceinline__ void dft(double2* v, const double* __restrict__ tw, i
         v[6] = make_double2(e[2].x - w2.x, e[2].y - w2.y);
         v[3] = make_double2(e[3].x + w3.x, e[3].y + w3.y);
         v[7] = make_double2(e[3].x - w3.x, e[3].y - w3.y);
+    } else if constexpr (R == 3 || R == 5 || R == 7) {
+        // pairs r, R - r: v_r w^{rs} + v_{R-r} w^{-rs} = a_r cos - i b_r sin
+        // with a_r = v_r + v_{R-r}, b_r = v_r - v_{R-r}, w = e^{-2 pi i / R}
+        constexpr int H = (R - 1) / 2;
+        double2 a[H], b[H];
+        double2 y0 = v[0];
+#pragma unroll
+        for (int r = 1; r <= H; ++r) {
+            a[r - 1] = make_double2(v[r].x + v[R - r].x, v[r].y + v[R - r].y);
+            b[r - 1] = make_double2(v[r].x - v[R - r].x, v[r].y - v[R - r].y);
+            y0.x += a[r - 1].x;
+            y0.y += a[r - 1].y;
+        }
+        double2 y[R];
+        y[0] = y0;
+#pragma unroll
+        for (int s = 1; s <= H; ++s) {
+            double2 re = v[0], im = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int r = 1; r <= H; ++r) {
+                const double c = Roots<R>::c[(r * s) % R], sn = Roots<R>::s[(r * s) % R];
+                re.x += c * a[r - 1].x;
+                re.y += c * a[r - 1].y;
+                im.x += sn * b[r - 1].x;
+                im.y += sn * b[r - 1].y;
+            }
+            y[s] = make_double2(re.x + im.y, re.y - im.x);      // re - i im
+            y[R - s] = make_double2(re.x - im.y, re.y + im.x);  // re + i im
+        }
+#pragma unroll
+        for (int s = 0; s < R; ++s) v[s] = y[s];
     } else {
         double2 y[R];
 #pragma unroll
@@ -111,6 +185,7 @@ __device__ void stage(double2* z, int cs, int m, int W, int Ns, const double* __
     const int nbf = m / R;
     const int total = W * nbf;
     const int step = m / (Ns * R);  // twiddle index stride
+    const float r_nbf = 1.0f / float(nbf), r_ns = 1.0f / float(Ns);
     double2 v[BPT][R];
     int dst[BPT];
 #pragma unroll
@@ -118,17 +193,20 @@ __device__ void stage(double2* z, int cs, int m, int W, int Ns, const double* __
         const int b = threadIdx.x + t * blockDim.x;
         dst[t] = -1;
         if (b < total) {
-            const int w = b / nbf, j = b - w * nbf;
-            const int k = j % Ns;
+            const int w = div_small(b, nbf, r_nbf), j = b - w * nbf;
+            const int jn = div_small(j, Ns, r_ns), k = j - jn * Ns;
             const double2* col = z + w * cs;
+            // every twiddle is read unconditionally (k = 0 reads the exact
+            // root 1), so all of the loads are in flight together;
+            // k r step < Ns R step = m: the index needs no wrap
+            double2 rt[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                double2 x = col[j + r * nbf];
-                if (r > 0 && k > 0) x = cmul(x, ld2(tw, (k * r * step) % m));
-                v[t][r] = x;
-            }
+            for (int r = 1; r < R; ++r) rt[r] = ld2(tw, k * r * step);
+            v[t][0] = col[j];
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[t][r] = cmul(col[j + r * nbf], rt[r]);
             dft<R>(v[t], tw, m);
-            dst[t] = w * cs + (j / Ns) * Ns * R + k;
+            dst[t] = w * cs + jn * Ns * R + k;
         }
     }
     __syncthreads();
@@ -193,6 +271,10 @@ __device__ void fft_columns(double2* z, int cs, const FFTArgs& a) {
     }
 }
 
+constexpr int kLoadBatch = 8;   // input elements per thread in flight together
+constexpr int kStoreBatch = 4;  // output elements per thread whose table reads go together
+constexpr int kInvBatch = 2;    // inverse cosine kinds: elements per thread read together
+
 // Forward (dir = 0) or inverse (dir = 1) transform of W columns per workgroup.
 template <int CLASS>
 __global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict__ tiles, int ntiles,
@@ -203,6 +285,7 @@ __global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict_
     const int tix = xcd_remap(blockIdx.x, ntiles);
     const FTile T = tiles[tix];
     const int n = a.n, m = a.m, W = a.W, cs = a.cs;
+    const int lw = __ffs(W) - 1;  // W is a power of two
     const int kind = a.kind;
     const double sc2 = sqrt(2.0 / n), sc1 = sqrt(1.0 / n);
     // which algorithm runs: forward kinds, and the inverse of N-N / D-D
@@ -211,36 +294,43 @@ __global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict_
     // ---------------- load + pre-processing ----------------
     if (!inv_cos) {
         bool bad = false;
-#pragma unroll 8
-        for (int idx = threadIdx.x; idx < n * W; idx += blockDim.x) {
-            int k = idx / W, w = idx - k * W;
-            double x = 0.0;
-            if (w < T.ncol) x = in[T.in_base + (long long)k * T.in_stride + w];
+        // kLoadBatch elements per thread are loaded before any is used, so
+        // their loads are in flight together.  Every load is unconditional:
+        // elements past the end repeat the last one, columns past the tile's
+        // last read that one and are zeroed.
+        for (int base = 0; base < n * W; base += kLoadBatch * blockDim.x) {
+            double xs[kLoadBatch];
+#pragma unroll
+            for (int b = 0; b < kLoadBatch; ++b) {
+                const int idx = min(base + b * int(blockDim.x) + int(threadIdx.x), n * W - 1);
+                const int k = idx >> lw, w = idx & (W - 1);
+                xs[b] = in[T.in_base + (long long)k * T.in_stride + min(w, T.ncol - 1)];
+            }
+#pragma unroll
+            for (int b = 0; b < kLoadBatch; ++b) {
+            const int idx = min(base + b * int(blockDim.x) + int(threadIdx.x), n * W - 1);
+            const int k = idx >> lw, w = idx & (W - 1);
+            double x = w >= T.ncol ? 0.0 : xs[b];
             if (!isfinite(x)) bad = true;
             double* zc = reinterpret_cast<double*>(z + w * cs);
-            int u;  // position in the length-n real sequence fed to the FFT
-            switch (kind) {
-                case Z_PP: u = k; break;
-                case Z_DD:
-                    if (k & 1) x = -x;
-                    [[fallthrough]];
-                case Z_NN: u = (k & 1) ? n - 1 - (k >> 1) : (k >> 1); break;
-                case Z_DN: {
-                    int j = n - 1 - k;  // reversed input, then the DCT-IV packing
-                    u = (j & 1) ? ((n - 1 - j) >> 1) * 2 + 1 : (j >> 1) * 2;
-                    break;
-                }
-                default:  // Z_ND
-                    u = (k & 1) ? ((n - 1 - k) >> 1) * 2 + 1 : (k >> 1) * 2;
-                    break;
-            }
+            // position u in the length-n real sequence fed to the FFT, chosen
+            // without branches: PP keeps k; NN / DD take Makhoul's even / odd
+            // reordering (DD with alternating signs); ND packs for the DCT-IV,
+            // DN packs the reversed input j = n - 1 - k the same way
+            const int uc = (k & 1) ? n - 1 - (k >> 1) : (k >> 1);
+            const int kk = kind == Z_DN ? n - 1 - k : k;
+            const int u4 = (kk & 1) ? ((n - 1 - kk) >> 1) * 2 + 1 : (kk >> 1) * 2;
+            const int u = kind == Z_PP ? k : (kind == Z_NN || kind == Z_DD) ? uc : u4;
+            x = (kind == Z_DD && (k & 1)) ? -x : x;
             zc[u] = x;  // real part at even u, imaginary part at odd u
+            }
         }
         if (bad && nonfinite) atomicOr(nonfinite, 1);
         __syncthreads();
         if (kind == Z_ND || kind == Z_DN) {
+            const float rm = 1.0f / float(m);
             for (int idx = threadIdx.x; idx < m * W; idx += blockDim.x) {
-                int w = idx / m, k = idx - w * m;
+                int w = div_small(idx, m, rm), k = idx - w * m;
                 z[w * cs + k] = cmul(z[w * cs + k], ld2(a.pre4, k));
             }
             __syncthreads();
@@ -250,43 +340,55 @@ __global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict_
         // Z_k = (V_k + conj V_{m-k}) + i (V_k - conj V_{m-k}) e^{2 pi i k/n};
         // the FFT below then computes conj(IFFT) of conj(Z).
         const int half = m / 2;
-#pragma unroll 4
-        for (int idx = threadIdx.x; idx < (half + 1) * W; idx += blockDim.x) {
-            const int k = idx / W, w = idx - k * W;
-            const bool colok = w < T.ncol;
-            // y'_q = y_q / c_q at q = k, n-k, m-k, m+k (y'_n = 0)
-            double yv0, yv1, yv2, yv3;
-#define MBP_LOAD_Y(qq, dst)                                                                   \
-    {                                                                                          \
-        double y_ = 0.0;                                                                       \
-        if ((qq) < n && colok) {                                                               \
-            const int row_ = kind == Z_DD ? n - 1 - (qq) : (qq);                               \
-            y_ = in[T.in_base + (long long)row_ * T.in_stride + w] / ((qq) == 0 ? sc1 : sc2);   \
-        }                                                                                      \
-        dst = y_;                                                                              \
-    }
-            MBP_LOAD_Y(k, yv0)
-            MBP_LOAD_Y(n - k, yv1)
-            MBP_LOAD_Y(m - k, yv2)
-            MBP_LOAD_Y(m + k, yv3)
-#undef MBP_LOAD_Y
-            // V_q = e^{i pi q/(2n)} (y'_q - i y'_{n-q}) for q = k and m - k
-            const double2 Vk = cmul(cconj(ld2(a.post, k)), make_double2(yv0, -yv1));
-            const double2 Vmk = cmul(cconj(ld2(a.post, m - k)), make_double2(yv2, -yv3));
-            // Z_kk = (A + conj B) + i (A - conj B) e^{2 pi i kk / n}
-            {
-                const double2 Bc = cconj(Vmk);
-                const double2 s = make_double2(Vk.x + Bc.x, Vk.y + Bc.y);
-                const double2 d = make_double2(Vk.x - Bc.x, Vk.y - Bc.y);
-                const double2 id = cmul(make_double2(-d.y, d.x), cconj(ld2(a.twn, k)));
-                if (k < m) z[w * cs + k] = cconj(make_double2(s.x + id.x, s.y + id.y));
+        for (int base = 0; base < (half + 1) * W; base += kInvBatch * blockDim.x) {
+            // y'_q = y_q / c_q at q = k, n-k, m-k, m+k (y'_n = 0), and the
+            // table values, read for kInvBatch elements before any is used
+            double yv[kInvBatch][4];
+            double2 pk[kInvBatch], pmk[kInvBatch], tk[kInvBatch], tmk[kInvBatch];
+#pragma unroll
+            for (int b = 0; b < kInvBatch; ++b) {
+                const int idx = min(base + b * int(blockDim.x) + int(threadIdx.x), (half + 1) * W - 1);
+                const int k = idx >> lw, w = idx & (W - 1);
+                const int qs[4] = {k, n - k, m - k, m + k};
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int qc = min(qs[v], n - 1);
+                    const int row = kind == Z_DD ? n - 1 - qc : qc;
+                    yv[b][v] = in[T.in_base + (long long)row * T.in_stride + min(w, T.ncol - 1)];
+                }
+                pk[b] = ld2(a.post, k);
+                pmk[b] = ld2(a.post, m - k);
+                tk[b] = ld2(a.twn, k);
+                tmk[b] = ld2(a.twn, m - k);
             }
-            if (k > 0 && m - k != k && m - k < m) {
-                const double2 Bc = cconj(Vk);
-                const double2 s = make_double2(Vmk.x + Bc.x, Vmk.y + Bc.y);
-                const double2 d = make_double2(Vmk.x - Bc.x, Vmk.y - Bc.y);
-                const double2 id = cmul(make_double2(-d.y, d.x), cconj(ld2(a.twn, m - k)));
-                z[w * cs + (m - k)] = cconj(make_double2(s.x + id.x, s.y + id.y));
+#pragma unroll
+            for (int b = 0; b < kInvBatch; ++b) {
+                const int idx = min(base + b * int(blockDim.x) + int(threadIdx.x), (half + 1) * W - 1);
+                const int k = idx >> lw, w = idx & (W - 1);
+                const bool colok = w < T.ncol;
+                const int qs[4] = {k, n - k, m - k, m + k};
+                double y[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    y[v] = (qs[v] < n && colok) ? yv[b][v] / (qs[v] == 0 ? sc1 : sc2) : 0.0;
+                // V_q = e^{i pi q/(2n)} (y'_q - i y'_{n-q}) for q = k and m - k
+                const double2 Vk = cmul(cconj(pk[b]), make_double2(y[0], -y[1]));
+                const double2 Vmk = cmul(cconj(pmk[b]), make_double2(y[2], -y[3]));
+                // Z_kk = (A + conj B) + i (A - conj B) e^{2 pi i kk / n}
+                {
+                    const double2 Bc = cconj(Vmk);
+                    const double2 s = make_double2(Vk.x + Bc.x, Vk.y + Bc.y);
+                    const double2 d = make_double2(Vk.x - Bc.x, Vk.y - Bc.y);
+                    const double2 id = cmul(make_double2(-d.y, d.x), cconj(tk[b]));
+                    if (k < m) z[w * cs + k] = cconj(make_double2(s.x + id.x, s.y + id.y));
+                }
+                if (k > 0 && m - k != k && m - k < m) {
+                    const double2 Bc = cconj(Vk);
+                    const double2 s = make_double2(Vmk.x + Bc.x, Vmk.y + Bc.y);
+                    const double2 d = make_double2(Vmk.x - Bc.x, Vmk.y - Bc.y);
+                    const double2 id = cmul(make_double2(-d.y, d.x), cconj(tmk[b]));
+                    z[w * cs + (m - k)] = cconj(make_double2(s.x + id.x, s.y + id.y));
+                }
             }
         }
         __syncthreads();
@@ -299,9 +401,11 @@ __global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict_
     if (inv_cos) {
         const double inv_n = 1.0 / n;
 #pragma unroll 8
-        for (int idx = threadIdx.x; idx < n * W; idx += blockDim.x) {
-            int j = idx / W, w = idx - j * W;
-            if (w >= T.ncol) continue;
+        for (int base = 0; base < n * W; base += blockDim.x) {
+            const int idx = min(base + int(threadIdx.x), n * W - 1);
+            // lanes past the tile's last column redo that column and store
+            // the same value to the same place: no branch around the store
+            int j = idx >> lw, w = min(idx & (W - 1), T.ncol - 1);
             int u = (j & 1) ? n - 1 - (j >> 1) : (j >> 1);
             double2 Fz = z[w * cs + (u >> 1)];
             double v = (u & 1) ? -Fz.y * inv_n : Fz.x * inv_n;
@@ -311,11 +415,20 @@ __global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict_
         return;
     }
     if (kind == Z_ND || kind == Z_DN) {
-#pragma unroll 4
-        for (int idx = threadIdx.x; idx < m * W; idx += blockDim.x) {
-            int k = idx / W, w = idx - k * W;
-            if (w >= T.ncol) continue;
-            double2 u = cmul(z[w * cs + k], ld2(a.post4, k));
+        for (int base = 0; base < m * W; base += kStoreBatch * blockDim.x) {
+            double2 zv[kStoreBatch], tv[kStoreBatch];
+#pragma unroll
+            for (int b = 0; b < kStoreBatch; ++b) {
+                const int idx = min(base + b * int(blockDim.x) + int(threadIdx.x), m * W - 1);
+                const int k = idx >> lw, w = min(idx & (W - 1), T.ncol - 1);
+                zv[b] = z[w * cs + k];
+                tv[b] = ld2(a.post4, k);
+            }
+#pragma unroll
+            for (int b = 0; b < kStoreBatch; ++b) {
+            const int idx = min(base + b * int(blockDim.x) + int(threadIdx.x), m * W - 1);
+            const int k = idx >> lw, w = min(idx & (W - 1), T.ncol - 1);
+            double2 u = cmul(zv[b], tv[b]);
             int q0 = 2 * k, q1 = n - 1 - 2 * k;
             double y0 = sc2 * u.x, y1 = -sc2 * u.y;
             if (kind == Z_DN) {
@@ -324,43 +437,52 @@ __global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict_
             }
             out[T.out_base + (long long)q0 * T.out_stride + w] = y0;
             out[T.out_base + (long long)q1 * T.out_stride + w] = y1;
+            }
         }
         return;
     }
     // PP / NN / DD: real DFT X_k (k = 0..m) from the half-length FFT
-#pragma unroll 4
-    for (int idx = threadIdx.x; idx < (m + 1) * W; idx += blockDim.x) {
-        int k = idx / W, w = idx - k * W;
-        if (w >= T.ncol) continue;
-        double2 Zk = z[w * cs + (k % m)];
-        double2 Zc = cconj(z[w * cs + ((m - k) % m)]);
+    for (int base = 0; base < (m + 1) * W; base += kStoreBatch * blockDim.x) {
+        double2 tks[kStoreBatch], pks[kStoreBatch], pns[kStoreBatch];
+#pragma unroll
+        for (int b = 0; b < kStoreBatch; ++b) {
+            const int k = min(base + b * int(blockDim.x) + int(threadIdx.x), (m + 1) * W - 1) >> lw;
+            tks[b] = ld2(a.twn, k);
+            pks[b] = ld2(a.post, k);
+            pns[b] = ld2(a.post, n - k);
+        }
+#pragma unroll
+        for (int b = 0; b < kStoreBatch; ++b) {
+        const int idx = min(base + b * int(blockDim.x) + int(threadIdx.x), (m + 1) * W - 1);
+        int k = idx >> lw, w = min(idx & (W - 1), T.ncol - 1);
+        const double2 tk = tks[b], pk = pks[b], pn = pns[b];
+        double2 Zk = z[w * cs + (k == m ? 0 : k)];
+        double2 Zc = cconj(z[w * cs + (k == 0 ? 0 : m - k)]);
         double2 s = make_double2(0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y + Zc.y));
         double2 d = make_double2(0.5 * (Zk.x - Zc.x), 0.5 * (Zk.y - Zc.y));
-        double2 t = cmul(ld2(a.twn, k), d);  // e^{-2 pi i k/n} (Zk - Zc) / 2
+        double2 t = cmul(tk, d);  // e^{-2 pi i k/n} (Zk - Zc) / 2
         double2 X = make_double2(s.x + t.y, s.y - t.x);  // s - i t
+        // PP: Hartley values at k and n - k; NN / DD: DCT-II
+        // y_q = c_q Re(e^{-i pi q/(2n)} X_q) at q = k and n - k (X_{n-k} = conj X_k),
+        // DD written in reversed order.  k = 0 and k = m have no partner: the
+        // second store repeats the first.  Selects, not branches, so that the
+        // loop body is one block.
+        const bool pp = kind == Z_PP, dd = kind == Z_DD, pair = k > 0 && k < m;
+        const double yk = pp ? sc1 * (X.x - X.y) : (k == 0 ? sc1 : sc2) * (pk.x * X.x - pk.y * X.y);
+        const double yn = pp ? sc1 * (X.x + X.y) : sc2 * (pn.x * X.x + pn.y * X.y);
+        const int rk = dd ? n - 1 - k : k;
+        const int rn = pp ? n - k : dd ? k - 1 : n - k;
         double* o = out + T.out_base + w;
         const long long st = T.out_stride;
-        if (kind == Z_PP) {
-            o[k * st] = sc1 * (X.x - X.y);
-            if (k > 0 && k < m) o[(n - k) * st] = sc1 * (X.x + X.y);
-        } else {
-            // DCT-II: y_q = c_q Re(e^{-i pi q/(2n)} X_q), X_{n-k} = conj X_k
-            double yk = (k == 0 ? sc1 : sc2) * (ld2(a.post, k).x * X.x - ld2(a.post, k).y * X.y);
-            int rk = kind == Z_DD ? n - 1 - k : k;
-            o[rk * st] = yk;
-            if (k > 0 && k < m) {
-                double2 pc = ld2(a.post, n - k);
-                double yn = sc2 * (pc.x * X.x + pc.y * X.y);  // Re(pc * conj X)
-                int rn = kind == Z_DD ? k - 1 : n - k;
-                o[rn * st] = yn;
-            }
+        o[rk * st] = yk;
+        o[(pair ? rn : rk) * st] = pair ? yn : yk;
         }
     }
 }
 
 int fft_col_stride(const mbp_plan* P);
 
-// Columns per workgroup: at most 16, the LDS image W * cs complex values must
+// Columns per workgroup (a power of two): at most 16, the LDS image W * cs complex values must
 // fit the budget, and every stage must fit 256 threads x (4 butterflies for
 // radices <= 8, 1 butterfly for the larger odd radices).
 constexpr int64_t kFFTLds = 80 * 1024;  // two workgroups per CU
