@@ -226,8 +226,13 @@ __device__ void stage_dispatch(double2* z, int cs, int m, int W, int Ns, const d
     if constexpr (R > 8) {
         stage<R, 1>(z, cs, m, W, Ns, tw);  // the host keeps W * m / R <= 256 here
     } else {
+        // the host keeps bpt <= 16 / R for R = 2 and 4, bpt <= 2 otherwise
         if (bpt <= 1) stage<R, 1>(z, cs, m, W, Ns, tw);
-        else stage<R, 2>(z, cs, m, W, Ns, tw);  // the host keeps W * m / R <= 512
+        else if (bpt <= 2) stage<R, 2>(z, cs, m, W, Ns, tw);
+        else if constexpr (R == 2 || R == 4) {
+            if (bpt <= 4) stage<R, 4>(z, cs, m, W, Ns, tw);
+            else if constexpr (R == 2) stage<R, 8>(z, cs, m, W, Ns, tw);
+        }
     }
 }
 
@@ -482,18 +487,29 @@ __global__ void __launch_bounds__(256) k_r2r(FFTArgs a, const FTile* __restrict_
 
 int fft_col_stride(const mbp_plan* P);
 
-// Columns per workgroup (a power of two): at most 16, the LDS image W * cs complex values must
-// fit the budget, and every stage must fit 256 threads x (4 butterflies for
-// radices <= 8, 1 butterfly for the larger odd radices).
-constexpr int64_t kFFTLds = 80 * 1024;  // two workgroups per CU
+// Columns per workgroup, a power of two up to 64: wide tiles read long row
+// segments and amortise the stage barriers.  Each stage gives a thread at
+// most 16 complex values (4 butterflies of radix 4, 8 of radix 2, 2 of the
+// radices 3 to 8, 1 of the larger ones).  The LDS image W * cs complex
+// values is held to 40 KB (four workgroups per CU) unless that leaves fewer
+// than 8 columns, then to 80 KB (two per CU).
+constexpr int64_t kFFTLdsSmall = 40 * 1024;
+constexpr int64_t kFFTLds = 80 * 1024;
+
+static int fft_width_for(const mbp_plan* P, int64_t lds) {
+    const int m = P->fft.m;
+    int W = 64;
+    while (W > 1 && int64_t(W) * fft_col_stride(P) * 16 > std::min<int64_t>(lds, P->lds_limit)) W >>= 1;
+    for (int R : P->fft.radices) {
+        const int per = R > 8 ? 1 : (R == 2 ? 8 : R == 4 ? 4 : 2);  // butterflies per thread
+        while (W > 1 && W * (m / R) > per * 256) W >>= 1;
+    }
+    return W;
+}
 
 int fft_columns_per_wg(const mbp_plan* P) {
-    const int m = P->fft.m;
-    int W = 16;
-    while (W > 1 && int64_t(W) * fft_col_stride(P) * 16 > std::min<int64_t>(kFFTLds, P->lds_limit)) W >>= 1;
-    for (int R : P->fft.radices)
-        while (W > 1 && W * (m / R) > (R > 8 ? 256 : 2 * 256)) W >>= 1;
-    return W;
+    const int W = fft_width_for(P, kFFTLdsSmall);
+    return W >= 8 ? W : fft_width_for(P, kFFTLds);
 }
 
 // Column stride in complex values: one padding slot breaks the power-of-two
