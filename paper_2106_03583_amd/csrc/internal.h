@@ -92,6 +92,7 @@ struct mbp_plan {
     int lds_level32 = 0;          // same for FP32 V-cycles
     int dp_levels_end = 0, ip_levels_end = 0;  // pool entries of all level tables
     int64_t lds_bytes64 = 0, lds_bytes32 = 0;
+    int lds_fglob64 = 0;          // FP64: level lds_level's rhs read from device memory
     int coarse_n = 0;             // cells of the coarsest plane
     std::vector<double> lambda;   // Table-1 eigenvalues
     std::vector<double> shift;    // lambda_q / dz^2

@@ -616,13 +616,16 @@ struct LdsArgs {
     const double* cmu;
     int nc;
     int dpb, dpn, ipb, ipn;  // pool ranges of the tables of levels L.. (copied into LDS)
+    int fglob;           // level L's rhs is read from device memory, not copied into LDS
     const double* cdp;   // in the kernel: the copies, indexed like the pools
     const int* cip;
 };
 
 template <typename T>
 struct LdsView {
-    T* base;             // LDS image: per level l >= L: p (plane) then f (plane)
+    T* base;             // LDS image: per level l >= L: p (plane) then f (plane; not
+                         // for level L when its rhs stays in device memory)
+    T* fL;               // level L's rhs (LDS or device memory)
     double* ctmp;        // coarse temp (nc doubles)
     double* red;         // reduction scratch (16 doubles)
     double* tdp;         // copy of the levels' coefficient / transfer tables
@@ -632,7 +635,7 @@ struct LdsView {
 template <typename T>
 __device__ __forceinline__ T* lds_p(const LdsArgs& a, const LdsView<T>& v, int l) {
     long long o = 0;
-    for (int k = a.L; k < l; ++k) o += 2LL * a.ip[a.lvinfo + 4 * k];
+    for (int k = a.L; k < l; ++k) o += (k == a.L && a.fglob ? 1LL : 2LL) * a.ip[a.lvinfo + 4 * k];
     return v.base + o;
 }
 
@@ -739,7 +742,7 @@ __device__ void lds_vcycle(const LdsArgs& a, const LdsView<T>& v, double sigd) {
         const DBlock* Bf = a.Ball + a.ip[a.lvinfo + 4 * l + 1];
         const DBlock* Bc = a.Ball + a.ip[a.lvinfo + 4 * (l + 1) + 1];
         T* pf = lds_p(a, v, l);
-        T* ff = pf + a.ip[a.lvinfo + 4 * l];
+        T* ff = l == a.L ? v.fL : pf + a.ip[a.lvinfo + 4 * l];
         T* pc = lds_p(a, v, l + 1);
         T* fc = pc + a.ip[a.lvinfo + 4 * (l + 1)];
         for (int s = 0; s < a.nu1; ++s) {
@@ -757,7 +760,7 @@ __device__ void lds_vcycle(const LdsArgs& a, const LdsView<T>& v, double sigd) {
         const DBlock* Bf = a.Ball + a.ip[a.lvinfo + 4 * l + 1];
         const DBlock* Bc = a.Ball + a.ip[a.lvinfo + 4 * (l + 1) + 1];
         T* pf = lds_p(a, v, l);
-        T* ff = pf + a.ip[a.lvinfo + 4 * l];
+        T* ff = l == a.L ? v.fL : pf + a.ip[a.lvinfo + 4 * l];
         const T* pc = lds_p(a, v, l + 1);
         lds_prolong(a, pc, pf, Bf, Bc);
         for (int s = 0; s < a.nu2; ++s) {
@@ -772,12 +775,13 @@ __device__ LdsView<T> lds_view(const LdsArgs& a, unsigned char* raw) {
     LdsView<T> v;
     v.base = reinterpret_cast<T*>(raw);
     long long e = 0;
-    for (int l = a.L; l < a.nlev; ++l) e += 2LL * a.ip[a.lvinfo + 4 * l];
+    for (int l = a.L; l < a.nlev; ++l) e += (l == a.L && a.fglob ? 1LL : 2LL) * a.ip[a.lvinfo + 4 * l];
     long long bytes = (e * (long long)sizeof(T) + 15) & ~15LL;
     v.ctmp = reinterpret_cast<double*>(raw + bytes);
     v.red = v.ctmp + ((a.nc + 1) & ~1);
     v.tdp = v.red + 16;
     v.tip = reinterpret_cast<int*>(v.tdp + a.dpn);
+    v.fL = v.base + a.ip[a.lvinfo + 4 * a.L];  // after level L's p (unless fglob)
     return v;
 }
 
@@ -813,10 +817,17 @@ __device__ __forceinline__ void lds_vcycle_body(const LdsJob<T>& J, int item) {
     LdsView<T> v = lds_view<T>(a, lds_raw);
     lds_tables(a, v);
     T* p = lds_p(a, v, a.L);
-    T* f = p + planeL;
-    for (long long c = threadIdx.x; c < planeL; c += blockDim.x) {
-        f[c] = J.fL[q * planeL + c];
-        p[c] = T(0);
+    if (a.fglob) {
+        // the rhs is only read; the sweeps and the restriction take it from
+        // device memory (just written by the level above, so cached)
+        v.fL = const_cast<T*>(J.fL + q * planeL);
+        for (long long c = threadIdx.x; c < planeL; c += blockDim.x) p[c] = T(0);
+    } else {
+        T* f = v.fL;
+        for (long long c = threadIdx.x; c < planeL; c += blockDim.x) {
+            f[c] = J.fL[q * planeL + c];
+            p[c] = T(0);
+        }
     }
     __syncthreads();
     lds_vcycle(a, v, J.shift[q]);
@@ -1005,6 +1016,7 @@ int launch_vcycle(const mbp_plan* P, T* p0, T* p0B, T* f0, const int* act, const
     }
     {
         LdsArgs a = lds_args(P, L);
+        a.fglob = is32 ? 0 : P->lds_fglob64;
         const size_t bytes = size_t(is32 ? P->lds_bytes32 : P->lds_bytes64);
         set_lds(reinterpret_cast<const void*>(k_lds_vcycle<T>), bytes);
         const LdsJob<T> J{a, P_(L), F_(L), (long long)P->levels[L].plane, P->d_shift, act, nact};

@@ -616,6 +616,20 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
             if (need(l, 4) <= budget32) P->lds_level32 = l;
         P->lds_bytes64 = need(P->lds_level, 8);
         P->lds_bytes32 = need(P->lds_level32, 4);
+        // two FP64 workgroups share a CU when the image fits half the budget;
+        // if it only fits once the top level's rhs stays in device memory
+        // (read by two sweeps and the restriction per cycle), keep it there.
+        // Not when the whole solve runs in LDS (level 0) or the top level is
+        // the coarsest (its rhs feeds the eigen solve from LDS).
+        P->lds_fglob64 = 0;
+        {
+            const int64_t fbytes = P->levels[P->lds_level].plane * 8;
+            if (P->lds_level > 0 && P->lds_level < P->nlev - 1 && P->lds_bytes64 > budget / 2 &&
+                P->lds_bytes64 - fbytes <= budget / 2) {
+                P->lds_fglob64 = 1;
+                P->lds_bytes64 -= fbytes;
+            }
+        }
         if (P->lds_bytes64 > budget) {
             if (err) *err = "coarsest plane does not fit the LDS budget";
             return MBP_ERR_INVALID;
