@@ -48,8 +48,12 @@ def two_block(nz, zpair, nx1=12, nx2=7, ny=9):
     return W.Problem([A, B], nz, 1.3, W.PAIRS[zpair], name=f"two_block_{zpair}_{nz}")
 
 
+# nz covers every radix (2..31 through n/2 = 1..31), and the workgroup shapes
+# of the power-of-two lengths: 64-column tiles (32, 64), 16 columns with four
+# radix-2 butterflies per thread (256), 8 columns in 80 KB (512, 1024), and
+# 4 columns with eight radix-2 butterflies per thread (2048).
 @pytest.mark.parametrize("kind", KINDS)
-@pytest.mark.parametrize("nz", [2, 4, 6, 8, 10, 14, 22, 26, 32, 48, 62, 64, 96, 160, 1024])
+@pytest.mark.parametrize("nz", [2, 4, 6, 8, 10, 14, 22, 26, 32, 48, 62, 64, 96, 160, 256, 512, 1024, 2048])
 def test_transforms(torch_cuda, mbp, kind, nz):
     torch = torch_cuda
     prob = two_block(nz, kind)
