@@ -320,8 +320,11 @@ __device__ __forceinline__ void residual_body(const ResJob& J, int bx, int by) {
             const int j = j0 + k;
             if (i >= b.nx || j >= b.ny) continue;
             double vxm = xm[k], vxp = xp[k], vym = pc[k], vyp = pc[k + 2];
-            // cells on the block's edge take their neighbours by the face rules
-            if (i == 0 || i == b.nx - 1 || j == 0 || j == b.ny - 1)
+            // cells on a joined or periodic face take their neighbours by the
+            // face rules; on a wall the face coefficient is zero, so the
+            // clamped (finite) value already contributes nothing
+            if ((i == 0 && b.nbr[XM] >= 0) || (i == b.nx - 1 && b.nbr[XP] >= 0) ||
+                (j == 0 && b.nbr[YM] >= 0) || (j == b.ny - 1 && b.nbr[YP] >= 0))
                 neighbours(pl, B, b, i, j, vxm, vxp, vym, vyp);
             const double c = pc[k + 1];
             const double d = dx + dy[k] + sig;
