@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload lshape|box|cube32]
                     [--precision fp64|mixed] [--lockstep] [--no-cpu] [--no-variants]
-    python bench.py --workload batch64 [--steps K]     # 64 uneven problems, batched form
+    python bench.py --workload batch64 [--steps K] [--no-variants]  # 64 uneven problems, batched form
     python bench.py --workload serve [--requests N]    # Poisson request stream, server
     python bench.py --transform-compare                # z transform: LDS FFT vs dense matrix product
     python bench.py --copy-calibrate                   # 1 GiB copies (scale for HBM byte counters)
@@ -172,7 +172,7 @@ def bench_batch(args, torch, mbp):
     rhs = [_device_rhs(torch, p.ncells, 4000 + i) for i, p in enumerate(probs)]
     t0 = time.perf_counter()
     fast = [mbp.Plan(p, precision="mixed") for p in probs]
-    plain = [mbp.Plan(p, precision="fp64") for p in probs]
+    plain = [] if args.no_variants else [mbp.Plan(p, precision="fp64") for p in probs]
     t_plan = time.perf_counter() - t0
     out_f = [torch.zeros_like(r) for r in rhs]
     out_p = [torch.zeros_like(r) for r in rhs]
@@ -188,21 +188,23 @@ def bench_batch(args, torch, mbp):
     torch.cuda.synchronize()
     t_fast = (time.perf_counter() - w0) / args.steps
     sched = mbp.batch_schedule(fast)
-    # plain FP64: one solve at a time, all modes in lockstep, host-driven
-    for pl, r, o in zip(plain, rhs, out_p):
-        pl.solve(r, o, rtol=RTOL, flags=mbp.PROJECT_RHS)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    for pl, r, o in zip(plain, rhs, out_p):
-        pl.solve(r, o, rtol=RTOL, flags=mbp.PROJECT_RHS)
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - w0
-    # the FP64 batched form, for the breakdown
-    w0 = time.perf_counter()
-    mbp.solve_batch(plain, rhs, out_p, rtol=RTOL, flags=mbp.PROJECT_RHS)
-    torch.cuda.synchronize()
-    t_fp64_batch = time.perf_counter() - w0
-    diff = max(_rel(torch, a, b) for a, b in zip(out_f, out_p))
+    t_plain = t_fp64_batch = diff = None
+    if plain:  # --no-variants: the batched form alone (e.g. under a profiler)
+        # plain FP64: one solve at a time, all modes in lockstep, host-driven
+        for pl, r, o in zip(plain, rhs, out_p):
+            pl.solve(r, o, rtol=RTOL, flags=mbp.PROJECT_RHS)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for pl, r, o in zip(plain, rhs, out_p):
+            pl.solve(r, o, rtol=RTOL, flags=mbp.PROJECT_RHS)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - w0
+        # the FP64 batched form, for the breakdown
+        w0 = time.perf_counter()
+        mbp.solve_batch(plain, rhs, out_p, rtol=RTOL, flags=mbp.PROJECT_RHS)
+        torch.cuda.synchronize()
+        t_fp64_batch = time.perf_counter() - w0
+        diff = max(_rel(torch, a, b) for a, b in zip(out_f, out_p))
     ok = all(i.status == 0 and i.rel_residual <= RTOL for i in infos)
     for pl in fast + plain:
         pl.close()
@@ -218,9 +220,9 @@ def bench_batch(args, torch, mbp):
                    "cells": ncells, "form": "mixed, batched graph replay, per-mode retirement",
                    "schedule_streams_cycles": sched},
         "grid_points_per_s": ncells / t_fast,
-        "plain_fp64_solves_per_s": len(probs) / t_plain,
-        "fp64_batched_solves_per_s": len(probs) / t_fp64_batch,
-        "speedup_vs_plain_fp64": t_plain / t_fast,
+        "plain_fp64_solves_per_s": len(probs) / t_plain if t_plain else None,
+        "fp64_batched_solves_per_s": len(probs) / t_fp64_batch if t_fp64_batch else None,
+        "speedup_vs_plain_fp64": t_plain / t_fast if t_plain else None,
         "max_rel_diff_vs_plain": diff,
         "ok": ok,
         "plan_s": round(t_plan, 2),
