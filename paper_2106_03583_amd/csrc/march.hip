@@ -1165,6 +1165,12 @@ bool group_ok(const SolveCtx& c) {
 GStage group_march32(GroupBlob& gb, const std::vector<SolveCtx*>& cs, int level, bool post, bool zero0) {
     std::vector<MArgs<float>> jobs;
     std::vector<int> gx, gy;
+    // the launch's workgroup target is shared by its problems in proportion
+    // to their work (strips x modes): every problem's workgroups share the
+    // chip, so each can reuse its strip set-up for more modes than alone
+    double total = 0.0;
+    for (const SolveCtx* c : cs)
+        if (level < c->P->lds_level32) total += double(c->P->mtile_cnt[level]) * c->nitems;
     for (const SolveCtx* c : cs) {
         const mbp_plan* P = c->P;
         if (level >= P->lds_level32) continue;
@@ -1174,7 +1180,8 @@ GStage group_march32(GroupBlob& gb, const std::vector<SolveCtx*>& cs, int level,
                               : margs<float>(P, l, P->p32[l], P->p32B[l], P->f32[l], nullptr, P->f32[l + 1],
                                              nullptr, P->d_act, P->d_nact);
         a.zero_in = post ? 0 : ((l == 0 ? zero0 : true) ? 1 : 0);
-        a.per = modes_per_wg(a.ntiles, c->nitems, a.wg_target);
+        const double share = total > 0.0 ? double(a.ntiles) * c->nitems / total : 1.0;
+        a.per = modes_per_wg(a.ntiles, c->nitems, std::max(1, int(a.wg_target * share + 0.5)));
         jobs.push_back(a);
         gx.push_back(a.ntiles);
         gy.push_back((c->nitems + a.per - 1) / a.per);
