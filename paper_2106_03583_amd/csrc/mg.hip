@@ -256,8 +256,8 @@ struct ResJob {
 
 // Items per residual workgroup: enough workgroups to fill the chip several
 // times over, the rest of the items run in turn.
-static int res_per(int ntiles, int nitems) {
-    const long long per = (long long)ntiles * nitems / 2048;
+static int res_per(int ntiles, int nitems, double share = 1.0) {
+    const long long per = (long long)(double(ntiles) * nitems / std::max(1.0, 2048.0 * share));
     return int(std::max(1LL, std::min<long long>(kResModes, per)));
 }
 
@@ -1228,10 +1228,15 @@ float* fp32_guess_to_zero(const mbp_plan* P) {
 GStage group_res32(GroupBlob& gb, const std::vector<SolveCtx*>& cs) {
     std::vector<ResJob> jobs;
     std::vector<int> gx, gy;
+    // one launch for all problems: the workgroup target is shared in
+    // proportion to each problem's tiles x modes
+    double total = 0.0;
+    for (const SolveCtx* c : cs) total += double(c->P->levels[0].ntiles) * c->nitems;
     for (const SolveCtx* c : cs) {
         const mbp_plan* P = c->P;
         const Level& L = P->levels[0];
-        const int per = res_per(L.ntiles, c->nitems);
+        const double share = total > 0.0 ? double(L.ntiles) * c->nitems / total : 1.0;
+        const int per = res_per(L.ntiles, c->nitems, share);
         jobs.push_back(ResJob{P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, P->phat,
                               P->fhat, (long long)L.plane, P->d_shift, P->d_act, P->d_nact, P->d_part,
                               P->f32[0], fp32_guess_to_zero(P), per});
