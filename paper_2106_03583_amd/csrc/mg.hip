@@ -544,8 +544,20 @@ __global__ void __launch_bounds__(1024)
 k_area_dot(const double* __restrict__ x, const double* __restrict__ a, long long n,
            double* __restrict__ out) {
     __shared__ double scratch[16];
+    constexpr int kBatch = 8;  // elements per thread whose loads go out together
     double acc = 0.0;
-    for (long long i = threadIdx.x; i < n; i += blockDim.x) acc += a[i] * x[i];
+    for (long long i0 = threadIdx.x; i0 < n; i0 += kBatch * (long long)blockDim.x) {
+        double av[kBatch], xv[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const long long i = min(i0 + k * (long long)blockDim.x, n - 1);  // in bounds, no branch
+            av[k] = a[i];
+            xv[k] = x[i];
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k)
+            acc += i0 + k * (long long)blockDim.x < n ? av[k] * xv[k] : 0.0;
+    }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if ((threadIdx.x & 63) == 0) scratch[threadIdx.x >> 6] = acc;
     __syncthreads();
