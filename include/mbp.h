@@ -94,10 +94,14 @@ typedef struct {
     int32_t bc_hi;
 } mbp_synth_desc;
 
-/* Solver options.  Pass NULL for the defaults in brackets.
+#define MBP_SMOOTHER_RBGS 0 /* red-black Gauss-Seidel (point smoother, Sec. 3.3.1) */
+
+/* Solver options (Sec. 3.3.1: the multigrid solver's settings; Sec. 2: the
+ * Helmholtz systems of implicit diffusion).  Pass NULL for the defaults in
+ * brackets.
  *   precision  MBP_FP64 | MBP_MIXED                              [MBP_FP64]
- *   nu1, nu2   red-black Gauss-Seidel sweeps before / after the
- *              coarse-grid correction                            [1, 1]
+ *   nu1, nu2   smoothing sweeps before / after the coarse-grid
+ *              correction                                        [1, 1]
  *   max_cycles cap on V-cycles (or refinement steps)             [60]
  *   flags      default solve flags OR-ed into each solve          [0]
  *   etol       target of the estimated relative solution error of
@@ -112,6 +116,14 @@ typedef struct {
  *   march      pre-smoothing form of the fused levels: 0 LDS strip
  *              tiles, 1 register march (mbp_plan_autotune may change
  *              it per level)                                     [0]
+ *   smoother   MBP_SMOOTHER_RBGS (the only smoother of this build; the
+ *              paper's PFMG also offers weighted Jacobi, which this
+ *              library uses only in its 3D multigrid, mbp3_*)  [RBGS]
+ *   helmholtz  alpha >= 0: solve (L_h - alpha) p = f, the Helmholtz
+ *              systems of implicit diffusion "solved with the same method"
+ *              (Sec. 2); every modal shift becomes lambda_q/dz^2 - alpha.
+ *              With alpha > 0 no problem is singular.  Change it between
+ *              solves with mbp_plan_set_helmholtz                  [0]
  * In the mixed form max_cycles and the reported cycles count refinement
  * steps (each one convergence test). */
 typedef struct {
@@ -122,6 +134,8 @@ typedef struct {
     double etol;
     int32_t inner;
     int32_t march;
+    int32_t smoother;
+    double helmholtz;
 } mbp_options;
 
 /* Per-solve report (caller-owned).
@@ -185,6 +199,14 @@ int mbp_plan_check(const mbp_block_desc* blocks, int nblocks, const mbp_synth_de
  * MBP_ERR_HIP, MBP_ERR_NO_DEVICE. */
 int mbp_plan_create(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* z,
                     const mbp_options* opt, mbp_plan** out);
+
+/* Change the Helmholtz term alpha (>= 0) of an idle plan, as the implicit
+ * diffusion of each Runge-Kutta substep needs (footnote of Sec. 3.3.1: the
+ * matrix diagonal is modified every substep).  Updates the modal shifts
+ * lambda_q/dz^2 - alpha on the host and the device (a blocking copy) and the
+ * plan's singular flag; no other table changes.  Errors: MBP_ERR_INVALID
+ * (NULL plan, alpha < 0 or not finite), MBP_ERR_BUSY, MBP_ERR_HIP. */
+int mbp_plan_set_helmholtz(mbp_plan* plan, double alpha);
 
 /* Layout query.  block_offsets (nblocks+1 int64, may be NULL): element
  * offsets of each block in the packed field; workspace_bytes and singular
@@ -306,7 +328,11 @@ void mbp_plan_destroy(mbp_plan* plan);
  *     MBP_ERR_INVALID for a bad problem.  Requests run with per-mode
  *     retirement and the server's options.
  *   mbp_server_poll: MBP_PENDING, or the request's final status with info
- *     filled; latency_ms (optional) = completion - submission, wall clock.
+ *     filled (info->cycles_per_mode, when not NULL, receives the request's
+ *     nz per-mode cycle counts); latency_ms (optional) = completion -
+ *     submission, wall clock.  A ticket is collected once: a later poll or
+ *     wait on it (also a wait already blocked on it in another thread)
+ *     returns MBP_ERR_INVALID.
  *   mbp_server_wait: blocks until the ticket completes, then as poll.
  *   mbp_server_destroy: waits for all work, frees every cached plan. */
 int mbp_server_create(size_t hbm_budget, int slots, const mbp_options* opt, mbp_server** out);

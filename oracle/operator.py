@@ -14,6 +14,11 @@ away: Neumann g = p_0 (no flux), Dirichlet g = -p_0 (zero on the face).
 Across a joined or periodic face df is half the sum of the two cell widths.
 z is uniform with spacing dz = lz / nz.
 
+The Helmholtz form (L_h - alpha) p, alpha >= 0, is the operator of the
+implicit-diffusion systems the paper solves "with the same numerical method"
+as the pressure equation (Sec. 2; the diagonal changes every Runge-Kutta
+substep, footnote of Sec. 3.3.1).  ``alpha`` defaults to 0 (Eq. (8) itself).
+
   * ``apply_3d``          vectorised apply on the packed multi-block field;
   * ``assemble_2d``       sparse x-y operator of one plane (for Eq. (9));
   * ``assemble_3d_dense`` dense 3D matrix built cell by cell with loops.
@@ -105,8 +110,8 @@ def _ghost_y(g, i, P, side):
     return sgn * P[i][:, first, :], dc[first]
 
 
-def apply_3d(g, p_flat: np.ndarray) -> np.ndarray:
-    """L_h p on the packed field (block after block, each (nz, ny, nx))."""
+def apply_3d(g, p_flat: np.ndarray, alpha: float = 0.0) -> np.ndarray:
+    """(L_h - alpha) p on the packed field (block after block, each (nz, ny, nx))."""
     P = g.split3(np.asarray(p_flat, dtype=np.float64))
     out = []
     kz = g.zkind
@@ -134,7 +139,7 @@ def apply_3d(g, p_flat: np.ndarray) -> np.ndarray:
             zr = Pi[-1:] * (1.0 if kz[1] == "N" else -1.0)
         Q = np.concatenate([zl, Pi, zr], axis=0)
         Lz = (Q[2:] - 2.0 * Q[1:-1] + Q[:-2]) / (g.dz * g.dz)
-        out.append((Lx + Ly + Lz).ravel())
+        out.append((Lx + Ly + Lz - alpha * Pi).ravel())
     return np.concatenate(out)
 
 
@@ -218,8 +223,8 @@ def assemble_2d(g) -> sp.csr_matrix:
     return sp.coo_matrix((v, (r, c)), shape=(M, M)).tocsr()
 
 
-def assemble_3d_dense(g) -> np.ndarray:
-    """Full 3D matrix, one cell at a time (tiny grids only)."""
+def assemble_3d_dense(g, alpha: float = 0.0) -> np.ndarray:
+    """Full 3D matrix of L_h - alpha, one cell at a time (tiny grids only)."""
     N = g.ncell3
     if N > 6000:
         raise ValueError("dense assembly is for tiny grids")
@@ -280,6 +285,7 @@ def assemble_3d_dense(g) -> np.ndarray:
                                 w = 1.0 / (dc * df)
                                 A[row, gidx(o, k, jo, r)] += w
                                 A[row, row] -= w
+                    A[row, row] -= alpha
                     # z direction (uniform)
                     w = 1.0 / (dz * dz)
                     for step, end in ((-1, zlo), (+1, zhi)):

@@ -12,7 +12,12 @@ transform back.  ``solve_separable`` diagonalises all three 1D operators of a
 single box (the direct matrix-decomposition route the paper describes for
 simple boxes, Sec. 2).  ``solve_dense`` assembles the whole 3D matrix.
 
-Singular problems (no Dirichlet condition anywhere): the rhs must be
+Every route also takes the Helmholtz shift ``alpha`` >= 0 and then solves
+(L_h - alpha) p = f, the implicit-diffusion systems of Sec. 2 (same method;
+in Eq. (9) the shift of mode q becomes lambda_q / dz^2 - alpha).  With
+alpha > 0 no problem is singular.
+
+Singular problems (no Dirichlet condition anywhere, alpha = 0): the rhs must be
 compatible, sum(V f) = 0 with V the cell volumes (``project_compatible``
 enforces it), and the solution is returned with zero volume-weighted mean.
 In Eq. (9) this affects only a mode with lambda_q = 0 on an x-y plane without
@@ -35,8 +40,8 @@ def _geom(problem):
     return problem if isinstance(problem, Geometry) else Geometry(problem)
 
 
-def is_singular(problem) -> bool:
-    return not _geom(problem).has_dirichlet()
+def is_singular(problem, alpha: float = 0.0) -> bool:
+    return alpha == 0.0 and not _geom(problem).has_dirichlet()
 
 
 def project_compatible(problem, f: np.ndarray) -> np.ndarray:
@@ -52,12 +57,12 @@ def remove_mean(problem, p: np.ndarray) -> np.ndarray:
     return p - np.dot(V, p) / V.sum()
 
 
-def residual(problem, p, f):
-    return f - apply_3d(_geom(problem), p)
+def residual(problem, p, f, alpha: float = 0.0):
+    return f - apply_3d(_geom(problem), p, alpha)
 
 
-def rel_residual(problem, p, f) -> float:
-    return float(np.linalg.norm(residual(problem, p, f)) / np.linalg.norm(f))
+def rel_residual(problem, p, f, alpha: float = 0.0) -> float:
+    return float(np.linalg.norm(residual(problem, p, f, alpha)) / np.linalg.norm(f))
 
 
 def rel_error(p, p_ref) -> float:
@@ -114,14 +119,14 @@ def _plane_solve(lu_b, rhs):
     return lu.solve(rhs)
 
 
-def solve_mode(problem, fhat_q: np.ndarray, q: int, A2=None) -> np.ndarray:
+def solve_mode(problem, fhat_q: np.ndarray, q: int, A2=None, alpha: float = 0.0) -> np.ndarray:
     """Solve Eq. (9) for one mode q (sparse LU)."""
     g = _geom(problem)
     lam = eigenvalues(g.zkind, g.nz)[q]
     if A2 is None:
         A2 = assemble_2d(g)
-    sing = (lam == 0.0) and not g.has_dirichlet_xy()
-    fac = _plane_factor(g, A2, lam / (g.dz * g.dz), sing)
+    sing = (lam == 0.0) and alpha == 0.0 and not g.has_dirichlet_xy()
+    fac = _plane_factor(g, A2, lam / (g.dz * g.dz) - alpha, sing)
     rhs = fhat_q
     if sing:
         a = g.areas()
@@ -129,25 +134,64 @@ def solve_mode(problem, fhat_q: np.ndarray, q: int, A2=None) -> np.ndarray:
     return _plane_solve(fac, rhs)
 
 
-def solve_alg1(problem, f: np.ndarray, project: bool = True) -> np.ndarray:
+def _pool_job(args):
+    """Worker: factor one shifted plane and solve its modes (runs in a child
+    process; the problem description is rebuilt there)."""
+    problem, sigma, sing, rows = args
+    g = _geom(problem)
+    fac = _plane_factor(g, assemble_2d(g), sigma, sing)
+    return np.stack([_plane_solve(fac, r) for r in rows])
+
+
+def _one_thread_per_worker():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:  # pragma: no cover - threadpoolctl missing
+        pass
+
+
+def _solve_groups_in_pool(problem, g, fhat, phat, jobs, workers):
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")  # fresh interpreters: no state of the parent is inherited
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=ctx,
+                                initializer=_one_thread_per_worker) as ex:
+        futs = {ex.submit(_pool_job, (problem, sigma, sing, fhat[qs])): qs for qs, sigma, sing in jobs}
+        for fu in cf.as_completed(futs):
+            qs = futs[fu]
+            phat[qs] = fu.result()
+
+
+def solve_alg1(problem, f: np.ndarray, project: bool = True, alpha: float = 0.0,
+               workers: int = 1) -> np.ndarray:
+    """Algorithm 1 with a sparse direct solve per mode.  ``workers`` > 1 runs
+    the independent per-shift solves in that many processes (the modes are
+    decoupled, so the result is the same; only the wall time changes)."""
     g = _geom(problem)
     f = np.asarray(f, dtype=np.float64)
-    singular = not g.has_dirichlet()
+    singular = alpha == 0.0 and not g.has_dirichlet()
     if singular and project:
         f = project_compatible(g, f)
     T = basis(g.zkind, g.nz)
     lam = eigenvalues(g.zkind, g.nz)
     fhat = _to_modes(g, f, T)                      # forward transform
-    A2 = assemble_2d(g)
+    sing_xy = alpha == 0.0 and not g.has_dirichlet_xy()
+    # modes sharing one shift (the periodic pairs q, n - q) share one factor
+    groups = {}
+    for q in range(g.nz):
+        key = (float(np.round(lam[q], 12)), bool((lam[q] == 0.0) and sing_xy))
+        groups.setdefault(key, []).append(q)
     phat = np.empty_like(fhat)
-    cache = {}
-    sing_xy = not g.has_dirichlet_xy()
-    for q in range(g.nz):                          # one 2D solve per mode
-        key = float(np.round(lam[q], 12))
-        sing = (lam[q] == 0.0) and sing_xy
-        if (key, sing) not in cache:
-            cache[(key, sing)] = _plane_factor(g, A2, lam[q] / (g.dz * g.dz), sing)
-        phat[q] = _plane_solve(cache[(key, sing)], fhat[q])
+    jobs = [(qs, lam[qs[0]] / (g.dz * g.dz) - alpha, sing) for (_, sing), qs in groups.items()]
+    if workers <= 1:
+        A2 = assemble_2d(g)
+        for qs, sigma, sing in jobs:               # one 2D solve per mode
+            fac = _plane_factor(g, A2, sigma, sing)
+            for q in qs:
+                phat[q] = _plane_solve(fac, fhat[q])
+    else:
+        _solve_groups_in_pool(problem, g, fhat, phat, jobs, workers)
     p = _from_modes(g, phat, T)                    # inverse transform
     if singular:
         p = remove_mean(g, p)
@@ -174,13 +218,13 @@ def _eig_axis(faces, lo, hi):
     return mu, W, Winv
 
 
-def solve_separable(problem, f: np.ndarray, project: bool = True) -> np.ndarray:
+def solve_separable(problem, f: np.ndarray, project: bool = True, alpha: float = 0.0) -> np.ndarray:
     g = _geom(problem)
     if g.nb != 1:
         raise ValueError("separable route needs a single box")
     b = g.blocks[0]
     f = np.asarray(f, dtype=np.float64)
-    singular = not g.has_dirichlet()
+    singular = alpha == 0.0 and not g.has_dirichlet()
     if singular and project:
         f = project_compatible(g, f)
     mux, Wx, Wix = _eig_axis(g.xf[0], *_axis_pair(b.bc[XM], b.bc[XP]))
@@ -191,7 +235,7 @@ def solve_separable(problem, f: np.ndarray, project: bool = True) -> np.ndarray:
     C = F @ Wix.T                                        # x
     C = np.einsum("jy,kyx->kjx", Wiy, C, optimize=True)  # y
     C = (Wiz @ C.reshape(g.nz, -1)).reshape(C.shape)     # z
-    den = muz[:, None, None] + muy[None, :, None] + mux[None, None, :]
+    den = muz[:, None, None] + muy[None, :, None] + mux[None, None, :] - alpha
     if singular:
         k0, j0, i0 = int(np.argmax(muz)), int(np.argmax(muy)), int(np.argmax(mux))
         den[k0, j0, i0] = 1.0
@@ -210,11 +254,11 @@ def solve_separable(problem, f: np.ndarray, project: bool = True) -> np.ndarray:
 # Dense 3D solve (tiny grids)
 # ---------------------------------------------------------------------------
 
-def solve_dense(problem, f: np.ndarray, project: bool = True) -> np.ndarray:
+def solve_dense(problem, f: np.ndarray, project: bool = True, alpha: float = 0.0) -> np.ndarray:
     g = _geom(problem)
     f = np.asarray(f, dtype=np.float64)
-    A = assemble_3d_dense(g)
-    singular = not g.has_dirichlet()
+    A = assemble_3d_dense(g, alpha)
+    singular = alpha == 0.0 and not g.has_dirichlet()
     if not singular:
         return sla.solve(A, f)
     if project:
@@ -229,9 +273,9 @@ def solve_dense(problem, f: np.ndarray, project: bool = True) -> np.ndarray:
     return x[:N]
 
 
-def solve(problem, f: np.ndarray, project: bool = True) -> np.ndarray:
+def solve(problem, f: np.ndarray, project: bool = True, alpha: float = 0.0, workers: int = 1) -> np.ndarray:
     """Direct solution by the cheapest applicable route."""
     g = _geom(problem)
     if g.nb == 1:
-        return solve_separable(g, f, project)
-    return solve_alg1(g, f, project)
+        return solve_separable(g, f, project, alpha)
+    return solve_alg1(problem, f, project, alpha, workers)

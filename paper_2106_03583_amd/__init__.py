@@ -41,7 +41,7 @@ class SynthDesc(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("max_cycles", C.c_int32), ("flags", C.c_int32), ("etol", C.c_double), ("inner", C.c_int32),
-                ("march", C.c_int32)]
+                ("march", C.c_int32), ("smoother", C.c_int32), ("helmholtz", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -79,6 +79,7 @@ def _load():
         "mbp_plan_create": (I, [C.POINTER(BlockDesc), I, C.POINTER(SynthDesc), C.POINTER(Options),
                                 C.POINTER(P)]),
         "mbp_plan_layout": (I, [P, C.POINTER(C.c_int64), C.POINTER(C.c_size_t), C.POINTER(I)]),
+        "mbp_plan_set_helmholtz": (I, [P, D]),
         "mbp_solve": (I, [P, VP, VP, D, I, VP, C.POINTER(SolveInfo)]),
         "mbp_solve_batch": (I, [C.POINTER(P), C.POINTER(VP), C.POINTER(VP), I, D, I, VP,
                                 C.POINTER(SolveInfo)]),
@@ -113,7 +114,7 @@ EXPORTED = [
     "mbp_inverse_transform", "mbp_apply_operator", "mbp_modal_shift", "mbp_plan_destroy",
     "mbp_server_create", "mbp_server_submit", "mbp_server_poll", "mbp_server_wait",
     "mbp_server_destroy", "mbp_profile_enable", "mbp_profile_read", "mbp_batch_schedule",
-    "mbp_plan_autotune",
+    "mbp_plan_autotune", "mbp_plan_set_helmholtz",
 ]
 
 
@@ -162,9 +163,13 @@ class _Desc:
         self.z = SynthDesc(int(problem.nz), float(problem.lz), int(problem.zbc[0]), int(problem.zbc[1]))
 
 
-def _options(precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0, etol=0.0, inner=0, march=0) -> Options:
+SMOOTHER_RBGS = 0
+
+
+def _options(precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0, etol=0.0, inner=0, march=0,
+             smoother=SMOOTHER_RBGS, helmholtz=0.0) -> Options:
     prec = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}[precision]
-    return Options(prec, nu1, nu2, max_cycles, flags, etol, inner, march)
+    return Options(prec, nu1, nu2, max_cycles, flags, etol, inner, march, smoother, float(helmholtz))
 
 
 def plan_check(problem, **opts) -> dict:
@@ -223,10 +228,10 @@ class Info:
 
 class Plan:
     def __init__(self, problem, precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0, etol=0.0, inner=0,
-                 march=0):
+                 march=0, smoother=SMOOTHER_RBGS, helmholtz=0.0):
         self.problem = problem
         self._desc = _Desc(problem)
-        self._opt = _options(precision, nu1, nu2, max_cycles, flags, etol, inner, march)
+        self._opt = _options(precision, nu1, nu2, max_cycles, flags, etol, inner, march, smoother, helmholtz)
         self._h = C.c_void_p()
         _check(lib.mbp_plan_create(self._desc.blocks, self._desc.nblocks, C.byref(self._desc.z),
                                    C.byref(self._opt), C.byref(self._h)), "mbp_plan_create")
@@ -244,6 +249,13 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def set_helmholtz(self, alpha: float):
+        """Solve (L_h - alpha) p = f from now on (alpha >= 0)."""
+        _check(lib.mbp_plan_set_helmholtz(self._h, float(alpha)), "mbp_plan_set_helmholtz")
+        sing = C.c_int()
+        _check(lib.mbp_plan_layout(self._h, None, None, C.byref(sing)), "mbp_plan_layout")
+        self.singular = bool(sing.value)
 
     def solve(self, rhs, p, rtol=1e-10, flags=0, stream=None, raise_on_error=True) -> Info:
         cpm = np.zeros(self.nz, dtype=np.int32)
@@ -350,21 +362,30 @@ class Server:
         self._keep[t.value] = (d, rhs, p)
         return t.value
 
-    def poll(self, ticket: int):
+    def _info(self, ticket):
         si = SolveInfo()
+        keep = self._keep.get(ticket)
+        cpm = None
+        if keep is not None:
+            cpm = np.zeros(int(keep[0].z.nz), dtype=np.int32)
+            si.cycles_per_mode = cpm.ctypes.data_as(C.POINTER(C.c_int32))
+        return si, cpm
+
+    def poll(self, ticket: int):
+        si, cpm = self._info(ticket)
         lat = C.c_double()
         st = lib.mbp_server_poll(self._h, C.c_uint64(ticket), C.byref(si), C.byref(lat))
         if st == PENDING:
             return None
         self._keep.pop(ticket, None)
-        return st, Info(si, None), lat.value
+        return st, Info(si, cpm), lat.value
 
     def wait(self, ticket: int):
-        si = SolveInfo()
+        si, cpm = self._info(ticket)
         lat = C.c_double()
         st = lib.mbp_server_wait(self._h, C.c_uint64(ticket), C.byref(si), C.byref(lat))
         self._keep.pop(ticket, None)
-        return st, Info(si, None), lat.value
+        return st, Info(si, cpm), lat.value
 
     def close(self):
         if self._h:

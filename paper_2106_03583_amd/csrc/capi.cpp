@@ -33,7 +33,7 @@ const char* mbp_status_string(int status) {
     }
 }
 
-int mbp_version(void) { return 100; }
+int mbp_version(void) { return 200; }
 
 int mbp_grid_tanh(int n, double lmin, double lmax, int type, double factor, double* faces_out) {
     return grid_tanh(n, lmin, lmax, type, factor, faces_out);
@@ -92,6 +92,20 @@ int mbp_plan_create(const mbp_block_desc* blocks, int nblocks, const mbp_synth_d
     return MBP_OK;
 }
 
+int mbp_plan_set_helmholtz(mbp_plan* plan, double alpha) {
+    if (!plan || !(alpha >= 0.0) || !std::isfinite(alpha)) return MBP_ERR_INVALID;
+    if (!plan->busy.claim()) return MBP_ERR_BUSY;
+    plan->opt.helmholtz = alpha;
+    plan_set_shifts(plan);
+    const size_t nz = plan->shift.size();
+    int st = MBP_OK;
+    if (hipMemcpy(plan->d_shift, plan->shift.data(), nz * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(plan->d_sabs, plan->sabs.data(), nz * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        st = MBP_ERR_HIP;
+    plan->busy.release();
+    return st;
+}
+
 int mbp_plan_layout(const mbp_plan* plan, int64_t* block_offsets, size_t* workspace_bytes,
                     int* singular) {
     if (!plan) return MBP_ERR_INVALID;
@@ -105,13 +119,12 @@ int mbp_plan_layout(const mbp_plan* plan, int64_t* block_offsets, size_t* worksp
 int mbp_solve(mbp_plan* plan, const double* rhs_dev, double* p_dev, double rtol, int flags,
               void* stream, mbp_solve_info* info) {
     if (!plan || !rhs_dev || !p_dev || !(rtol > 0.0) || rhs_dev == p_dev) return MBP_ERR_INVALID;
-    if (plan->busy) return MBP_ERR_BUSY;
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) return MBP_ERR_INVALID;
-    plan->busy = true;
+    if (!plan->busy.claim()) return MBP_ERR_BUSY;
     int st = solve_one(plan, rhs_dev, p_dev, rtol, flags | plan->opt.flags,
                        static_cast<hipStream_t>(stream), info);
-    plan->busy = false;
+    plan->busy.release();
     return st;
 }
 
@@ -122,15 +135,18 @@ int mbp_solve_batch(mbp_plan* const* plans, const double* const* rhs_dev, double
     if (hipGetDevice(&dev) != hipSuccess) return MBP_ERR_HIP;
     for (int i = 0; i < count; ++i) {
         if (!plans[i] || !rhs_dev[i] || !p_dev[i] || rhs_dev[i] == p_dev[i]) return MBP_ERR_INVALID;
-        if (plans[i]->busy) return MBP_ERR_BUSY;
         if (plans[i]->device != dev) return MBP_ERR_INVALID;
         for (int k = 0; k < i; ++k)
             if (plans[k] == plans[i]) return MBP_ERR_INVALID;
     }
-    for (int i = 0; i < count; ++i) plans[i]->busy = true;
+    for (int i = 0; i < count; ++i)
+        if (!plans[i]->busy.claim()) {
+            for (int k = 0; k < i; ++k) plans[k]->busy.release();
+            return MBP_ERR_BUSY;
+        }
     int st = solve_batch(plans, rhs_dev, p_dev, count, rtol, flags, static_cast<hipStream_t>(stream),
                          infos);
-    for (int i = 0; i < count; ++i) plans[i]->busy = false;
+    for (int i = 0; i < count; ++i) plans[i]->busy.release();
     return st;
 }
 
@@ -167,12 +183,11 @@ int mbp_modal_shift(const mbp_plan* plan, double* shift_host) {
 
 int mbp_plan_autotune(mbp_plan* plan, const double* rhs_dev, void* stream, mbp_tuning* out) {
     if (!plan || !rhs_dev) return MBP_ERR_INVALID;
-    if (plan->busy) return MBP_ERR_BUSY;
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) return MBP_ERR_INVALID;
-    plan->busy = true;
+    if (!plan->busy.claim()) return MBP_ERR_BUSY;
     const int st = plan_autotune(plan, rhs_dev, static_cast<hipStream_t>(stream), out);
-    plan->busy = false;
+    plan->busy.release();
     return st;
 }
 

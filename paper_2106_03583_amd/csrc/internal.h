@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
@@ -76,6 +77,25 @@ struct Item {
 
 struct DevPlan;  // device pointers of one plan (see below)
 
+// "One solve in flight per plan": claimed atomically so that two host
+// threads calling into the same plan cannot both pass the check.  Copyable
+// (the value is copied) so that plan descriptions can still be copied.
+struct BusyFlag {
+    std::atomic<bool> v{false};
+    BusyFlag() = default;
+    BusyFlag(const BusyFlag& o) : v(o.v.load()) {}
+    BusyFlag& operator=(const BusyFlag& o) {
+        v.store(o.v.load());
+        return *this;
+    }
+    bool claim() {
+        bool expect = false;
+        return v.compare_exchange_strong(expect, true);
+    }
+    void release() { v.store(false); }
+    bool held() const { return v.load(); }
+};
+
 struct FFTPlan {
     int n = 0, m = 0;              // real length, complex length n/2
     std::vector<int> radices;      // Stockham stages, product = m
@@ -125,7 +145,7 @@ struct mbp_plan {
     std::vector<int64_t> block_off;  // packed-field element offsets, nb + 1
     // ---- device state ----
     int device = -1;
-    bool busy = false;
+    mbp::BusyFlag busy;
     void* dmem = nullptr;         // one allocation holding everything below
     size_t dbytes = 0;
     mbp::DBlock* d_blk = nullptr;
@@ -173,6 +193,7 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
 int build_plan_host(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* z,
                     const mbp_options* opt, mbp_plan* P, std::string* err);
 void options_default(mbp_options* o);
+void plan_set_shifts(mbp_plan* P);  // shift, sabs, singular from lambda and opt.helmholtz
 int grid_tanh(int n, double lmin, double lmax, int type, double factor, double* out);
 
 // fft.hip (host helpers)

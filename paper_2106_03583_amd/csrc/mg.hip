@@ -575,12 +575,13 @@ __global__ void k_sub(double* __restrict__ x, long long n, const double* __restr
         x[i] -= m;
 }
 
-// L_h p on the packed 3D field: x-y part from the level-0 tables, z part
-// with the ghost rules of the pair (N: g = p0, D: g = -p0, P: wrap).
+// (L_h - alpha) p on the packed 3D field: x-y part from the level-0 tables,
+// z part with the ghost rules of the pair (N: g = p0, D: g = -p0, P: wrap),
+// alpha the Helmholtz term (0 for the pressure equation).
 __global__ void __launch_bounds__(256)
 k_apply3d(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntiles,
           const double* __restrict__ dp, const double* __restrict__ p, double* __restrict__ out,
-          int nz, double idz2, int zkind) {
+          int nz, double idz2, int zkind, double alpha) {
     const int k = blockIdx.y;
     const int4 t = tiles[xcd_remap_mg(blockIdx.x, ntiles)];
     const DBlock b = B[t.x];
@@ -611,7 +612,7 @@ k_apply3d(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntil
         else zm = zkind == Z_PP ? p[c + (nz - 1) * cols] : ((zkind == Z_NN || zkind == Z_ND) ? v : -v);
         if (k < nz - 1) zp = p[c + cols];
         else zp = zkind == Z_PP ? p[c - (nz - 1) * cols] : ((zkind == Z_NN || zkind == Z_DN) ? v : -v);
-        const double d = dp[b.cx + 2 * b.nx + i] + dp[b.cy + 2 * b.ny + j];
+        const double d = dp[b.cx + 2 * b.nx + i] + dp[b.cy + 2 * b.ny + j] - alpha;
         out[c] = dp[b.cx + i] * xm + dp[b.cx + b.nx + i] * xp + dp[b.cy + j] * ym +
                  dp[b.cy + b.ny + j] * yp + d * v + (zm - 2.0 * v + zp) * idz2;
     }
@@ -1183,7 +1184,7 @@ void launch_apply3d(const mbp_plan* P, const double* p, double* out, hipStream_t
     const Level& L = P->levels[0];
     hipLaunchKernelGGL(k_apply3d, dim3(L.ntiles, P->g.nz), dim3(kTileX, kRowsPerPass), 0, s,
                        P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, out,
-                       P->g.nz, 1.0 / (P->g.dz * P->g.dz), int(P->g.zkind));
+                       P->g.nz, 1.0 / (P->g.dz * P->g.dz), int(P->g.zkind), P->opt.helmholtz);
 }
 
 // ============================ grouped launches ============================

@@ -21,6 +21,8 @@ void options_default(mbp_options* o) {
     o->etol = 0.0;
     o->inner = 2;
     o->march = 0;
+    o->smoother = MBP_SMOOTHER_RBGS;
+    o->helmholtz = 0.0;
 }
 
 // Hyperbolic-tangent face clustering (Sec. 3.1, Table 2 caption).  Two-sided:
@@ -238,6 +240,30 @@ std::vector<int> fft_radices(int m) {
 
 }  // namespace
 
+// Modal shifts of Eq. (9), sigma_q = lambda_q / dz^2 - alpha, with alpha >= 0
+// the Helmholtz term of the implicit-diffusion systems (Sec. 2; the diagonal
+// changes every Runge-Kutta substep, footnote of Sec. 3.3.1).  Also the lower
+// bound |mu + sigma_q| >= sabs_q of the mode's non-null eigenvalue magnitudes
+// used by the error test: a plane without Dirichlet faces has the constant
+// mode (mu = 0), so its smallest magnitude is |sigma_q| unless sigma_q = 0
+// (the null mode, removed by the gauge), where it is mu0.  The problem is
+// singular only without Dirichlet conditions and with alpha = 0.
+void plan_set_shifts(mbp_plan* P) {
+    const Geometry& g = P->g;
+    const int nz = g.nz;
+    const double alpha = P->opt.helmholtz;
+    P->shift.resize(nz);
+    P->sabs.resize(nz);
+    for (int q = 0; q < nz; ++q) {
+        const long double s = (long double)P->lambda[q] / ((long double)g.dz * g.dz) - alpha;
+        P->shift[q] = double(s);
+        const double as = std::fabs(P->shift[q]);
+        P->sabs[q] = g.dirichlet_xy ? P->mu0 + as : (as > 0.0 ? as : P->mu0);
+    }
+    const bool zd = g.zlo == MBP_DIRICHLET || g.zhi == MBP_DIRICHLET;
+    P->g.singular = !g.dirichlet_xy && !zd && alpha == 0.0;
+}
+
 int build_plan_host(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* z,
                     const mbp_options* opt, mbp_plan* P, std::string* err) {
     return build_plan_host_limits(blocks, nblocks, z, opt, 64 * 1024, P, err);
@@ -268,6 +294,14 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
             if (err) *err = "bad pre-smoothing form";
             return MBP_ERR_INVALID;
         }
+        if (P->opt.smoother != MBP_SMOOTHER_RBGS) {
+            if (err) *err = "unknown smoother";
+            return MBP_ERR_INVALID;
+        }
+        if (!(P->opt.helmholtz >= 0.0) || !std::isfinite(P->opt.helmholtz)) {
+            if (err) *err = "Helmholtz shift must be finite and >= 0";
+            return MBP_ERR_INVALID;
+        }
     } else {
         options_default(&P->opt);
     }
@@ -289,9 +323,7 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
         if (g.zkind == Z_PP && q == 0) lam = 0.0L;
         if (g.zkind == Z_NN && q == 0) lam = 0.0L;
         P->lambda[q] = double(lam);
-        P->shift[q] = double(lam / ((long double)g.dz * g.dz));
     }
-    P->sabs.resize(nz);
 
     // ---- multigrid levels: full coarsening while every block has >= 4 cells
     //      per direction; odd counts merge their last three cells ----
@@ -641,7 +673,7 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
         }
     }
 
-    for (int q = 0; q < nz; ++q) P->sabs[q] = P->mu0 + std::fabs(P->shift[q]);
+    plan_set_shifts(P);
 
     // ---- level summary for the kernels ----
     {

@@ -60,6 +60,7 @@ struct Request {
     // result
     int status = MBP_OK;
     mbp_solve_info info{};
+    std::vector<int32_t> cycles;  // per mode, handed out by poll / wait
     double latency_ms = 0.0;
 };
 
@@ -89,6 +90,8 @@ std::string describe(const mbp_block_desc* blocks, int nblocks, const mbp_synth_
     put(&opt.etol, sizeof(opt.etol));
     put(&opt.inner, sizeof(opt.inner));
     put(&opt.march, sizeof(opt.march));
+    put(&opt.smoother, sizeof(opt.smoother));
+    put(&opt.helmholtz, sizeof(opt.helmholtz));
     return k;
 }
 
@@ -210,7 +213,10 @@ struct mbp_server {
             case kEpilogue: {
                 const hipError_t q = hipEventQuery(r->ev);
                 if (q == hipErrorNotReady) return false;
+                r->cycles.assign(size_t(c.P->g.nz), 0);
+                r->info.cycles_per_mode = r->cycles.data();
                 int st = q == hipSuccess ? ctx_info(c, s, &r->info) : MBP_ERR_HIP;
+                r->info.cycles_per_mode = nullptr;
                 r->status = st != MBP_OK ? st : c.status;
                 r->info.status = r->status;
                 r->latency_ms =
@@ -389,12 +395,14 @@ static int take_result(mbp_server* S, uint64_t ticket, mbp_solve_info* info, dou
         int32_t* keep = info->cycles_per_mode;
         *info = r->info;
         info->cycles_per_mode = keep;
+        if (keep && !r->cycles.empty()) std::memcpy(keep, r->cycles.data(), r->cycles.size() * sizeof(int32_t));
     }
     if (latency_ms) *latency_ms = r->latency_ms;
     S->finished.erase(it);
     S->all.erase(ticket);
     (void)hipEventDestroy(r->ev);
     delete r;
+    S->cv_done.notify_all();  // other waiters on this ticket re-check and leave
     return st;
 }
 
@@ -410,7 +418,13 @@ int mbp_server_wait(mbp_server* S, uint64_t ticket, mbp_solve_info* info, double
     if (!S) return MBP_ERR_INVALID;
     std::unique_lock<std::mutex> lk(S->mu);
     if (S->all.find(ticket) == S->all.end()) return MBP_ERR_INVALID;
-    S->cv_done.wait(lk, [&] { return S->finished.find(ticket) != S->finished.end(); });
+    // Another thread may collect the same ticket first (wait or poll): then
+    // the ticket is gone from `all` and this waiter reports it as invalid
+    // instead of waiting for a result that will never come.
+    S->cv_done.wait(lk, [&] {
+        return S->finished.find(ticket) != S->finished.end() || S->all.find(ticket) == S->all.end();
+    });
+    if (S->finished.find(ticket) == S->finished.end()) return MBP_ERR_INVALID;
     return take_result(S, ticket, info, latency_ms);
 }
 

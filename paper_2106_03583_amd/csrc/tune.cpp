@@ -51,6 +51,10 @@ int plan_autotune(mbp_plan* P, const double* rhs, hipStream_t s, mbp_tuning* out
         if (out) out->wg_target = P->wg_target;
         return MBP_OK;
     }
+    // Fill every buffer a V-cycle reads before timing it: the test computes
+    // the finest residual (and, for a mixed plan, its FP32 copy, the rhs of
+    // the FP32 V-cycles), so no candidate runs on uninitialised memory.
+    ctx_test(c, s);
     c.cycles = 1;  // from here on the iterate is not zero
     hipEvent_t a, b;
     (void)hipEventCreate(&a);

@@ -171,3 +171,34 @@ def test_server_budget_and_errors(torch_cuda, mbp):
         srv.submit(big, rb, ob)
     assert e.value.status == mbp.ERR_TOO_LARGE
     srv.close()
+
+
+def test_server_two_waiters_one_ticket(torch_cuda, mbp):
+    """Two host threads wait on the same ticket: one collects the result, the
+    other is told the ticket is no longer valid; neither blocks for ever."""
+    import ctypes as C
+    import threading
+    torch = torch_cuda
+    pr = W.box(96, 80, 16, 96 / 128, 80 / 128, 16 / 128, "DD", "NN", "PP", name="w2")
+    f = W.rhs(pr, 500)
+    r = dev(torch, f)
+    o = torch.zeros_like(r)
+    torch.cuda.synchronize()
+    srv = mbp.Server(hbm_budget=1 << 30, slots=2, precision="fp64")
+    t = srv.submit(pr, r, o, flags=mbp.PROJECT_RHS)
+    codes = []
+
+    def waiter():
+        si = mbp.SolveInfo()
+        lat = C.c_double()
+        codes.append(mbp.lib.mbp_server_wait(srv._h, C.c_uint64(t), C.byref(si), C.byref(lat)))
+
+    ths = [threading.Thread(target=waiter) for _ in range(2)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join(timeout=60)
+    assert not any(th.is_alive() for th in ths), "a waiter is still blocked"
+    assert sorted(codes) == sorted([mbp.OK, mbp.ERR_INVALID]), codes
+    _check(pr, o.cpu().numpy(), f, "two-waiters")
+    srv.close()

@@ -240,55 +240,6 @@ def test_deterministic(torch_cuda, mbp):
 
 
 # ---------------------------------------------------------------------------
-# Full sizes (the workloads bench.py times), checked on sampled modes: the
-# oracle solves a few shifted planes one by one (sparse LU) and the GPU
-# solution is compared with them in mode space; every other mode is checked
-# through the residual of the full 3D operator.
-# ---------------------------------------------------------------------------
-
-def _full_size_case(torch, mbp, prob, seed, dist, precision, modes):
-    f = W.rhs(prob, seed, dist)
-    fd = dev(torch, f)
-    plan = mbp.Plan(prob, precision=precision)
-    p = torch.zeros_like(fd)
-    flags = mbp.PROJECT_RHS | mbp.RETIRE
-    info = plan.solve(fd, p, rtol=1e-10, flags=flags)
-    assert info.status == 0 and info.rel_residual <= 1e-10
-    # residual of the 3D operator on the device, every cell
-    Ap = torch.empty_like(fd)
-    plan.apply(p, Ap)
-    fp = fd - info.removed_mean
-    res3 = float(torch.linalg.vector_norm(fp - Ap) / torch.linalg.vector_norm(fp))
-    # sampled modes: oracle plane solves of the same modal rhs
-    ph = torch.empty_like(fd)
-    plan.forward(p, ph)
-    ph = ph.cpu().numpy().reshape(prob.nz, -1)
-    fproj = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
-    fh = oracle.modal_rhs(prob, fproj, modes)
-    errs = []
-    for i, q in enumerate(modes):
-        ref = oracle.solve_mode(prob, fh[i], q)
-        errs.append(float(np.linalg.norm(ph[q] - ref) / np.linalg.norm(ref)))
-    print(f"  {prob.name} {precision}: cycles={info.cycles} residual3d={res3:.2e} "
-          f"mode errors={[f'{e:.1e}' for e in errs]}", flush=True)
-    assert res3 <= 1e-10
-    assert max(errs) <= 1e-9
-    plan.close()
-
-
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_full_size_lshape(torch_cuda, mbp, precision):
-    print(f"full-size L-shape {precision}", flush=True)
-    _full_size_case(torch_cuda, mbp, W.config2(), W.CONFIG_SEEDS[2], W.CONFIG_DIST[2], precision, [0, 1, 255, 511])
-
-
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_full_size_box(torch_cuda, mbp, precision):
-    print(f"full-size box {precision}", flush=True)
-    _full_size_case(torch_cuda, mbp, W.config3(), W.CONFIG_SEEDS[3], W.CONFIG_DIST[3], precision, [0, 1, 1023])
-
-
-# ---------------------------------------------------------------------------
 # Schedules: the register-march pre-smoothing form and the plan autotuner must
 # leave the answer unchanged.
 # ---------------------------------------------------------------------------
@@ -312,12 +263,13 @@ def test_register_march_form(torch_cuda, mbp, prob, precision):
     plan.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("prob", [W.lshape(96, 6, 1.5, 1.0), _global_problems()[2]], ids=lambda p: p.name)
-def test_plan_autotune(torch_cuda, mbp, prob):
+def test_plan_autotune(torch_cuda, mbp, prob, precision):
     torch = torch_cuda
     f = W.rhs(prob, 35)
     fd = dev(torch, f)
-    plan = mbp.Plan(prob)
+    plan = mbp.Plan(prob, precision=precision)
     t = plan.autotune(fd)
     print(f"  tuning {prob.name}: {t}", flush=True)
     assert t["ms_tuned"] <= t["ms_default"] + 1e-9

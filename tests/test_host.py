@@ -117,6 +117,19 @@ def test_plan_check_singular_flag(mbp):
     assert not mbp.plan_check(W.box(8, 8, 4, 1, 1, 1, "ND", "PP", "PP"))["singular"]
 
 
+def test_helmholtz_and_smoother_options(mbp):
+    """The Helmholtz term (Sec. 2, implicit diffusion) removes the singular
+    null space; negative or non-finite terms and unknown smoothers are refused."""
+    prob = W.box(8, 8, 4, 1, 1, 1, "NN", "NN", "PP")
+    assert mbp.plan_check(prob)["singular"]
+    assert not mbp.plan_check(prob, helmholtz=2.0)["singular"]
+    assert mbp.plan_check_status(prob, helmholtz=-1.0) == mbp.ERR_INVALID
+    assert mbp.plan_check_status(prob, helmholtz=float("nan")) == mbp.ERR_INVALID
+    assert mbp.plan_check_status(prob, helmholtz=float("inf")) == mbp.ERR_INVALID
+    assert mbp.plan_check_status(prob, smoother=7) == mbp.ERR_INVALID
+    assert mbp.lib.mbp_plan_set_helmholtz(None, 1.0) == mbp.ERR_INVALID
+
+
 def test_workload_generators():
     c4 = W.config4()
     assert len(c4) == 64
