@@ -285,6 +285,70 @@ def bench_single(args, torch, mbp, prob, f, with_variants=True):
 
 
 # ---------------------------------------------------------------------------
+# 3D multigrid without the z synthesis (the paper's comparison solver)
+# ---------------------------------------------------------------------------
+
+def bench_mg3d(args, torch, mbp, prob, f, t_fft_ms, reps=3):
+    """Weighted-Jacobi V(2,2) cycles on the whole 3D system, to the same
+    1e-10 relative residual; the FFT-accelerated solve's time over this one
+    is the paper's speed-up figure (Sec. 4.2)."""
+    fd = torch.from_numpy(f).cuda()
+    plan = mbp.Plan3D(prob)
+    p = torch.zeros_like(fd)
+    flags = mbp.PROJECT_RHS
+    plan.solve(fd, p, rtol=RTOL, flags=flags)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    infos = []
+    for k in range(reps):
+        infos.append(plan.solve(fd, p, rtol=RTOL, flags=flags, stream=stream))
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]
+    ms = float(np.mean(per))
+    last = infos[-1]
+    ok = all(i.status == 0 and i.rel_residual <= RTOL for i in infos)
+    # dominant kernel: the finest-level Jacobi sweep, timed alone (read p, f; write p)
+    q = torch.empty_like(p)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    plan.jacobi_sweep(p, q, fd)
+    a.record(stream)
+    nl = 10
+    for k in range(nl):
+        plan.jacobi_sweep(p if k % 2 == 0 else q, q if k % 2 == 0 else p, fd, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    sweep_ms = a.elapsed_time(b) / nl
+    sweep_bytes = 24.0 * prob.ncells
+    # whole-solve byte model: per cycle and level, (nu1 + nu2) sweeps of 3 words,
+    # residual + restriction (2 words + 1 coarse word), prolongation + correction
+    # (2 words + 1 coarse word); plus the rhs norm and the final residual (2 + 2 words)
+    cl = plan.cells_per_level
+    cyc_bytes = sum(8.0 * (4 * 3 * cl[i] + 4 * cl[i] + 2 * cl[i + 1]) for i in range(len(cl) - 1))
+    solve_bytes = last.cycles * cyc_bytes + 8.0 * 4 * prob.ncells
+    rec = {"ms_per_solve": round(ms, 3), "ms_min": round(float(np.min(per)), 3), "cycles": last.cycles,
+           "rel_residual": last.rel_residual, "grid_points_per_s": prob.ncells / (ms * 1e-3), "ok": ok,
+           "levels": plan.nlevels, "nz_per_level": plan.nz_per_level,
+           "fft_accelerated_speedup": ms / t_fft_ms,
+           "roofline": {"bound": "hbm", "kernel": "k3_jacobi (finest weighted-Jacobi sweep)",
+                        "achieved": round(sweep_bytes / (sweep_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(sweep_bytes / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "traffic": None, "avg_launch_ms": round(sweep_ms, 4),
+                        "bytes_model": "24 B per cell (read p, f; write p)"},
+           "solve_roofline": {"bytes_per_solve": solve_bytes,
+                              "achieved_GBs": round(solve_bytes / (ms * 1e-3) / 1e9, 1),
+                              "frac": round(solve_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    plan.close()
+    del fd, p, q
+    torch.cuda.empty_cache()
+    log(f"mg3d {prob.name}: {ms:.1f} ms/solve, {last.cycles} cycles; FFT-accelerated is "
+        f"{rec['fft_accelerated_speedup']:.2f}x faster")
+    return rec
+
+
+# ---------------------------------------------------------------------------
 # Batched form
 # ---------------------------------------------------------------------------
 
@@ -613,6 +677,9 @@ def main(argv=None):
     prob, seed, dist = _workload(name)
     f = W.rhs(prob, seed, dist)
     main_rec, variants = bench_single(args, torch, mbp, prob, f, with_variants=not args.no_variants)
+    mg3d = None
+    if not args.no_variants and args.workload in ("headline", "box", "lshape"):
+        mg3d = bench_mg3d(args, torch, mbp, prob, f, main_rec["ms_per_solve"])
     cpu = None
     if not args.no_cpu:
         log("cpu baseline (oracle, full run on the same field)")
@@ -626,9 +693,10 @@ def main(argv=None):
         lf = W.rhs(lp, lseed, ldist)
         largs = argparse.Namespace(**{**vars(args), "precision": "fp64", "lockstep": False})
         lmain, lvar = bench_single(largs, torch, mbp, lp, lf, with_variants=True)
+        lmg = bench_mg3d(largs, torch, mbp, lp, lf, lmain["ms_per_solve"])
         del lf
         sub["lshape"] = {"config": {"workload": lp.name, "cells": lp.ncells, "nz": lp.nz, "blocks": 3},
-                         "fp64": _strip(lmain), **{k: _strip(v) for k, v in lvar.items()}}
+                         "fp64": _strip(lmain), **{k: _strip(v) for k, v in lvar.items()}, "mg3d": lmg}
         sub["batch64"] = bench_batch(args, torch, mbp, not args.no_cpu)
         sub["serve"] = bench_serve(args, torch, mbp, not args.no_cpu)
 
@@ -657,6 +725,8 @@ def main(argv=None):
         out["mixed"] = {"grid_points_per_s": variants["mixed_retire"]["grid_points_per_s"],
                         "ms_per_solve": variants["mixed_retire"]["ms_per_solve"],
                         "speedup_vs_fp64": ms / variants["mixed_retire"]["ms_per_solve"]}
+    if mg3d:
+        out["mg3d"] = mg3d
     if sub:
         out["sub"] = sub
     ok = main_rec["ok"] and all(v.get("ok", True) for v in variants.values()) and \

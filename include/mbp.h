@@ -94,7 +94,11 @@ typedef struct {
     int32_t bc_hi;
 } mbp_synth_desc;
 
-#define MBP_SMOOTHER_RBGS 0 /* red-black Gauss-Seidel (point smoother, Sec. 3.3.1) */
+/* Smoothers (Sec. 3.3.1: the paper's PFMG offers weighted Jacobi and
+ * red-black Gauss-Seidel point smoothers). */
+#define MBP_SMOOTHER_DEFAULT 0 /* the solver's own: RB-GS (FFT path), weighted Jacobi (mbp3_*) */
+#define MBP_SMOOTHER_RBGS    1 /* red-black Gauss-Seidel; FFT-accelerated path only */
+#define MBP_SMOOTHER_JACOBI  2 /* weighted Jacobi, omega = 6/7; 3D multigrid (mbp3_*) only */
 
 /* Solver options (Sec. 3.3.1: the multigrid solver's settings; Sec. 2: the
  * Helmholtz systems of implicit diffusion).  Pass NULL for the defaults in
@@ -116,9 +120,8 @@ typedef struct {
  *   march      pre-smoothing form of the fused levels: 0 LDS strip
  *              tiles, 1 register march (mbp_plan_autotune may change
  *              it per level)                                     [0]
- *   smoother   MBP_SMOOTHER_RBGS (the only smoother of this build; the
- *              paper's PFMG also offers weighted Jacobi, which this
- *              library uses only in its 3D multigrid, mbp3_*)  [RBGS]
+ *   smoother   MBP_SMOOTHER_DEFAULT | _RBGS (FFT path) | _JACOBI (mbp3_*)
+ *                                                                [DEFAULT]
  *   helmholtz  alpha >= 0: solve (L_h - alpha) p = f, the Helmholtz
  *              systems of implicit diffusion "solved with the same method"
  *              (Sec. 2); every modal shift becomes lambda_q/dz^2 - alpha.
@@ -313,6 +316,49 @@ int mbp_plan_autotune(mbp_plan* plan, const double* rhs_dev, void* stream, mbp_t
 /* Release the plan's device memory.  The caller ensures no work is in
  * flight on it.  NULL is ignored. */
 void mbp_plan_destroy(mbp_plan* plan);
+
+/* ---- 3D multigrid without the z synthesis ----------------------------- */
+/* The comparison solver of Sec. 3.3.1 (the paper's "3D MG", timed against
+ * the FFT-accelerated solve in Sec. 4.2): geometric multigrid V-cycles on the
+ * whole 3D system (L_h - alpha) p = f of Eq. (8), on the same multi-block,
+ * stretched x-y grid and uniform z.  Level l = x-y level l of the FFT path's
+ * hierarchy times nz_l z cells (z halved with x-y while its count is even and
+ * >= 4); rediscretised coarse operators; weighted Jacobi smoothing (omega =
+ * 6/7, the smoother the paper runs in PFMG); volume-weighted restriction of
+ * the residual; trilinear prolongation (physical weights in x-y); exact
+ * coarsest solve by separation (dense z and x-y eigen-decompositions).
+ * FP64 only.  Fields use the packed layout of mbp_plan_layout, on the
+ * caller's buffers directly.
+ *   mbp3_plan_create: same descriptors as mbp_plan_create.  opt (NULL =
+ *     defaults nu1 = nu2 = 2, max_cycles 100): precision must be MBP_FP64,
+ *     smoother MBP_SMOOTHER_DEFAULT or _JACOBI, nu1, nu2 >= 1, helmholtz =
+ *     alpha >= 0.  Blocking; owns its device memory (about 1.5 x 8 B per
+ *     cell beyond the caller's fields).  Errors as mbp_plan_create.
+ *   mbp3_plan_levels: levels, nz and cells per level (caller arrays of
+ *     nlevels entries, each may be NULL), device bytes (may be NULL).
+ *   mbp3_jacobi_sweep: one weighted-Jacobi sweep of the finest level,
+ *     pout = pin + omega D^-1 (f - (L_h - alpha) pin), packed fields, out of
+ *     place (pin != pout); stream-ordered and asynchronous.  Exposed for
+ *     checking and timing the smoother alone.
+ *   mbp3_solve: stopping rule ||f - L_h p||_2 <= rtol ||f||_2 on the whole
+ *     3D field (checked on the returned iterate).  Flags MBP_PROJECT_RHS
+ *     (singular problems: remove the volume-weighted mean of f, without
+ *     writing rhs_dev) and MBP_WARM_START.  Ordered on `stream`; returns when
+ *     the solve is done (it reads each cycle's residual to decide whether to
+ *     queue the next).  info: status, cycles, rel_residual (of the returned
+ *     p), removed_mean, t_ms[1] = t_ms[3] = solve time; cycles_per_mode is
+ *     not used.  Same error codes as mbp_solve.
+ *   mbp3_plan_destroy: frees the plan (no work may be in flight). */
+typedef struct mbp3_plan mbp3_plan;
+int mbp3_plan_create(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* z,
+                     const mbp_options* opt, mbp3_plan** out);
+int mbp3_plan_levels(const mbp3_plan* plan, int* nlevels, int* nz_per_level, int64_t* cells_per_level,
+                     size_t* workspace_bytes);
+int mbp3_jacobi_sweep(mbp3_plan* plan, const double* pin_dev, double* pout_dev, const double* f_dev,
+                      void* stream);
+int mbp3_solve(mbp3_plan* plan, const double* rhs_dev, double* p_dev, double rtol, int flags,
+               void* stream, mbp_solve_info* info);
+void mbp3_plan_destroy(mbp3_plan* plan);
 
 /* ---- serving loop ------------------------------------------------------- */
 /* A server admits solve requests of any size and conditions, keeps plans

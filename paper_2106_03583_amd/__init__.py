@@ -98,6 +98,12 @@ def _load():
         "mbp_server_poll": (I, [P, C.c_uint64, C.POINTER(SolveInfo), C.POINTER(D)]),
         "mbp_server_wait": (I, [P, C.c_uint64, C.POINTER(SolveInfo), C.POINTER(D)]),
         "mbp_server_destroy": (None, [P]),
+        "mbp3_plan_create": (I, [C.POINTER(BlockDesc), I, C.POINTER(SynthDesc), C.POINTER(Options),
+                                 C.POINTER(P)]),
+        "mbp3_plan_levels": (I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
+        "mbp3_jacobi_sweep": (I, [P, VP, VP, VP, VP]),
+        "mbp3_solve": (I, [P, VP, VP, D, I, VP, C.POINTER(SolveInfo)]),
+        "mbp3_plan_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -115,6 +121,7 @@ EXPORTED = [
     "mbp_server_create", "mbp_server_submit", "mbp_server_poll", "mbp_server_wait",
     "mbp_server_destroy", "mbp_profile_enable", "mbp_profile_read", "mbp_batch_schedule",
     "mbp_plan_autotune", "mbp_plan_set_helmholtz",
+    "mbp3_plan_create", "mbp3_plan_levels", "mbp3_solve", "mbp3_plan_destroy", "mbp3_jacobi_sweep",
 ]
 
 
@@ -163,11 +170,11 @@ class _Desc:
         self.z = SynthDesc(int(problem.nz), float(problem.lz), int(problem.zbc[0]), int(problem.zbc[1]))
 
 
-SMOOTHER_RBGS = 0
+SMOOTHER_DEFAULT, SMOOTHER_RBGS, SMOOTHER_JACOBI = 0, 1, 2
 
 
 def _options(precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0, etol=0.0, inner=0, march=0,
-             smoother=SMOOTHER_RBGS, helmholtz=0.0) -> Options:
+             smoother=SMOOTHER_DEFAULT, helmholtz=0.0) -> Options:
     prec = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}[precision]
     return Options(prec, nu1, nu2, max_cycles, flags, etol, inner, march, smoother, float(helmholtz))
 
@@ -228,7 +235,7 @@ class Info:
 
 class Plan:
     def __init__(self, problem, precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0, etol=0.0, inner=0,
-                 march=0, smoother=SMOOTHER_RBGS, helmholtz=0.0):
+                 march=0, smoother=SMOOTHER_DEFAULT, helmholtz=0.0):
         self.problem = problem
         self._desc = _Desc(problem)
         self._opt = _options(precision, nu1, nu2, max_cycles, flags, etol, inner, march, smoother, helmholtz)
@@ -304,6 +311,56 @@ class Plan:
     def close(self):
         if self._h:
             lib.mbp_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan3D:
+    """The 3D multigrid solver without z synthesis (the comparison solver):
+    weighted-Jacobi V-cycles on the whole 3D system, FP64."""
+
+    def __init__(self, problem, nu1=2, nu2=2, max_cycles=100, flags=0, helmholtz=0.0):
+        self.problem = problem
+        self._desc = _Desc(problem)
+        self._opt = _options("fp64", nu1, nu2, max_cycles, flags, 0.0, 0, 0, SMOOTHER_JACOBI, helmholtz)
+        self._h = C.c_void_p()
+        _check(lib.mbp3_plan_create(self._desc.blocks, self._desc.nblocks, C.byref(self._desc.z),
+                                    C.byref(self._opt), C.byref(self._h)), "mbp3_plan_create")
+        self.nz = int(problem.nz)
+        self.ncells = int(problem.ncells)
+        n = C.c_int()
+        _check(lib.mbp3_plan_levels(self._h, C.byref(n), None, None, None), "mbp3_plan_levels")
+        nzl = (C.c_int * n.value)()
+        cl = (C.c_int64 * n.value)()
+        ws = C.c_size_t()
+        _check(lib.mbp3_plan_levels(self._h, None, nzl, cl, C.byref(ws)), "mbp3_plan_levels")
+        self.nlevels = n.value
+        self.nz_per_level = list(nzl)
+        self.cells_per_level = list(cl)
+        self.workspace_bytes = ws.value
+
+    def jacobi_sweep(self, pin, pout, f, stream=None):
+        """One weighted-Jacobi sweep of the finest level (out of place)."""
+        _check(lib.mbp3_jacobi_sweep(self._h, _ptr(pin, self.ncells), _ptr(pout, self.ncells),
+                                     _ptr(f, self.ncells), _stream(stream)), "mbp3_jacobi_sweep")
+
+    def solve(self, rhs, p, rtol=1e-10, flags=0, stream=None, raise_on_error=True) -> Info:
+        si = SolveInfo()
+        st = lib.mbp3_solve(self._h, _ptr(rhs, self.ncells), _ptr(p, self.ncells), float(rtol), int(flags),
+                            _stream(stream), C.byref(si))
+        if raise_on_error and st != OK:
+            raise MBPError(st, "mbp3_solve")
+        si.status = st if si.status == 0 else si.status
+        return Info(si, None)
+
+    def close(self):
+        if self._h:
+            lib.mbp3_plan_destroy(self._h)
             self._h = C.c_void_p()
 
     def __del__(self):

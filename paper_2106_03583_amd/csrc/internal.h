@@ -147,6 +147,8 @@ struct mbp_plan {
     int device = -1;
     mbp::BusyFlag busy;
     void* dmem = nullptr;         // one allocation holding everything below
+    bool owns_mem = true;         // false: dmem lies in a caller's arena (server)
+    bool owns_pinned = true;      // false: host_pinned belongs to the caller (server slot)
     size_t dbytes = 0;
     mbp::DBlock* d_blk = nullptr;
     int* d_int = nullptr;
@@ -194,6 +196,9 @@ int build_plan_host(const mbp_block_desc* blocks, int nblocks, const mbp_synth_d
                     const mbp_options* opt, mbp_plan* P, std::string* err);
 void options_default(mbp_options* o);
 void plan_set_shifts(mbp_plan* P);  // shift, sabs, singular from lambda and opt.helmholtz
+// Symmetric eigen-decomposition (cyclic Jacobi); A (n x n, row-major) is
+// overwritten, V gets the eigenvectors as columns, w the eigenvalues.
+void jacobi_eig(std::vector<double>& A, int n, std::vector<double>& V, std::vector<double>& w);
 int grid_tanh(int n, double lmin, double lmax, int type, double factor, double* out);
 
 // fft.hip (host helpers)
@@ -261,7 +266,10 @@ void launch_singular_fix(const mbp_plan* P, double* plane, double* out_mean, hip
 
 // solve.cpp
 size_t plan_device_bytes(const mbp_plan* P);
-int plan_device_init(mbp_plan* P);
+// Device part of a plan.  ext_mem (optional): place the plan in that region
+// of ext_bytes instead of allocating; ext_pinned (optional): a 4 KB pinned
+// host buffer to use for readbacks.
+int plan_device_init(mbp_plan* P, void* ext_mem = nullptr, size_t ext_bytes = 0, void* ext_pinned = nullptr);
 void plan_device_free(mbp_plan* P);
 int solve_one(mbp_plan* P, const double* rhs, double* p, double rtol, int flags, hipStream_t s,
               mbp_solve_info* info);

@@ -1,0 +1,471 @@
+// Geometric multigrid on the whole 3D system, without the z synthesis: the
+// comparison solver of Sec. 3.3.1 (the paper's "3D MG" against which the
+// FFT-accelerated solve is timed, Sec. 4.2).  It solves
+//     (L_h - alpha) p = f
+// on the same multi-block, stretched x-y grid extruded along z, with the same
+// cell-centred finite-volume operator (Eq. (8) on uniform grids).
+//
+// Hierarchy: each level is one x-y level of the FFT path's plan (full x-y
+// coarsening, odd counts merging their last three cells) times nz_l cells
+// along z.  Each coarsening step coarsens the direction(s) with the smaller
+// spacing, as the paper's PFMG picks its semicoarsening direction: z alone
+// when dz is at most half the mean x-y cell width, x-y alone when that width
+// is at most half of dz, both otherwise (z only while its count is even and
+// >= 4).  Coarse operators are rediscretised.  Smoother: weighted Jacobi
+// (the paper's PFMG runs weighted Jacobi), out of place.  Transfers:
+// volume-weighted restriction of the residual (fused with its evaluation),
+// trilinear prolongation with physical-coordinate weights in x-y and the
+// 3/4-1/4 weights of uniform cell-centred z.  The coarsest grid is solved
+// exactly by separation: the dense z eigenvectors of the coarsest z operator
+// and the x-y eigen-decomposition of the coarsest plane.
+//
+// Fields use the caller's packed layout on every level: block b occupies
+// [nz_l * off_b, nz_l * off_{b+1}) in C order (nz_l, ny_b, nx_b), so the
+// finest level reads the caller's rhs and writes the caller's p directly.
+#include "internal.h"
+#include "mg3d.h"
+
+namespace mbp {
+
+namespace {
+
+__device__ __forceinline__ int xcd_remap3(int g, int n) {
+    int x = g & 7, l = g >> 3;
+    int per = n >> 3, rem = n & 7;
+    return x * per + min(x, rem) + l;
+}
+
+__device__ __forceinline__ long long cell3(const DBlock& b, int nz, int k, int j, int i) {
+    return (long long)nz * b.off + ((long long)k * b.ny + j) * b.nx + i;
+}
+
+// Sum over one workgroup; the result is valid in thread 0.
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int t = threadIdx.x + threadIdx.y * blockDim.x;
+    const int w = t >> 6, nw = (blockDim.x * blockDim.y + 63) >> 6;
+    __syncthreads();
+    if ((t & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (t == 0)
+        for (int k = 0; k < nw; ++k) s += red[k];
+    return s;
+}
+
+// (L_h - alpha) p at cell (b, k, j, i) and its diagonal coefficient.  x-y
+// neighbours beyond a joined face come from the partner block; beyond a wall
+// the coefficient already holds the boundary condition (Neumann: none,
+// Dirichlet: folded into the diagonal).  z ends: periodic wrap, or a mirror
+// ghost (Neumann +p, Dirichlet -p) one cell away.
+struct Op3 {
+    const DBlock* B;
+    const double* dp;
+    int nz;
+    double idz2;
+    int zlo, zhi;  // MBP_PERIODIC / MBP_NEUMANN / MBP_DIRICHLET
+    double alpha;
+};
+
+__device__ __forceinline__ double zdiag(const Op3& o, int k) {
+    double d = -2.0 * o.idz2;
+    if (k == 0 && o.zlo != MBP_PERIODIC) d += o.zlo == MBP_NEUMANN ? o.idz2 : -o.idz2;
+    if (k == o.nz - 1 && o.zhi != MBP_PERIODIC) d += o.zhi == MBP_NEUMANN ? o.idz2 : -o.idz2;
+    return d;
+}
+
+// Off-diagonal part sum_n a_n p_n at (b, k, j, i).
+__device__ __forceinline__ double offdiag(const Op3& o, const double* __restrict__ p, const DBlock& b, int bi,
+                                          int k, int j, int i, long long c) {
+    const double* dp = o.dp;
+    double xm = 0.0, xp = 0.0, ym = 0.0, yp = 0.0;
+    if (i > 0) xm = p[c - 1];
+    else if (b.nbr[XM] >= 0) { const DBlock& n = o.B[b.nbr[XM]]; xm = p[cell3(n, o.nz, k, j, n.nx - 1)]; }
+    if (i < b.nx - 1) xp = p[c + 1];
+    else if (b.nbr[XP] >= 0) { const DBlock& n = o.B[b.nbr[XP]]; xp = p[cell3(n, o.nz, k, j, 0)]; }
+    if (j > 0) ym = p[c - b.nx];
+    else if (b.nbr[YM] >= 0) { const DBlock& n = o.B[b.nbr[YM]]; ym = p[cell3(n, o.nz, k, n.ny - 1, i)]; }
+    if (j < b.ny - 1) yp = p[c + b.nx];
+    else if (b.nbr[YP] >= 0) { const DBlock& n = o.B[b.nbr[YP]]; yp = p[cell3(n, o.nz, k, 0, i)]; }
+    const long long kz = (long long)b.nx * b.ny;
+    double zs = 0.0;
+    if (k > 0) zs += p[c - kz];
+    else if (o.zlo == MBP_PERIODIC) zs += p[c + (o.nz - 1) * kz];
+    if (k < o.nz - 1) zs += p[c + kz];
+    else if (o.zhi == MBP_PERIODIC) zs += p[c - (o.nz - 1) * kz];
+    (void)bi;
+    return dp[b.cx + i] * xm + dp[b.cx + b.nx + i] * xp + dp[b.cy + j] * ym + dp[b.cy + b.ny + j] * yp +
+           o.idz2 * zs;
+}
+
+__device__ __forceinline__ double diag(const Op3& o, const DBlock& b, int k, int j, int i) {
+    return o.dp[b.cx + 2 * b.nx + i] + o.dp[b.cy + 2 * b.ny + j] + zdiag(o, k) - o.alpha;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Weighted Jacobi sweep: pout = pin + omega D^-1 (f - fshift - A pin).
+// ZERO: pin is zero (not read).  NORM: per-workgroup partial sums of the
+// squared residual of pin into part[0, nw) and of pin^2 into part[nw, 2 nw)
+// (nw = workgroups of the launch).  WRITE: store pout.
+// ---------------------------------------------------------------------------
+template <bool ZERO, bool NORM, bool WRITE>
+__global__ void __launch_bounds__(256)
+k3_jacobi(Op3 o, const int4* __restrict__ tiles, int ntiles, const double* __restrict__ pin,
+          double* __restrict__ pout, const double* __restrict__ f, double fshift, double omega,
+          double* __restrict__ part) {
+    const int k = blockIdx.y;
+    const int4 t = tiles[xcd_remap3(blockIdx.x, ntiles)];
+    const DBlock b = o.B[t.x];
+    const int i = t.y + threadIdx.x;
+    double acc = 0.0, accp = 0.0;
+    if (i < b.nx) {
+        for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
+            const int j = t.z + r;
+            if (j >= b.ny) break;
+            const long long c = cell3(b, o.nz, k, j, i);
+            const double d = diag(o, b, k, j, i);
+            double res = f[c] - fshift;
+            double v = 0.0;
+            if (!ZERO) {
+                v = pin[c];
+                res -= offdiag(o, pin, b, t.x, k, j, i, c) + d * v;
+            }
+            if (NORM) {
+                acc += res * res;
+                accp += v * v;
+            }
+            if (WRITE) pout[c] = v + omega * res / d;
+        }
+    }
+    if (NORM) {
+        __shared__ double red[8];
+        const long long w = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+        const long long nw = (long long)gridDim.y * gridDim.x;
+        const double s = wg_sum(acc, red);
+        if (threadIdx.x == 0 && threadIdx.y == 0) part[w] = s;
+        const double sp = wg_sum(accp, red);
+        if (threadIdx.x == 0 && threadIdx.y == 0) part[nw + w] = sp;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Residual of level l restricted to level l+1 (volume-weighted average of
+// the children), written to fc; one thread per coarse cell.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k3_restrict(Op3 of, const DBlock* __restrict__ Bc, const int4* __restrict__ tiles_c, int ntiles_c,
+            int nzc, const int* __restrict__ ip, const double* __restrict__ p, const double* __restrict__ f,
+            double fshift, double* __restrict__ fc, int xycoarse, int zcoarse) {
+    const int K = blockIdx.y;
+    const int4 t = tiles_c[xcd_remap3(blockIdx.x, ntiles_c)];
+    const DBlock bc = Bc[t.x];
+    const DBlock bf = of.B[t.x];
+    const double* dp = of.dp;
+    const int I = t.y + threadIdx.x;
+    if (I >= bc.nx) return;
+    // children: the x-y transfer tables when x-y coarsens, else the same cell
+    const int i0 = xycoarse ? ip[bf.rsx + I] : I, i1 = xycoarse ? ip[bf.rsx + I + 1] : I + 1;
+    const int k0 = zcoarse ? 2 * K : K, k1 = zcoarse ? 2 * K + 2 : K + 1;
+    const double wz = zcoarse ? 0.5 : 1.0;
+    for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
+        const int J = t.z + r;
+        if (J >= bc.ny) break;
+        const int j0 = xycoarse ? ip[bf.rsy + J] : J, j1 = xycoarse ? ip[bf.rsy + J + 1] : J + 1;
+        double acc = 0.0;
+        for (int k = k0; k < k1; ++k)
+            for (int j = j0; j < j1; ++j) {
+                const double wy = xycoarse ? dp[bf.rwy + j] : 1.0;
+                double row = 0.0;
+                for (int i = i0; i < i1; ++i) {
+                    const long long c = cell3(bf, of.nz, k, j, i);
+                    const double res =
+                        f[c] - fshift - offdiag(of, p, bf, t.x, k, j, i, c) - diag(of, bf, k, j, i) * p[c];
+                    row += (xycoarse ? dp[bf.rwx + i] : 1.0) * res;
+                }
+                acc += wy * row;
+            }
+        fc[cell3(bc, nzc, K, J, I)] = wz * acc;
+    }
+}
+
+namespace {
+
+// Coarse value at (I, J) of plane K (K inside [0, nzc)) of block b, I in
+// [-1, nx], J in [-1, ny]: beyond a joined face the partner's cell, beyond a
+// wall the mirror image (Neumann +, Dirichlet -); corners through y first.
+__device__ __forceinline__ double cvalue(const double* __restrict__ pc, const DBlock* __restrict__ B, int nzc,
+                                         int b, int I, int J, int K) {
+    double s = 1.0;
+    const DBlock* bb = &B[b];
+    if (J < 0) {
+        if (bb->nbr[YM] >= 0) { bb = &B[bb->nbr[YM]]; J = bb->ny - 1; }
+        else { if (bb->bc[YM] == MBP_DIRICHLET) s = -s; J = 0; }
+    } else if (J >= bb->ny) {
+        if (bb->nbr[YP] >= 0) { bb = &B[bb->nbr[YP]]; J = 0; }
+        else { if (bb->bc[YP] == MBP_DIRICHLET) s = -s; J = bb->ny - 1; }
+    }
+    if (I < 0) {
+        if (bb->nbr[XM] >= 0) { bb = &B[bb->nbr[XM]]; I = bb->nx - 1; }
+        else { if (bb->bc[XM] == MBP_DIRICHLET) s = -s; I = 0; }
+    } else if (I >= bb->nx) {
+        if (bb->nbr[XP] >= 0) { bb = &B[bb->nbr[XP]]; I = 0; }
+        else { if (bb->bc[XP] == MBP_DIRICHLET) s = -s; I = bb->nx - 1; }
+    }
+    return s * pc[cell3(*bb, nzc, K, J, I)];
+}
+
+// Bilinear (physical weights) value of coarse plane K at fine cell (i, j).
+__device__ __forceinline__ double bilinear(const double* __restrict__ pc, const DBlock* __restrict__ Bc, int nzc,
+                                           const DBlock& bf, int b, const double* __restrict__ dp,
+                                           const int* __restrict__ ip, int i, int j, int K) {
+    const int cx = ip[bf.pcx + i], cy = ip[bf.pcy + j];
+    const double wx = dp[bf.pwx + i], wy = dp[bf.pwy + j];
+    const double e00 = cvalue(pc, Bc, nzc, b, cx, cy, K), e10 = cvalue(pc, Bc, nzc, b, cx + 1, cy, K);
+    const double e01 = cvalue(pc, Bc, nzc, b, cx, cy + 1, K), e11 = cvalue(pc, Bc, nzc, b, cx + 1, cy + 1, K);
+    return wy * (wx * e00 + (1.0 - wx) * e10) + (1.0 - wy) * (wx * e01 + (1.0 - wx) * e11);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// p_l += P e_{l+1}: trilinear interpolation of the coarse correction.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k3_prolong(const DBlock* __restrict__ Bf, const DBlock* __restrict__ Bc, const int4* __restrict__ tiles_f,
+           int ntiles_f, int nzf, int nzc, const double* __restrict__ dp, const int* __restrict__ ip,
+           const double* __restrict__ pc, double* __restrict__ pf, int xycoarse, int zcoarse, int zlo, int zhi) {
+    const int k = blockIdx.y;
+    const int4 t = tiles_f[xcd_remap3(blockIdx.x, ntiles_f)];
+    const DBlock bf = Bf[t.x];
+    const int i = t.y + threadIdx.x;
+    if (i >= bf.nx) return;
+    // z: the two coarse planes around the fine centre, weight of the lower one
+    int K0 = k, K1 = k;
+    double w0 = 1.0, s0 = 1.0, s1 = 1.0;
+    if (zcoarse) {
+        const int K = k >> 1;
+        if (k & 1) { K0 = K; K1 = K + 1; w0 = 0.75; }
+        else { K0 = K - 1; K1 = K; w0 = 0.25; }
+        if (K0 < 0) {  // below the first coarse cell: periodic wrap or mirror ghost
+            if (zlo == MBP_PERIODIC) K0 = nzc - 1;
+            else { K0 = 0; s0 = zlo == MBP_DIRICHLET ? -1.0 : 1.0; }
+        }
+        if (K1 >= nzc) {
+            if (zhi == MBP_PERIODIC) K1 = 0;
+            else { K1 = nzc - 1; s1 = zhi == MBP_DIRICHLET ? -1.0 : 1.0; }
+        }
+    }
+    for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
+        const int j = t.z + r;
+        if (j >= bf.ny) break;
+        double e;
+        if (xycoarse) {
+            e = w0 * s0 * bilinear(pc, Bc, nzc, bf, t.x, dp, ip, i, j, K0);
+            if (zcoarse) e += (1.0 - w0) * s1 * bilinear(pc, Bc, nzc, bf, t.x, dp, ip, i, j, K1);
+        } else {  // same x-y grid: the coarse cell under the fine one
+            e = w0 * s0 * pc[cell3(bf, nzc, K0, j, i)];
+            if (zcoarse) e += (1.0 - w0) * s1 * pc[cell3(bf, nzc, K1, j, i)];
+        }
+        pf[cell3(bf, nzf, k, j, i)] += e;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exact coarsest solve by separation.  Stage 1, one workgroup per z mode m:
+// fz = sum_k V[k][m] f_k (z eigenvectors), then the x-y solve
+// x_m = WL diag(1 / (mu + muz_m - alpha)) WR fz, with the null mode dropped.
+// Stage 2: p_k = sum_m V[k][m] x_m.  Plane cells are indexed like the x-y
+// eigen tables; cmap gives each one's packed offset at z = 0 and its z stride.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k3_coarse_modes(const double* __restrict__ f, const int2* __restrict__ cmap, int nc, int nzc,
+                const double* __restrict__ vz, const double* __restrict__ muz, const double* __restrict__ wl,
+                const double* __restrict__ wr, const double* __restrict__ mu, double alpha,
+                double* __restrict__ xhat) {
+    extern __shared__ double sm[];
+    double* fz = sm;       // nc
+    double* tmp = sm + nc; // nc
+    const int m = blockIdx.x;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        const int2 cm = cmap[c];
+        double a = 0.0;
+        for (int k = 0; k < nzc; ++k) a += vz[k * nzc + m] * f[cm.x + (long long)k * cm.y];
+        fz[c] = a;
+    }
+    __syncthreads();
+    double mumax = 0.0;
+    for (int q = 0; q < nc; ++q) mumax = fmax(mumax, fabs(mu[q]));
+    const double sh = muz[m] - alpha;
+    for (int q = threadIdx.x; q < nc; q += blockDim.x) {
+        double a = 0.0;
+        const double* row = wr + (long long)q * nc;
+        for (int c = 0; c < nc; ++c) a += row[c] * fz[c];
+        const double d = mu[q] + sh;
+        tmp[q] = fabs(d) > 1e-11 * (mumax + fabs(sh)) ? a / d : 0.0;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        double a = 0.0;
+        const double* row = wl + (long long)c * nc;
+        for (int q = 0; q < nc; ++q) a += row[q] * tmp[q];
+        xhat[(long long)m * nc + c] = a;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k3_coarse_back(const double* __restrict__ xhat, const int2* __restrict__ cmap, int nc, int nzc,
+               const double* __restrict__ vz, double* __restrict__ p) {
+    const long long n = (long long)nc * nzc;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const int k = int(e / nc), c = int(e % nc);
+        double a = 0.0;
+        for (int m = 0; m < nzc; ++m) a += vz[k * nzc + m] * xhat[(long long)m * nc + c];
+        const int2 cm = cmap[c];
+        p[cm.x + (long long)k * cm.y] = a;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions on the packed finest field: partial sums of area * x (the
+// volume-weighted sum, dz being uniform) per workgroup, and their total.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k3_area_sum(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntiles, int nz,
+            const double* __restrict__ area, const double* __restrict__ x, double* __restrict__ part) {
+    const int k = blockIdx.y;
+    const int4 t = tiles[xcd_remap3(blockIdx.x, ntiles)];
+    const DBlock b = B[t.x];
+    const int i = t.y + threadIdx.x;
+    double acc = 0.0;
+    if (i < b.nx)
+        for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
+            const int j = t.z + r;
+            if (j >= b.ny) break;
+            acc += area[b.off + j * b.nx + i] * x[cell3(b, nz, k, j, i)];
+        }
+    __shared__ double red[8];
+    const double s = wg_sum(acc, red);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[(long long)blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(1024) k3_total(const double* __restrict__ part, long long n, double scale,
+                                                  double* __restrict__ out) {
+    double acc = 0.0;
+    for (long long e = threadIdx.x; e < n; e += blockDim.x) acc += part[e];
+    __shared__ double red[16];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < int(blockDim.x >> 6); ++w) s += red[w];
+        *out = s * scale;
+    }
+}
+
+// x -= *mean (device scalar) over n elements.
+__global__ void __launch_bounds__(256) k3_sub(double* __restrict__ x, long long n, const double* __restrict__ mean) {
+    const double m = *mean;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        x[e] -= m;
+}
+
+__global__ void __launch_bounds__(256) k3_copy(const double* __restrict__ a, double* __restrict__ b, long long n) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        b[e] = a[e];
+}
+
+// ============================== launchers ==============================
+
+namespace {
+Op3 op_of(const Mg3Plan& M, int l) {
+    const Mg3Level& L = M.lev[l];
+    return Op3{M.d_blk + L.blk_off, M.d_dbl, L.nz, L.idz2, M.zlo, M.zhi, M.alpha};
+}
+dim3 grid_of(const Mg3Level& L) { return dim3(unsigned(L.ntiles), unsigned(L.nz)); }
+const dim3 kBlk(kTileX, kRowsPerPass);
+}  // namespace
+
+void m3_jacobi(const Mg3Plan& M, int l, const double* pin, double* pout, const double* f, double fshift,
+               bool zero, double* part, hipStream_t s) {
+    const Mg3Level& L = M.lev[l];
+    const Op3 o = op_of(M, l);
+    const int4* tl = M.d_tiles + L.tile_off;
+    if (zero) {
+        if (part) hipLaunchKernelGGL((k3_jacobi<true, true, true>), grid_of(L), kBlk, 0, s, o, tl, L.ntiles, pin, pout, f,
+                                     fshift, M.omega, part);
+        else hipLaunchKernelGGL((k3_jacobi<true, false, true>), grid_of(L), kBlk, 0, s, o, tl, L.ntiles, pin, pout, f,
+                                fshift, M.omega, part);
+    } else {
+        if (part) hipLaunchKernelGGL((k3_jacobi<false, true, true>), grid_of(L), kBlk, 0, s, o, tl, L.ntiles, pin, pout,
+                                     f, fshift, M.omega, part);
+        else hipLaunchKernelGGL((k3_jacobi<false, false, true>), grid_of(L), kBlk, 0, s, o, tl, L.ntiles, pin, pout, f,
+                                fshift, M.omega, part);
+    }
+}
+
+// Squared norms of the finest residual of p and of p itself into out[0], out[1].
+void m3_residual_norm(const Mg3Plan& M, const double* p, const double* f, double fshift, bool zero, double* part,
+                      double* out, hipStream_t s) {
+    const Mg3Level& L = M.lev[0];
+    const Op3 o = op_of(M, 0);
+    const int4* tl = M.d_tiles + L.tile_off;
+    if (zero)
+        hipLaunchKernelGGL((k3_jacobi<true, true, false>), grid_of(L), kBlk, 0, s, o, tl, L.ntiles, p, nullptr, f,
+                           fshift, M.omega, part);
+    else
+        hipLaunchKernelGGL((k3_jacobi<false, true, false>), grid_of(L), kBlk, 0, s, o, tl, L.ntiles, p, nullptr, f,
+                           fshift, M.omega, part);
+    const long long nw = (long long)L.ntiles * L.nz;
+    m3_total(part, nw, 1.0, out, s);
+    m3_total(part + nw, nw, 1.0, out + 1, s);
+}
+
+void m3_total(const double* part, long long n, double scale, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k3_total, dim3(1), dim3(1024), 0, s, part, n, scale, out);
+}
+
+void m3_restrict(const Mg3Plan& M, int l, const double* p, const double* f, double fshift, double* fc,
+                 hipStream_t s) {
+    const Mg3Level& C = M.lev[l + 1];
+    const Op3 o = op_of(M, l);
+    hipLaunchKernelGGL(k3_restrict, grid_of(C), kBlk, 0, s, o, M.d_blk + C.blk_off, M.d_tiles + C.tile_off, C.ntiles,
+                       C.nz, M.d_int, p, f, fshift, fc, M.lev[l].xyc, M.lev[l].zc);
+}
+
+void m3_prolong(const Mg3Plan& M, int l, const double* pc, double* pf, hipStream_t s) {
+    const Mg3Level& F = M.lev[l];
+    const Mg3Level& C = M.lev[l + 1];
+    hipLaunchKernelGGL(k3_prolong, grid_of(F), kBlk, 0, s, M.d_blk + F.blk_off, M.d_blk + C.blk_off,
+                       M.d_tiles + F.tile_off, F.ntiles, F.nz, C.nz, M.d_dbl, M.d_int, pc, pf, F.xyc, F.zc,
+                       M.zlo, M.zhi);
+}
+
+void m3_coarse(const Mg3Plan& M, const double* f, double* p, hipStream_t s) {
+    const Mg3Level& L = M.lev[M.nlev - 1];
+    const size_t lds = 2 * size_t(M.nc) * sizeof(double);
+    hipLaunchKernelGGL(k3_coarse_modes, dim3(unsigned(L.nz)), dim3(256), lds, s, f, M.d_cmap, M.nc, L.nz, M.d_vz,
+                       M.d_muz, M.d_cwl, M.d_cwr, M.d_cmu, M.alpha, M.d_xhat);
+    const long long n = (long long)M.nc * L.nz;
+    const unsigned g = unsigned(std::min<long long>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(k3_coarse_back, dim3(g), dim3(256), 0, s, M.d_xhat, M.d_cmap, M.nc, L.nz, M.d_vz, p);
+}
+
+void m3_area_sum(const Mg3Plan& M, const double* x, double* part, double* out, double scale, hipStream_t s) {
+    const Mg3Level& L = M.lev[0];
+    hipLaunchKernelGGL(k3_area_sum, grid_of(L), kBlk, 0, s, M.d_blk + L.blk_off, M.d_tiles + L.tile_off, L.ntiles,
+                       L.nz, M.d_area0, x, part);
+    m3_total(part, (long long)L.ntiles * L.nz, scale, out, s);
+}
+
+void m3_sub(double* x, long long n, const double* mean, hipStream_t s) {
+    hipLaunchKernelGGL(k3_sub, dim3(2048), dim3(256), 0, s, x, n, mean);
+}
+
+void m3_copy(const double* a, double* b, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(k3_copy, dim3(4096), dim3(256), 0, s, a, b, n);
+}
+
+}  // namespace mbp

@@ -21,7 +21,7 @@ void options_default(mbp_options* o) {
     o->etol = 0.0;
     o->inner = 2;
     o->march = 0;
-    o->smoother = MBP_SMOOTHER_RBGS;
+    o->smoother = MBP_SMOOTHER_DEFAULT;
     o->helmholtz = 0.0;
 }
 
@@ -185,6 +185,8 @@ std::vector<double> coarsen_faces(const std::vector<double>& f) {
     return c;
 }
 
+}  // namespace
+
 // Symmetric eigen-decomposition by cyclic Jacobi rotations (A is overwritten;
 // V receives the eigenvectors as columns, row-major n x n).
 void jacobi_eig(std::vector<double>& A, int n, std::vector<double>& V, std::vector<double>& w) {
@@ -227,6 +229,8 @@ void jacobi_eig(std::vector<double>& A, int n, std::vector<double>& V, std::vect
     w.resize(n);
     for (int i = 0; i < n; ++i) w[i] = a(i, i);
 }
+
+namespace {
 
 std::vector<int> fft_radices(int m) {
     std::vector<int> r;
@@ -294,7 +298,7 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
             if (err) *err = "bad pre-smoothing form";
             return MBP_ERR_INVALID;
         }
-        if (P->opt.smoother != MBP_SMOOTHER_RBGS) {
+        if (P->opt.smoother != MBP_SMOOTHER_DEFAULT && P->opt.smoother != MBP_SMOOTHER_RBGS) {
             if (err) *err = "unknown smoother";
             return MBP_ERR_INVALID;
         }

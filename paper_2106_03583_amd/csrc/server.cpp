@@ -7,6 +7,14 @@
 // an event, and is looked at again when that event has completed.  Requests
 // therefore overlap on the device, and one that arrives while others run
 // starts at once when a slot and memory are free.
+//
+// The budget is one device allocation made at creation (the arena): plans
+// are placed in it and their ranges returned on eviction, so admission never
+// calls hipMalloc or hipFree (hipFree waits for the whole device, which
+// would stall every running request).  The host part of a plan (validation,
+// hierarchy, tables) is built in the submitting thread, so the worker only
+// places the plan and uploads its tables in one copy; readbacks use pinned
+// buffers owned by the slots.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -33,8 +41,49 @@ struct CachedPlan {
     std::string key;
     mbp_plan* plan = nullptr;
     size_t bytes = 0;
+    size_t off = 0;  // range in the arena
     bool busy = false;
     uint64_t last_use = 0;
+};
+
+// First-fit allocator over the arena with coalescing free ranges.
+class Arena {
+  public:
+    void init(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    // offset of a range of `bytes` (256-byte aligned), or SIZE_MAX
+    size_t alloc(size_t bytes) {
+        bytes = (bytes + 255) & ~size_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= bytes) {
+                const size_t off = it->first, len = it->second;
+                free_.erase(it);
+                if (len > bytes) free_[off + bytes] = len - bytes;
+                return off;
+            }
+        return SIZE_MAX;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = (bytes + 255) & ~size_t(255);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    std::map<size_t, size_t> free_;
 };
 
 enum Stage { kQueued, kPrologue, kCycles, kEpilogue, kDone };
@@ -57,6 +106,7 @@ struct Request {
     Stage stage = kQueued;
     SolveCtx ctx;
     hipEvent_t ev = nullptr;
+    std::unique_ptr<mbp_plan> host;  // host plan built at submission (none when cached)
     // result
     int status = MBP_OK;
     mbp_solve_info info{};
@@ -105,6 +155,9 @@ struct mbp_server {
     mbp_options opt{};
     std::vector<hipStream_t> streams;
     std::vector<char> slot_busy;
+    void* arena_mem = nullptr;      // the budget, allocated once
+    Arena arena;
+    void* pinned = nullptr;         // 4 KB readback buffer per slot
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -112,7 +165,6 @@ struct mbp_server {
     std::vector<Request*> running;
     std::map<uint64_t, Request*> finished;
     std::map<uint64_t, Request*> all;  // every live ticket
-    std::map<std::string, size_t> footprint;  // descriptor -> plan bytes
     std::vector<std::unique_ptr<CachedPlan>> cache;
     size_t resident = 0;
     uint64_t use_clock = 0;
@@ -121,44 +173,49 @@ struct mbp_server {
     std::thread worker;
 
     // ---- worker side (no lock held during HIP work) ----
-    CachedPlan* acquire_plan(Request* r) {
+    void evict(CachedPlan* victim) {
+        plan_device_free(victim->plan);  // arena memory and slot buffers are not owned: nothing to free
+        delete victim->plan;
+        arena.release(victim->off, victim->bytes);
+        resident -= victim->bytes;
+        cache.erase(std::find_if(cache.begin(), cache.end(),
+                                 [&](const std::unique_ptr<CachedPlan>& c) { return c.get() == victim; }));
+    }
+
+    CachedPlan* acquire_plan(Request* r, int slot) {
+        void* pin = static_cast<unsigned char*>(pinned) + size_t(slot) * 4096;
         for (auto& c : cache)
             if (!c->busy && c->key == r->key) {
                 c->busy = true;
                 c->last_use = ++use_clock;
+                c->plan->host_pinned = pin;
                 return c.get();
             }
-        // make room: drop idle plans, least recently used first
-        while (resident + r->bytes > budget) {
+        // make room: drop idle plans, least recently used first, until a
+        // contiguous range of the arena fits the plan
+        size_t off;
+        while ((off = arena.alloc(r->bytes)) == SIZE_MAX) {
             CachedPlan* victim = nullptr;
             for (auto& c : cache)
                 if (!c->busy && (!victim || c->last_use < victim->last_use)) victim = c.get();
-            if (!victim) return nullptr;
-            plan_device_free(victim->plan);
-            delete victim->plan;
-            resident -= victim->bytes;
-            cache.erase(std::find_if(cache.begin(), cache.end(),
-                                     [&](const std::unique_ptr<CachedPlan>& c) { return c.get() == victim; }));
+            if (!victim) return nullptr;  // waits for memory held by running requests
+            evict(victim);
         }
-        mbp_plan* P = new (std::nothrow) mbp_plan();
-        if (!P) return nullptr;
-        std::string err;
-        int st = build_plan_host_limits(r->blocks.data(), int(r->blocks.size()), &r->z, &opt, int64_t(lds_limit),
-                                        P, &err);
-        if (st == MBP_OK) {
-            P->device = device;
-            st = plan_device_init(P);
-        }
+        mbp_plan* P = r->host.release();
+        P->device = device;
+        int st = plan_device_init(P, static_cast<unsigned char*>(arena_mem) + off, r->bytes, pin);
         if (st != MBP_OK) {
             plan_device_free(P);
             delete P;
+            arena.release(off, r->bytes);
             r->status = st;
             return nullptr;
         }
         auto c = std::make_unique<CachedPlan>();
         c->key = r->key;
         c->plan = P;
-        c->bytes = P->dbytes;
+        c->bytes = r->bytes;
+        c->off = off;
         c->busy = true;
         c->last_use = ++use_clock;
         resident += c->bytes;
@@ -247,7 +304,7 @@ struct mbp_server {
                 Request* r = waiting.front();
                 lk.unlock();
                 r->status = MBP_OK;
-                CachedPlan* cp = acquire_plan(r);
+                CachedPlan* cp = acquire_plan(r, slot);
                 lk.lock();
                 if (!cp) {
                     if (r->status != MBP_OK) {  // the plan could not be built
@@ -321,9 +378,22 @@ int mbp_server_create(size_t hbm_budget, int slots, const mbp_options* opt, mbp_
     S->lds_limit = lds;
     S->streams.resize(slots);
     S->slot_busy.assign(slots, 0);
+    if (hipMalloc(&S->arena_mem, hbm_budget) != hipSuccess) {
+        (void)hipGetLastError();
+        delete S;
+        return MBP_ERR_NOMEM;
+    }
+    S->arena.init(hbm_budget);
+    if (hipHostMalloc(&S->pinned, size_t(slots) * 4096, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(S->arena_mem);
+        delete S;
+        return MBP_ERR_NOMEM;
+    }
     for (int k = 0; k < slots; ++k)
         if (hipStreamCreateWithFlags(&S->streams[k], hipStreamNonBlocking) != hipSuccess) {
             for (int j = 0; j < k; ++j) (void)hipStreamDestroy(S->streams[j]);
+            (void)hipHostFree(S->pinned);
+            (void)hipFree(S->arena_mem);
             delete S;
             return MBP_ERR_HIP;
         }
@@ -339,22 +409,16 @@ int mbp_server_submit(mbp_server* S, const mbp_block_desc* blocks, int nblocks, 
         return MBP_ERR_INVALID;
     auto r = std::make_unique<Request>();
     r->key = describe(blocks, nblocks, z, S->opt);
-    size_t bytes = 0;
-    {
-        std::lock_guard<std::mutex> lk(S->mu);
-        auto it = S->footprint.find(r->key);
-        if (it != S->footprint.end()) bytes = it->second;
-    }
-    if (bytes == 0) {
-        // validate and size the plan on the host (no device memory yet)
-        mbp_plan tmp;
-        std::string err;
-        const int st = build_plan_host_limits(blocks, nblocks, z, &S->opt, int64_t(S->lds_limit), &tmp, &err);
-        if (st != MBP_OK) return st;
-        bytes = plan_device_bytes(&tmp);
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->footprint[r->key] = bytes;
-    }
+    // validate and build the host part of the plan in this thread (no device
+    // memory yet); the worker places it in the arena when it admits the
+    // request, or drops it when a cached plan with the same key is idle
+    auto P = std::unique_ptr<mbp_plan>(new (std::nothrow) mbp_plan());
+    if (!P) return MBP_ERR_NOMEM;
+    std::string err;
+    const int st = build_plan_host_limits(blocks, nblocks, z, &S->opt, int64_t(S->lds_limit), P.get(), &err);
+    if (st != MBP_OK) return st;
+    const size_t bytes = plan_device_bytes(P.get());
+    r->host = std::move(P);
     if (bytes > S->budget) return MBP_ERR_TOO_LARGE;
     r->bytes = bytes;
     r->blocks.assign(blocks, blocks + nblocks);
@@ -445,6 +509,8 @@ void mbp_server_destroy(mbp_server* S) {
         delete c->plan;
     }
     for (hipStream_t s : S->streams) (void)hipStreamDestroy(s);
+    if (S->pinned) (void)hipHostFree(S->pinned);
+    if (S->arena_mem) (void)hipFree(S->arena_mem);
     delete S;
 }
 

@@ -134,15 +134,21 @@ size_t plan_device_bytes(const mbp_plan* P) {
     return layout(&tmp, nt * 32, mt.size(), partial_count(&tmp)).total;
 }
 
-int plan_device_init(mbp_plan* P) {
+int plan_device_init(mbp_plan* P, void* ext_mem, size_t ext_bytes, void* ext_pinned) {
     std::vector<unsigned char> ftf, fti, mt;
     fft_build_tiles(P, ftf, fti, &P->fft_ntiles);
     plan_march_tables(P, mt);
     Layout L = layout(P, ftf.size(), mt.size(), partial_count(P));
-    void* mem = nullptr;
-    if (hipMalloc(&mem, L.total) != hipSuccess) {
-        (void)hipGetLastError();
-        return MBP_ERR_NOMEM;
+    void* mem = ext_mem;
+    if (ext_mem) {
+        if (ext_bytes < L.total) return MBP_ERR_NOMEM;
+        P->owns_mem = false;
+    } else {
+        if (hipMalloc(&mem, L.total) != hipSuccess) {
+            (void)hipGetLastError();
+            return MBP_ERR_NOMEM;
+        }
+        P->owns_mem = true;
     }
     P->dmem = mem;
     P->dbytes = L.total;
@@ -191,26 +197,37 @@ int plan_device_init(mbp_plan* P) {
     P->d_cyc = reinterpret_cast<int*>(b + L.cyc);
     P->d_flag = reinterpret_cast<int*>(b + L.flag);
     P->d_scal = reinterpret_cast<double*>(b + L.scal);
-    auto up = [&](void* dst, const void* src, size_t bytes) {
-        if (bytes == 0) return true;
-        return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    // every table sits below fhat in the allocation: one host image, one copy
+    std::vector<unsigned char> img(L.fhat, 0);
+    auto put = [&](size_t off, const void* src, size_t bytes) {
+        if (bytes) std::memcpy(img.data() + off, src, bytes);
     };
-    bool ok = up(P->d_blk, P->hblk.data(), P->hblk.size() * sizeof(DBlock)) &&
-              up(P->d_int, P->hint.data(), P->hint.size() * sizeof(int)) &&
-              up(P->d_dbl, P->hdbl.data(), P->hdbl.size() * sizeof(double)) &&
-              up(P->d_tiles, P->htiles.data(), P->htiles.size() * sizeof(int4)) &&
-              up(P->d_shift, P->shift.data(), P->shift.size() * sizeof(double)) &&
-              up(P->d_sabs, P->sabs.data(), P->sabs.size() * sizeof(double)) &&
-              up(P->d_cwl, P->coarse_wl.data(), P->coarse_wl.size() * sizeof(double)) &&
-              up(P->d_cwr, P->coarse_wr.data(), P->coarse_wr.size() * sizeof(double)) &&
-              up(P->d_cmu, P->coarse_mu.data(), P->coarse_mu.size() * sizeof(double)) &&
-              up(P->d_area0, P->areas0.data(), P->areas0.size() * sizeof(double)) &&
-              up(P->d_ftiles_fwd, ftf.data(), ftf.size()) && up(P->d_ftiles_inv, fti.data(), fti.size()) &&
-              up(P->d_mtiles, mt.data(), mt.size());
-    if (!ok) return MBP_ERR_HIP;
+    put(L.blk, P->hblk.data(), P->hblk.size() * sizeof(DBlock));
+    put(L.ints, P->hint.data(), P->hint.size() * sizeof(int));
+    put(L.dbls, P->hdbl.data(), P->hdbl.size() * sizeof(double));
+    put(L.tiles, P->htiles.data(), P->htiles.size() * sizeof(int4));
+    put(L.shift, P->shift.data(), P->shift.size() * sizeof(double));
+    put(L.cwl, P->coarse_wl.data(), P->coarse_wl.size() * sizeof(double));
+    put(L.cwr, P->coarse_wr.data(), P->coarse_wr.size() * sizeof(double));
+    put(L.cmu, P->coarse_mu.data(), P->coarse_mu.size() * sizeof(double));
+    put(L.area0, P->areas0.data(), P->areas0.size() * sizeof(double));
+    put(L.ftf, ftf.data(), ftf.size());
+    put(L.fti, fti.data(), fti.size());
+    put(L.mt, mt.data(), mt.size());
+    if (hipMemcpy(mem, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess) return MBP_ERR_HIP;
+    // (the error-test bounds sit after the fields)
+    if (hipMemcpy(P->d_sabs, P->sabs.data(), P->sabs.size() * sizeof(double), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return MBP_ERR_HIP;
+    if (ext_pinned) {
+        P->host_pinned = ext_pinned;
+        P->owns_pinned = false;
+        return MBP_OK;
+    }
     void* hp = nullptr;
     if (hipHostMalloc(&hp, 4096, hipHostMallocDefault) != hipSuccess) return MBP_ERR_NOMEM;
     P->host_pinned = hp;
+    P->owns_pinned = true;
     return MBP_OK;
 }
 
@@ -249,8 +266,8 @@ void plan_device_free(mbp_plan* P) {
             (void)hipEventDestroy(static_cast<hipEvent_t>(e[0]));
             (void)hipEventDestroy(static_cast<hipEvent_t>(e[1]));
         }
-    if (P->dmem) (void)hipFree(P->dmem);
-    if (P->host_pinned) (void)hipHostFree(P->host_pinned);
+    if (P->dmem && P->owns_mem) (void)hipFree(P->dmem);
+    if (P->host_pinned && P->owns_pinned) (void)hipHostFree(P->host_pinned);
     P->dmem = nullptr;
     P->host_pinned = nullptr;
 }

@@ -25,7 +25,7 @@ def mbp():
 def _declared():
     src = open(os.path.join(ROOT, "include", "mbp.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(mbp_[a-z_0-9]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(mbp3?_[a-z_0-9]+)\s*\(", src)))
 
 
 def test_exports_every_declared_symbol(mbp):
