@@ -270,6 +270,20 @@ int mbp_batch_schedule(mbp_plan* const* plans, int count, int* streams, int* cyc
  *   mbp_apply_operator: out = L_h p on the packed field (float64).
  *   mbp_modal_shift: writes the nz shifts lambda_q / dz^2 (host array). */
 int mbp_forward_transform(mbp_plan* plan, const double* f_dev, double* fhat_dev, void* stream);
+
+/* Final check of a solve (Eq. (8) on the whole field; the paper validates
+ * its solver by checking the result up to the tolerance, Sec. 4.1):
+ *   out_dev[0] = ||f - s - (L_h - alpha) p||_2,  out_dev[1] = ||f - s||_2
+ * over every cell, with f = rhs_dev, p = p_dev (packed float64 device
+ * fields), s = rhs_shift (pass info.removed_mean of a projected singular
+ * solve, else 0), alpha the plan's Helmholtz term.  out_dev: two device
+ * doubles, written by the stream's work.  Stream-ordered and asynchronous;
+ * per-workgroup partial sums go to the plan's workspace, so it must not
+ * overlap a solve on the same plan.  Errors: MBP_ERR_INVALID (NULL
+ * argument), MBP_ERR_BUSY (a solve is running in another thread),
+ * MBP_ERR_HIP. */
+int mbp_residual_norm(mbp_plan* plan, const double* rhs_dev, const double* p_dev, double rhs_shift,
+                      double* out_dev, void* stream);
 int mbp_inverse_transform(mbp_plan* plan, const double* phat_dev, double* p_dev, void* stream);
 int mbp_apply_operator(mbp_plan* plan, const double* p_dev, double* out_dev, void* stream);
 int mbp_modal_shift(const mbp_plan* plan, double* shift_host);

@@ -87,6 +87,7 @@ def _load():
         "mbp_forward_transform": (I, [P, VP, VP, VP]),
         "mbp_inverse_transform": (I, [P, VP, VP, VP]),
         "mbp_apply_operator": (I, [P, VP, VP, VP]),
+        "mbp_residual_norm": (I, [P, VP, VP, D, VP, VP]),
         "mbp_modal_shift": (I, [P, C.POINTER(D)]),
         "mbp_plan_destroy": (None, [P]),
         "mbp_profile_enable": (I, [P, I]),
@@ -117,7 +118,7 @@ lib = _load()
 EXPORTED = [
     "mbp_status_string", "mbp_version", "mbp_grid_tanh", "mbp_plan_check", "mbp_plan_create",
     "mbp_plan_layout", "mbp_solve", "mbp_solve_batch", "mbp_forward_transform",
-    "mbp_inverse_transform", "mbp_apply_operator", "mbp_modal_shift", "mbp_plan_destroy",
+    "mbp_inverse_transform", "mbp_apply_operator", "mbp_residual_norm", "mbp_modal_shift", "mbp_plan_destroy",
     "mbp_server_create", "mbp_server_submit", "mbp_server_poll", "mbp_server_wait",
     "mbp_server_destroy", "mbp_profile_enable", "mbp_profile_read", "mbp_batch_schedule",
     "mbp_plan_autotune", "mbp_plan_set_helmholtz",
@@ -286,6 +287,15 @@ class Plan:
     def apply(self, p, out, stream=None):
         _check(lib.mbp_apply_operator(self._h, _ptr(p, self.ncells), _ptr(out, self.ncells),
                                       _stream(stream)), "apply")
+
+    def residual_norm(self, rhs, p, rhs_shift=0.0, out=None, stream=None):
+        """(||f - s - L_h p||, ||f - s||) as a 2-element float64 device tensor."""
+        import torch
+        if out is None:
+            out = torch.empty(2, dtype=torch.float64, device=rhs.device)
+        _check(lib.mbp_residual_norm(self._h, _ptr(rhs, self.ncells), _ptr(p, self.ncells), float(rhs_shift),
+                                     _ptr(out, 2), _stream(stream)), "mbp_residual_norm")
+        return out
 
     def modal_shift(self) -> np.ndarray:
         out = np.empty(self.nz, dtype=np.float64)

@@ -1,4 +1,5 @@
 // The extern "C" surface declared in include/mbp.h.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -172,6 +173,19 @@ int mbp_inverse_transform(mbp_plan* plan, const double* phat_dev, double* p_dev,
 int mbp_apply_operator(mbp_plan* plan, const double* p_dev, double* out_dev, void* stream) {
     if (!plan || !p_dev || !out_dev || p_dev == out_dev) return MBP_ERR_INVALID;
     launch_apply3d(plan, p_dev, out_dev, static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? MBP_OK : MBP_ERR_HIP;
+}
+
+int mbp_residual_norm(mbp_plan* plan, const double* rhs_dev, const double* p_dev, double rhs_shift,
+                      double* out_dev, void* stream) {
+    if (!plan || !rhs_dev || !p_dev || !out_dev) return MBP_ERR_INVALID;
+    // the plan's partial-sum buffer holds 2 nz max(nparts, finest tiles) doubles
+    if (resnorm_scratch_doubles(plan) >
+        2 * size_t(plan->g.nz) * size_t(std::max(plan->nparts, plan->levels[0].ntiles)))
+        return MBP_ERR_INVALID;
+    if (!plan->busy.claim()) return MBP_ERR_BUSY;
+    launch_resnorm3d(plan, rhs_dev, p_dev, rhs_shift, plan->d_part, out_dev, static_cast<hipStream_t>(stream));
+    plan->busy.release();
     return hipGetLastError() == hipSuccess ? MBP_OK : MBP_ERR_HIP;
 }
 

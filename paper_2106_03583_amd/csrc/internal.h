@@ -212,6 +212,11 @@ void launch_forward(const mbp_plan* P, const double* f, double* fhat, int* nonfi
                     hipStream_t s);
 void launch_inverse(const mbp_plan* P, const double* phat, double* p, hipStream_t s);
 void launch_apply3d(const mbp_plan* P, const double* p, double* out, hipStream_t s);
+// Final check: out[0] = ||f - shift - (L_h - alpha) p||_2, out[1] = ||f - shift||_2
+// (device doubles), per-workgroup partials in part (resnorm_scratch_doubles).
+size_t resnorm_scratch_doubles(const mbp_plan* P);
+void launch_resnorm3d(const mbp_plan* P, const double* f, const double* p, double shift, double* part,
+                      double* out, hipStream_t s);
 
 // One V-cycle on every active mode.  p0 / f0: finest-level iterate and rhs;
 // p0B: second finest buffer for the out-of-place sweeps (the result is

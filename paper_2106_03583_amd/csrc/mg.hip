@@ -575,9 +575,39 @@ __global__ void k_sub(double* __restrict__ x, long long n, const double* __restr
         x[i] -= m;
 }
 
-// (L_h - alpha) p on the packed 3D field: x-y part from the level-0 tables,
-// z part with the ghost rules of the pair (N: g = p0, D: g = -p0, P: wrap),
-// alpha the Helmholtz term (0 for the pressure equation).
+// (L_h - alpha) p at cell c = (b, k, j, i) of the packed 3D field: x-y part
+// from the level-0 tables, z part with the ghost rules of the pair (N: g =
+// p0, D: g = -p0, P: wrap), alpha the Helmholtz term (0 for the pressure
+// equation).
+__device__ __forceinline__ double apply3d_value(const DBlock* __restrict__ B, const DBlock& b,
+                                                const double* __restrict__ dp, const double* __restrict__ p,
+                                                int nz, double idz2, int zkind, double alpha, int i, int j, int k,
+                                                long long c) {
+    const long long cols = (long long)b.nx * b.ny;
+    const double v = p[c];
+    // x-y neighbours (other blocks addressed through their own base)
+    auto at = [&](const DBlock& bb, int ii, int jj) __attribute__((always_inline)) {
+        return p[(long long)bb.off * nz + k * (long long)bb.nx * bb.ny + jj * bb.nx + ii];
+    };
+    double xm = 0, xp = 0, ym = 0, yp = 0;
+    if (i > 0) xm = p[c - 1];
+    else if (b.nbr[XM] >= 0) { const DBlock& kk = B[b.nbr[XM]]; xm = at(kk, kk.nx - 1, j); }
+    if (i < b.nx - 1) xp = p[c + 1];
+    else if (b.nbr[XP] >= 0) { const DBlock& kk = B[b.nbr[XP]]; xp = at(kk, 0, j); }
+    if (j > 0) ym = p[c - b.nx];
+    else if (b.nbr[YM] >= 0) { const DBlock& kk = B[b.nbr[YM]]; ym = at(kk, i, kk.ny - 1); }
+    if (j < b.ny - 1) yp = p[c + b.nx];
+    else if (b.nbr[YP] >= 0) { const DBlock& kk = B[b.nbr[YP]]; yp = at(kk, i, 0); }
+    double zm, zp;
+    if (k > 0) zm = p[c - cols];
+    else zm = zkind == Z_PP ? p[c + (nz - 1) * cols] : ((zkind == Z_NN || zkind == Z_ND) ? v : -v);
+    if (k < nz - 1) zp = p[c + cols];
+    else zp = zkind == Z_PP ? p[c - (nz - 1) * cols] : ((zkind == Z_NN || zkind == Z_DN) ? v : -v);
+    const double d = dp[b.cx + 2 * b.nx + i] + dp[b.cy + 2 * b.ny + j] - alpha;
+    return dp[b.cx + i] * xm + dp[b.cx + b.nx + i] * xp + dp[b.cy + j] * ym + dp[b.cy + b.ny + j] * yp +
+           d * v + (zm - 2.0 * v + zp) * idz2;
+}
+
 __global__ void __launch_bounds__(256)
 k_apply3d(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntiles,
           const double* __restrict__ dp, const double* __restrict__ p, double* __restrict__ out,
@@ -585,36 +615,65 @@ k_apply3d(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntil
     const int k = blockIdx.y;
     const int4 t = tiles[xcd_remap_mg(blockIdx.x, ntiles)];
     const DBlock b = B[t.x];
-    const long long cols = (long long)b.nx * b.ny;
     const long long base = (long long)b.off * nz;  // block start in the packed field
     const int i = t.y + threadIdx.x;
     if (i >= b.nx) return;
     for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
         const int j = t.z + r;
         if (j >= b.ny) break;
-        const long long c = base + k * cols + j * b.nx + i;
-        const double v = p[c];
-        // x-y neighbours (other blocks addressed through their own base)
-        auto at = [&](const DBlock& bb, int ii, int jj) __attribute__((always_inline)) {
-            return p[(long long)bb.off * nz + k * (long long)bb.nx * bb.ny + jj * bb.nx + ii];
-        };
-        double xm = 0, xp = 0, ym = 0, yp = 0;
-        if (i > 0) xm = p[c - 1];
-        else if (b.nbr[XM] >= 0) { const DBlock& kk = B[b.nbr[XM]]; xm = at(kk, kk.nx - 1, j); }
-        if (i < b.nx - 1) xp = p[c + 1];
-        else if (b.nbr[XP] >= 0) { const DBlock& kk = B[b.nbr[XP]]; xp = at(kk, 0, j); }
-        if (j > 0) ym = p[c - b.nx];
-        else if (b.nbr[YM] >= 0) { const DBlock& kk = B[b.nbr[YM]]; ym = at(kk, i, kk.ny - 1); }
-        if (j < b.ny - 1) yp = p[c + b.nx];
-        else if (b.nbr[YP] >= 0) { const DBlock& kk = B[b.nbr[YP]]; yp = at(kk, i, 0); }
-        double zm, zp;
-        if (k > 0) zm = p[c - cols];
-        else zm = zkind == Z_PP ? p[c + (nz - 1) * cols] : ((zkind == Z_NN || zkind == Z_ND) ? v : -v);
-        if (k < nz - 1) zp = p[c + cols];
-        else zp = zkind == Z_PP ? p[c - (nz - 1) * cols] : ((zkind == Z_NN || zkind == Z_DN) ? v : -v);
-        const double d = dp[b.cx + 2 * b.nx + i] + dp[b.cy + 2 * b.ny + j] - alpha;
-        out[c] = dp[b.cx + i] * xm + dp[b.cx + b.nx + i] * xp + dp[b.cy + j] * ym +
-                 dp[b.cy + b.ny + j] * yp + d * v + (zm - 2.0 * v + zp) * idz2;
+        const long long c = base + k * (long long)b.nx * b.ny + j * b.nx + i;
+        out[c] = apply3d_value(B, b, dp, p, nz, idz2, zkind, alpha, i, j, k, c);
+    }
+}
+
+// Final check of a solve (every cell of the packed field): per-workgroup
+// partial sums of (f - shift - (L_h - alpha) p)^2 into part[w] and of
+// (f - shift)^2 into part[nw + w], nw = workgroups of the launch.
+__global__ void __launch_bounds__(256)
+k_resnorm3d(const DBlock* __restrict__ B, const int4* __restrict__ tiles, int ntiles,
+            const double* __restrict__ dp, const double* __restrict__ p, const double* __restrict__ f,
+            double shift, int nz, double idz2, int zkind, double alpha, double* __restrict__ part) {
+    const int k = blockIdx.y;
+    const int4 t = tiles[xcd_remap_mg(blockIdx.x, ntiles)];
+    const DBlock b = B[t.x];
+    const long long base = (long long)b.off * nz;
+    const int i = t.y + threadIdx.x;
+    double rr = 0.0, ff = 0.0;
+    if (i < b.nx)
+        for (int r = threadIdx.y; r < kTileY; r += kRowsPerPass) {
+            const int j = t.z + r;
+            if (j >= b.ny) break;
+            const long long c = base + k * (long long)b.nx * b.ny + j * b.nx + i;
+            const double fv = f[c] - shift;
+            const double res = fv - apply3d_value(B, b, dp, p, nz, idz2, zkind, alpha, i, j, k, c);
+            rr += res * res;
+            ff += fv * fv;
+        }
+    __shared__ double red[8];
+    const long long w = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    const long long nw = (long long)gridDim.y * gridDim.x;
+    const double sr = block_sum(rr, red);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[w] = sr;
+    const double sf = block_sum(ff, red);
+    if (threadIdx.x == 0 && threadIdx.y == 0) part[nw + w] = sf;
+}
+
+// out[0] = sqrt(sum part[0, n)), out[1] = sqrt(sum part[n, 2n)).
+__global__ void __launch_bounds__(1024) k_resnorm_finish(const double* __restrict__ part, long long n,
+                                                         double* __restrict__ out) {
+    __shared__ double red[16];
+    for (int h = 0; h < 2; ++h) {
+        double acc = 0.0;
+        for (long long e = threadIdx.x; e < n; e += blockDim.x) acc += part[h * n + e];
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s2 = 0.0;
+            for (int w = 0; w < int(blockDim.x >> 6); ++w) s2 += red[w];
+            out[h] = sqrt(s2);
+        }
     }
 }
 
@@ -1178,6 +1237,19 @@ void launch_singular_fix(const mbp_plan* P, double* plane, double* out_sum, hipS
 void launch_area_dot(const mbp_plan* P, const double* plane, double* out_sum, hipStream_t s) {
     hipLaunchKernelGGL(k_area_dot, dim3(1), dim3(1024), 0, s, plane, P->d_area0, (long long)P->plane0,
                        out_sum);
+}
+
+size_t resnorm_scratch_doubles(const mbp_plan* P) {
+    return 2 * size_t(P->levels[0].ntiles) * size_t(P->g.nz);
+}
+
+void launch_resnorm3d(const mbp_plan* P, const double* f, const double* p, double shift, double* part,
+                      double* out, hipStream_t s) {
+    const Level& L = P->levels[0];
+    hipLaunchKernelGGL(k_resnorm3d, dim3(L.ntiles, P->g.nz), dim3(kTileX, kRowsPerPass), 0, s,
+                       P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, f, shift, P->g.nz,
+                       1.0 / (P->g.dz * P->g.dz), int(P->g.zkind), P->opt.helmholtz, part);
+    hipLaunchKernelGGL(k_resnorm_finish, dim3(1), dim3(1024), 0, s, part, (long long)L.ntiles * P->g.nz, out);
 }
 
 void launch_apply3d(const mbp_plan* P, const double* p, double* out, hipStream_t s) {

@@ -280,3 +280,29 @@ def test_plan_autotune(torch_cuda, mbp, prob, precision):
     assert info.status == 0
     assert oracle.rel_error(host(p), ref) <= 1e-9
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# Final check (mbp_residual_norm): the 3D residual norm of any field, against
+# the oracle's operator, with the rhs shift of a projected singular solve and
+# the Helmholtz term.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("alpha", [0.0, 7.5])
+@pytest.mark.parametrize("prob", [W.lshape(40, 12, 1.5, 1.0), two_block(10, "DN"),
+                                  W.box(70, 33, 8, 1.0, 0.5, 0.25, "PP", "ND", "PP", yfactor=1.2, name="box70x33")],
+                         ids=lambda p: p.name)
+def test_residual_norm(torch_cuda, mbp, prob, alpha):
+    torch = torch_cuda
+    rng = np.random.default_rng(71)
+    p = rng.standard_normal(prob.ncells)
+    f = rng.standard_normal(prob.ncells)
+    shift = 0.125
+    plan = mbp.Plan(prob, helmholtz=alpha)
+    out = host(plan.residual_norm(dev(torch, f), dev(torch, p), shift))
+    g = oracle.Geometry(prob)
+    r = f - shift - oracle.apply_3d(g, p, alpha)
+    print(f"  {prob.name} alpha={alpha}: {out} vs {np.linalg.norm(r)}, {np.linalg.norm(f - shift)}", flush=True)
+    assert abs(out[0] - np.linalg.norm(r)) <= 1e-12 * np.linalg.norm(r)
+    assert abs(out[1] - np.linalg.norm(f - shift)) <= 1e-12 * np.linalg.norm(f - shift)
+    plan.close()
