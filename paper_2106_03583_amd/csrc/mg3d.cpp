@@ -292,11 +292,9 @@ void mg3_cycle(mbp3_plan* X, double* p, const double* f, double fshift, bool zer
         for (int k = 0; k < nu1; ++k) {
             const bool zero = k == 0 && (l > 0 || zero_p);
             const bool norm = l == 0 && k == 0 && ev;
-            m3_jacobi(M, l, cur[l], oth[l], rhs[l], sh, zero, norm ? M.d_part : nullptr, s);
+            const long long nw = m3_jacobi(M, l, cur[l], oth[l], rhs[l], sh, zero, norm ? M.d_part : nullptr, s);
             std::swap(cur[l], oth[l]);
             if (norm) {
-                const Mg3Level& F = M.lev[0];
-                const long long nw = (long long)F.ntiles * F.nz;
                 m3_total(M.d_part, nw, 1.0, M.d_scal, s);
                 m3_total(M.d_part + nw, nw, 1.0, M.d_scal + 1, s);
                 (void)hipMemcpyAsync(pin + 8 * slot, M.d_scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s);

@@ -51,8 +51,10 @@ struct Mg3Plan {
     double* q0 = nullptr;     // second finest buffer
 };
 
-void m3_jacobi(const Mg3Plan& M, int l, const double* pin, double* pout, const double* f, double fshift,
-               bool zero, double* part, hipStream_t s);
+// One sweep; returns the number of workgroups (the count of partial sums
+// written to part[0, n) and part[n, 2n) when part is given).
+long long m3_jacobi(const Mg3Plan& M, int l, const double* pin, double* pout, const double* f, double fshift,
+                    bool zero, double* part, hipStream_t s);
 void m3_residual_norm(const Mg3Plan& M, const double* p, const double* f, double fshift, bool zero, double* part,
                       double* out, hipStream_t s);
 void m3_total(const double* part, long long n, double scale, double* out, hipStream_t s);

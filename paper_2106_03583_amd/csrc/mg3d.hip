@@ -151,6 +151,149 @@ k3_jacobi(Op3 o, const int4* __restrict__ tiles, int ntiles, const double* __res
 }
 
 // ---------------------------------------------------------------------------
+// The same sweep (pin read, so not the zero start) marching along z: a
+// workgroup owns one 64 x 16 x-y tile and a chunk of kZChunk planes; each
+// thread keeps its four cells' values at planes k-1, k, k+1 in registers and
+// the plane-k tile (with a one-cell ring from the tile's neighbours, or from
+// the partner block across a joined face) in LDS.  Every value of p is read
+// from device memory once per sweep, plus the ring.
+// ---------------------------------------------------------------------------
+constexpr int kZChunk = 32;
+
+namespace {
+
+// p at (k, jj, ii) of block b where (ii, jj) may lie one cell outside the
+// block: the partner's cell across a joined face, 0 beyond a wall (its
+// coupling coefficient is zero) or diagonally outside.
+__device__ __forceinline__ double ring_value(const Op3& o, const double* __restrict__ p, const DBlock& b, int k,
+                                             int ii, int jj) {
+    const bool xin = ii >= 0 && ii < b.nx, yin = jj >= 0 && jj < b.ny;
+    if (xin && yin) return p[cell3(b, o.nz, k, jj, ii)];
+    if (yin) {
+        if (ii == -1 && b.nbr[XM] >= 0) { const DBlock& n = o.B[b.nbr[XM]]; return p[cell3(n, o.nz, k, jj, n.nx - 1)]; }
+        if (ii == b.nx && b.nbr[XP] >= 0) { const DBlock& n = o.B[b.nbr[XP]]; return p[cell3(n, o.nz, k, jj, 0)]; }
+    } else if (xin) {
+        if (jj == -1 && b.nbr[YM] >= 0) { const DBlock& n = o.B[b.nbr[YM]]; return p[cell3(n, o.nz, k, n.ny - 1, ii)]; }
+        if (jj == b.ny && b.nbr[YP] >= 0) { const DBlock& n = o.B[b.nbr[YP]]; return p[cell3(n, o.nz, k, 0, ii)]; }
+    }
+    return 0.0;
+}
+
+// Plane index of z neighbour k (periodic wrap) or -1 where the ghost rule
+// applies (its coupling is folded into the diagonal).
+__device__ __forceinline__ int zplane(const Op3& o, int k) {
+    if (k >= 0 && k < o.nz) return k;
+    if (o.zlo == MBP_PERIODIC) return (k + o.nz) % o.nz;
+    return -1;
+}
+
+}  // namespace
+
+template <bool NORM>
+__global__ void __launch_bounds__(256)
+k3_jacobi_zm(Op3 o, const int4* __restrict__ tiles, int ntiles, const double* __restrict__ pin,
+             double* __restrict__ pout, const double* __restrict__ f, double fshift, double omega,
+             double* __restrict__ part) {
+    __shared__ double sp[kTileY + 2][kTileX + 2];
+    const int4 t = tiles[xcd_remap3(blockIdx.x, ntiles)];
+    const DBlock b = o.B[t.x];
+    const int k0 = blockIdx.y * kZChunk;
+    const int k1 = min(k0 + kZChunk, o.nz);
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = ty * kTileX + tx;
+    const int i = t.y + tx;
+    const bool in_i = i < b.nx;
+    const double* dp = o.dp;
+    const long long kz = (long long)b.nx * b.ny;
+    const long long base = (long long)o.nz * b.off;
+    constexpr int R = kTileY / kRowsPerPass;  // rows per thread
+    int j[R];
+    bool act[R];
+    double wym[R], wyp[R], dxy[R];
+    const double wxm = in_i ? dp[b.cx + i] : 0.0, wxp = in_i ? dp[b.cx + b.nx + i] : 0.0;
+    const double dx = in_i ? dp[b.cx + 2 * b.nx + i] : 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        j[r] = t.z + ty + kRowsPerPass * r;
+        act[r] = in_i && j[r] < b.ny;
+        wym[r] = act[r] ? dp[b.cy + j[r]] : 0.0;
+        wyp[r] = act[r] ? dp[b.cy + b.ny + j[r]] : 0.0;
+        dxy[r] = act[r] ? dx + dp[b.cy + 2 * b.ny + j[r]] - o.alpha : 1.0;
+    }
+    auto load = [&](int kp, double* v) {
+        const int q = zplane(o, kp);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = (act[r] && q >= 0) ? pin[base + q * kz + (long long)j[r] * b.nx + i] : 0.0;
+    };
+    auto loadf = [&](int kp, double* v) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            v[r] = (act[r] && kp < o.nz) ? f[base + kp * kz + (long long)j[r] * b.nx + i] - fshift : 0.0;
+    };
+    double pm[R], pc[R], pp[R], fc[R], pn[R], fn[R];
+    load(k0 - 1, pm);
+    load(k0, pc);
+    load(k0 + 1, pp);
+    loadf(k0, fc);
+    double acc = 0.0, accp = 0.0;
+    for (int k = k0; k < k1; ++k) {
+        if (k + 1 < k1) {  // next plane's loads in flight during this plane's work
+            load(k + 2, pn);
+            loadf(k + 1, fn);
+        }
+        // plane k into LDS: own cells from registers, the ring and cells of a
+        // ragged tile's edge through ring_value
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int ly = ty + kRowsPerPass * r;
+            sp[ly + 1][tx + 1] = act[r] ? pc[r] : ring_value(o, pin, b, k, i, t.z + ly);
+        }
+        if (tid < 2 * kTileX) {
+            const int side = tid / kTileX, lx = tid % kTileX;
+            const int jj = side == 0 ? t.z - 1 : t.z + kTileY;
+            sp[side == 0 ? 0 : kTileY + 1][lx + 1] = ring_value(o, pin, b, k, t.y + lx, jj);
+        } else if (tid < 2 * kTileX + 2 * kTileY) {
+            const int e = tid - 2 * kTileX, side = e / kTileY, ly = e % kTileY;
+            const int ii = side == 0 ? t.y - 1 : t.y + kTileX;
+            sp[ly + 1][side == 0 ? 0 : kTileX + 1] = ring_value(o, pin, b, k, ii, t.z + ly);
+        }
+        __syncthreads();
+        const double zd = zdiag(o, k);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!act[r]) continue;
+            const int ly = ty + kRowsPerPass * r + 1, lx = tx + 1;
+            const double d = dxy[r] + zd;
+            const double off = wxm * sp[ly][lx - 1] + wxp * sp[ly][lx + 1] + wym[r] * sp[ly - 1][lx] +
+                               wyp[r] * sp[ly + 1][lx] + o.idz2 * (pm[r] + pp[r]);
+            const double res = fc[r] - off - d * pc[r];
+            if (NORM) {
+                acc += res * res;
+                accp += pc[r] * pc[r];
+            }
+            pout[base + k * kz + (long long)j[r] * b.nx + i] = pc[r] + omega * res / d;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            pm[r] = pc[r];
+            pc[r] = pp[r];
+            pp[r] = pn[r];
+            fc[r] = fn[r];
+        }
+    }
+    if (NORM) {
+        __shared__ double red[8];
+        const long long w = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+        const long long nw = (long long)gridDim.y * gridDim.x;
+        const double sr = wg_sum(acc, red);
+        if (tid == 0) part[w] = sr;
+        const double sq = wg_sum(accp, red);
+        if (tid == 0) part[nw + w] = sq;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Residual of level l restricted to level l+1 (volume-weighted average of
 // the children), written to fc; one thread per coarse cell.
 // ---------------------------------------------------------------------------
@@ -388,22 +531,23 @@ dim3 grid_of(const Mg3Level& L) { return dim3(unsigned(L.ntiles), unsigned(L.nz)
 const dim3 kBlk(kTileX, kRowsPerPass);
 }  // namespace
 
-void m3_jacobi(const Mg3Plan& M, int l, const double* pin, double* pout, const double* f, double fshift,
-               bool zero, double* part, hipStream_t s) {
+long long m3_jacobi(const Mg3Plan& M, int l, const double* pin, double* pout, const double* f, double fshift,
+                    bool zero, double* part, hipStream_t s) {
     const Mg3Level& L = M.lev[l];
     const Op3 o = op_of(M, l);
     const int4* tl = M.d_tiles + L.tile_off;
-    if (zero) {
+    if (zero) {  // elementwise: no neighbour is read
         if (part) hipLaunchKernelGGL((k3_jacobi<true, true, true>), grid_of(L), kBlk, 0, s, o, tl, L.ntiles, pin, pout, f,
                                      fshift, M.omega, part);
         else hipLaunchKernelGGL((k3_jacobi<true, false, true>), grid_of(L), kBlk, 0, s, o, tl, L.ntiles, pin, pout, f,
                                 fshift, M.omega, part);
-    } else {
-        if (part) hipLaunchKernelGGL((k3_jacobi<false, true, true>), grid_of(L), kBlk, 0, s, o, tl, L.ntiles, pin, pout,
-                                     f, fshift, M.omega, part);
-        else hipLaunchKernelGGL((k3_jacobi<false, false, true>), grid_of(L), kBlk, 0, s, o, tl, L.ntiles, pin, pout, f,
-                                fshift, M.omega, part);
+        return (long long)L.ntiles * L.nz;
     }
+    const dim3 g(unsigned(L.ntiles), unsigned((L.nz + kZChunk - 1) / kZChunk));
+    if (part) hipLaunchKernelGGL(k3_jacobi_zm<true>, g, kBlk, 0, s, o, tl, L.ntiles, pin, pout, f, fshift, M.omega,
+                                 part);
+    else hipLaunchKernelGGL(k3_jacobi_zm<false>, g, kBlk, 0, s, o, tl, L.ntiles, pin, pout, f, fshift, M.omega, part);
+    return (long long)g.x * g.y;
 }
 
 // Squared norms of the finest residual of p and of p itself into out[0], out[1].
