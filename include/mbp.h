@@ -284,6 +284,22 @@ int mbp_forward_transform(mbp_plan* plan, const double* f_dev, double* fhat_dev,
  * MBP_ERR_HIP. */
 int mbp_residual_norm(mbp_plan* plan, const double* rhs_dev, const double* p_dev, double rhs_shift,
                       double* out_dev, void* stream);
+
+/* The same check for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): allocates
+ * nothing and does not touch the plan's workspace (only its read-only
+ * tables), so it may also run while a solve on the plan is in flight.  Its
+ * partial sums live in a fixed per-device scratch array of
+ * mbp_noalloc_scratch_bytes() bytes (8 MiB; the check needs
+ * 16 * nz * (finest-level tiles of 64 x 16 cells) bytes); larger problems
+ * get MBP_ERR_TOO_LARGE.  Every call on a GPU shares that GPU's array:
+ * calls that overlap on one GPU (several streams or threads) race and must
+ * be ordered by the caller.  Same arguments and results as
+ * mbp_residual_norm; the plan must live on the current device
+ * (MBP_ERR_INVALID otherwise). */
+int mbp_residual_norm_noalloc(const mbp_plan* plan, const double* rhs_dev, const double* p_dev,
+                              double rhs_shift, double* out_dev, void* stream);
+size_t mbp_noalloc_scratch_bytes(void);
 int mbp_inverse_transform(mbp_plan* plan, const double* phat_dev, double* p_dev, void* stream);
 int mbp_apply_operator(mbp_plan* plan, const double* p_dev, double* out_dev, void* stream);
 int mbp_modal_shift(const mbp_plan* plan, double* shift_host);

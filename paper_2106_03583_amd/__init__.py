@@ -88,6 +88,8 @@ def _load():
         "mbp_inverse_transform": (I, [P, VP, VP, VP]),
         "mbp_apply_operator": (I, [P, VP, VP, VP]),
         "mbp_residual_norm": (I, [P, VP, VP, D, VP, VP]),
+        "mbp_residual_norm_noalloc": (I, [P, VP, VP, D, VP, VP]),
+        "mbp_noalloc_scratch_bytes": (C.c_size_t, []),
         "mbp_modal_shift": (I, [P, C.POINTER(D)]),
         "mbp_plan_destroy": (None, [P]),
         "mbp_profile_enable": (I, [P, I]),
@@ -118,7 +120,8 @@ lib = _load()
 EXPORTED = [
     "mbp_status_string", "mbp_version", "mbp_grid_tanh", "mbp_plan_check", "mbp_plan_create",
     "mbp_plan_layout", "mbp_solve", "mbp_solve_batch", "mbp_forward_transform",
-    "mbp_inverse_transform", "mbp_apply_operator", "mbp_residual_norm", "mbp_modal_shift", "mbp_plan_destroy",
+    "mbp_inverse_transform", "mbp_apply_operator", "mbp_residual_norm", "mbp_residual_norm_noalloc",
+    "mbp_noalloc_scratch_bytes", "mbp_modal_shift", "mbp_plan_destroy",
     "mbp_server_create", "mbp_server_submit", "mbp_server_poll", "mbp_server_wait",
     "mbp_server_destroy", "mbp_profile_enable", "mbp_profile_read", "mbp_batch_schedule",
     "mbp_plan_autotune", "mbp_plan_set_helmholtz",
