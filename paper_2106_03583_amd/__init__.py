@@ -337,10 +337,10 @@ class Plan3D:
     """The 3D multigrid solver without z synthesis (the comparison solver):
     weighted-Jacobi V-cycles on the whole 3D system, FP64."""
 
-    def __init__(self, problem, nu1=2, nu2=2, max_cycles=100, flags=0, helmholtz=0.0):
+    def __init__(self, problem, nu1=2, nu2=2, max_cycles=100, flags=0, helmholtz=0.0, etol=0.0):
         self.problem = problem
         self._desc = _Desc(problem)
-        self._opt = _options("fp64", nu1, nu2, max_cycles, flags, 0.0, 0, 0, SMOOTHER_JACOBI, helmholtz)
+        self._opt = _options("fp64", nu1, nu2, max_cycles, flags, etol, 0, 0, SMOOTHER_JACOBI, helmholtz)
         self._h = C.c_void_p()
         _check(lib.mbp3_plan_create(self._desc.blocks, self._desc.nblocks, C.byref(self._desc.z),
                                     C.byref(self._opt), C.byref(self._h)), "mbp3_plan_create")

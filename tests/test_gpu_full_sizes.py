@@ -2,13 +2,15 @@
 
 Workloads (the shapes bench.py times): the three-block L-shape 3 x 256^2 x 512
 (periodic z, Neumann walls, tanh-stretched y), the 512 x 512 x 1024 box
-(DD / NN / NN with the DCT-II along z), the 64-problem batch (boxes
+(DD / NN / NN with the DCT-II along z), the eight blocks around a square
+obstacle (64 cells per side, 576 periodic z cells), the 64-problem batch (boxes
 64..384 x 64..384 x 64..256, every condition pair) and a sample of the request
 stream (sizes log-uniform 32..512 per axis, stretched walls).  Every rhs is
 drawn on the host with NumPy's PCG64 from its seed, so the oracle sees the
 same bits.
 
-For each result, in FP64 and in the mixed form:
+For each result, in FP64 and in the mixed form (and, for single problems, the
+3D multigrid comparison solver):
   * the relative 3D residual ||f - L_h p|| / ||f|| with the ORACLE's operator
     (host, every cell) must be <= 1e-10;
   * the relative error against the oracle's direct solution (Algorithm 1 with
@@ -69,6 +71,17 @@ def _solve_one(torch, mbp, prob, fd, precision):
     return out, info
 
 
+def _solve_mg3d(torch, mbp, prob, fd):
+    plan = mbp.Plan3D(prob)
+    p = torch.zeros_like(fd)
+    info = plan.solve(fd, p, rtol=RTOL, flags=mbp.PROJECT_RHS)
+    plan.close()
+    assert info.status == 0 and info.rel_residual <= RTOL
+    out = p.cpu().numpy()
+    del p
+    return out, info
+
+
 def _single(torch, mbp, prob, seed, dist, ref_fn):
     f = W.rhs(prob, seed, dist)
     fd = torch.from_numpy(f).cuda()
@@ -77,6 +90,10 @@ def _single(torch, mbp, prob, seed, dist, ref_fn):
         print(f"full-size {prob.name} {precision}: solving on the GPU", flush=True)
         sols[precision], info = _solve_one(torch, mbp, prob, fd, precision)
         print(f"  {info}", flush=True)
+    # the comparison solver (3D multigrid without z synthesis) reaches the same solution
+    print(f"full-size {prob.name} 3D multigrid: solving on the GPU", flush=True)
+    sols["mg3d"], info = _solve_mg3d(torch, mbp, prob, fd)
+    print(f"  {info}", flush=True)
     del fd
     torch.cuda.empty_cache()
     print(f"full-size {prob.name}: oracle", flush=True)
@@ -94,6 +111,13 @@ def test_full_field_lshape(torch_cuda, mbp):
 def test_full_field_box(torch_cuda, mbp):
     """512 x 512 x 1024 box: separable eigen-decomposition in the oracle."""
     _single(torch_cuda, mbp, W.config3(), W.CONFIG_SEEDS[3], W.CONFIG_DIST[3], oracle.solve_separable)
+
+
+def test_full_field_obstacle8(torch_cuda, mbp):
+    """Eight blocks around a square obstacle, 64 cells per side, 576 periodic z
+    cells: Algorithm 1 in the oracle with per-shift LUs in a process pool."""
+    _single(torch_cuda, mbp, W.obstacle8(64, 576), 6, "normal",
+            lambda prob, f: oracle.solve_alg1(prob, f, workers=_workers()))
 
 
 BATCH_SEED0 = 4000  # rhs seed of batch problem i is BATCH_SEED0 + i

@@ -93,7 +93,7 @@ def four_block(n=32, nz=8):
 
 
 def _small():
-    out = [W.lshape(32, 16, 1.5, 1.0), four_block()]
+    out = [W.lshape(32, 16, 1.5, 1.0), four_block(), W.obstacle8(8, 12)]
     for i, zk in enumerate(KINDS):
         xp, yp = KINDS[(i + 2) % 5], KINDS[(i + 4) % 5]
         out.append(W.box(40, 36, 12, 40 / 64, 36 / 64, 12 / 64, xp, yp, zk, xfactor=1.3, yfactor=1.1,

@@ -306,3 +306,22 @@ def test_residual_norm(torch_cuda, mbp, prob, alpha):
     assert abs(out[0] - np.linalg.norm(r)) <= 1e-12 * np.linalg.norm(r)
     assert abs(out[1] - np.linalg.norm(f - shift)) <= 1e-12 * np.linalg.norm(f - shift)
     plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_obstacle8_small(torch_cuda, mbp, precision):
+    """Eight blocks around a square obstacle (Sec. 4.2): joined faces on all
+    sides of the obstacle, Neumann inflow and walls, Dirichlet outflow."""
+    torch = torch_cuda
+    prob = W.obstacle8(16, 12)
+    f = W.rhs(prob, 91, "normal")
+    ref = oracle.solve(prob, f)
+    plan = mbp.Plan(prob, precision=precision)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.PROJECT_RHS | mbp.RETIRE)
+    got = host(p)
+    res = oracle.rel_residual(prob, got, f)
+    err = oracle.rel_error(got, ref)
+    print(f"  obstacle8 {precision}: {info} residual={res:.2e} error={err:.2e}", flush=True)
+    assert info.status == 0 and res <= 1e-10 and err <= 1e-9
+    plan.close()

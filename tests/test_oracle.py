@@ -395,3 +395,23 @@ def test_workload_shapes():
     assert kinds == set(KINDS)
     c5 = W.config5(50)
     assert all(32 <= b.nx <= 512 and b.nx % 16 == 0 for r in c5 for b in r.problem.blocks)
+
+
+def test_obstacle8_layout_and_routes():
+    """Eight blocks around a square obstacle (Sec. 4.2): every block is joined
+    to its neighbours in the 3 x 3 arrangement except across the obstacle,
+    whose four sides are walls; Algorithm 1 and the dense route agree."""
+    prob = W.obstacle8(4, 6)
+    g = Geometry(prob)
+    assert g.nb == 8
+    # rows bottom (0, 1, 2), middle (3: left, 4: right), top (5, 6, 7)
+    assert g.nbr == [[-1, 1, -1, 3], [0, 2, -1, -1], [1, -1, -1, 4], [-1, -1, 0, 5],
+                     [-1, -1, 2, 7], [-1, 6, 3, -1], [5, 7, -1, -1], [6, -1, 4, -1]]
+    assert prob.blocks[1].bc[3] == W.NEUMANN and prob.blocks[6].bc[2] == W.NEUMANN  # obstacle walls
+    assert prob.blocks[3].bc[1] == W.NEUMANN and prob.blocks[4].bc[0] == W.NEUMANN
+    assert prob.blocks[0].bc[0] == W.NEUMANN and prob.blocks[2].bc[1] == W.DIRICHLET  # inflow / outflow
+    f = W.rhs(prob, 14, "normal")
+    a = oracle.solve_alg1(prob, f)
+    b = oracle.solve_dense(prob, f)
+    assert oracle.rel_error(a, b) < 1e-12
+    assert oracle.rel_residual(prob, a, f) < 1e-12

@@ -149,6 +149,38 @@ def lshape(n: int = 256, nz: int = 512, factor: float = 1.5, lz: float = 2.0) ->
                    name=f"lshape3x{n}^2x{nz}_stretch{factor}")
 
 
+def obstacle8(n: int = 64, nz: int = 576, lz_per_h: float = 9.0) -> Problem:
+    """Eight blocks around a square obstacle of side H = 1 (Sec. 4.2, the flow
+    around a square cylinder): a 3 x 3 arrangement of blocks with the centre
+    one removed.  Widths along x: 2H upstream, H, 2H downstream; heights H
+    below, H, H above (the performance setup shrinks the top, bottom and
+    downstream blocks by 3 from a 3H / 6H layout).  n cells per H, uniform
+    spacing; z periodic with nz cells on [0, lz_per_h * H * nz / 576) so that
+    dz = H / 64 at nz = 576.  Pressure-correction conditions: Neumann at the
+    inflow (x = 0) and on the obstacle walls, Dirichlet (zero pressure) at the
+    outflow, top and bottom."""
+    D, N, C = DIRICHLET, NEUMANN, CONNECT
+    widths, heights = [2, 1, 2], [1, 1, 1]  # in units of H
+    x0 = [0, 2, 3, 5]
+    y0 = [0, 1, 2, 3]
+    blocks = []
+    for row in range(3):
+        for col in range(3):
+            if row == 1 and col == 1:
+                continue
+            nx, ny = widths[col] * n, heights[row] * n
+            lo = (x0[col] * n + 1, y0[row] * n + 1)
+            hi = (lo[0] + nx - 1, lo[1] + ny - 1)
+            bxm = N if col == 0 else (N if (row == 1 and col == 2) else C)
+            bxp = D if col == 2 else (N if (row == 1 and col == 0) else C)
+            bym = D if row == 0 else (N if (col == 1 and row == 2) else C)
+            byp = D if row == 2 else (N if (col == 1 and row == 0) else C)
+            blocks.append(Block(lo, hi, faces(nx, float(x0[col]), float(x0[col + 1])),
+                                faces(ny, float(y0[row]), float(y0[row + 1])), (bxm, bxp, bym, byp)))
+    lz = lz_per_h * nz / 576.0
+    return Problem(blocks=blocks, nz=nz, lz=lz, zbc=PAIRS["PP"], name=f"obstacle8_{n}perH_nz{nz}")
+
+
 def config2() -> Problem:
     return lshape(256, 512, 1.5, 2.0)
 
