@@ -27,6 +27,7 @@ volume-weighted mean.
 from .transforms import basis, eigenvalues, table1_unnormalised, KINDS  # noqa: F401
 from .grid import Geometry  # noqa: F401
 from .operator import apply_3d, assemble_2d, assemble_3d_dense, second_difference_1d  # noqa: F401
+from . import projection  # noqa: F401
 from .solve import (  # noqa: F401
     solve, solve_alg1, solve_separable, solve_dense, residual, rel_residual,
     rel_error, project_compatible, remove_mean, is_singular, modal_rhs, solve_mode,

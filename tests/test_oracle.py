@@ -415,3 +415,78 @@ def test_obstacle8_layout_and_routes():
     b = oracle.solve_dense(prob, f)
     assert oracle.rel_error(a, b) < 1e-12
     assert oracle.rel_residual(prob, a, f) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Projection (Eqs. (3)-(6)): divergence and face gradient of the staggered grid
+# ---------------------------------------------------------------------------
+
+from oracle import projection as PJ  # noqa: E402
+
+
+def _random_faces(prob, seed):
+    nu, nv, nw = PJ.face_sizes(prob)
+    rng = np.random.default_rng(seed)
+    return PJ.make_consistent(prob, rng.standard_normal(nu), rng.standard_normal(nv), rng.standard_normal(nw))
+
+
+@pytest.mark.parametrize("prob", _tiny_problems() + [W.obstacle8(4, 4)], ids=lambda p: p.name)
+def test_divergence_of_gradient_is_the_operator(prob):
+    """D G = L_h: the face gradient and divergence, written on their own,
+    compose to the (independently pinned) finite-volume operator."""
+    g = Geometry(prob)
+    phi = np.random.default_rng(15).standard_normal(g.ncell3)
+    gu, gv, gw = PJ.gradient(prob, phi)
+    assert np.allclose(PJ.divergence(prob, gu, gv, gw), apply_3d(g, phi), rtol=1e-12, atol=1e-8)
+
+
+@pytest.mark.parametrize("pairs", [("DD", "NN", "PP"), ("PP", "PP", "NN"), ("ND", "DN", "DD")])
+def test_divergence_of_discrete_curl_vanishes(pairs):
+    """u = d psi / dy, v = -d psi / dx from corner values of a stream function
+    psi (constant in z, w = 0) is discretely divergence free on any spacing."""
+    xp, yp, zp = pairs
+    prob = W.box(9, 7, 4, 1.0, 0.8, 0.5, xp, yp, zp, xfactor=1.3 if xp != "PP" else 0.0,
+                 yfactor=1.6 if yp != "PP" else 0.0)
+    g = Geometry(prob)
+    nx, ny, nz = 9, 7, 4
+    psi = np.random.default_rng(16).standard_normal((ny + 1, nx + 1))
+    if xp == "PP":
+        psi[:, -1] = psi[:, 0]
+    if yp == "PP":
+        psi[-1, :] = psi[0, :]
+    u = np.broadcast_to(np.diff(psi, axis=0)[None, :, :] / g.dcy[0][None, :, None], (nz, ny, nx + 1))
+    v = np.broadcast_to(-np.diff(psi, axis=1)[None, :, :] / g.dcx[0][None, None, :], (nz, ny + 1, nx))
+    nwz = nz if zp == "PP" else nz + 1
+    div = PJ.divergence(prob, u.ravel(), v.ravel(), np.zeros(nwz * ny * nx))
+    assert np.abs(div).max() < 1e-12 * (np.abs(u).max() / g.dcx[0].min())
+
+
+def test_divergence_theorem_and_projection():
+    """Gauss: sum V D u equals the net outflow through the walls; after the
+    projection D u vanishes, the velocity changes by -gamma dt G Phi only, and
+    a field that is already divergence free is left as it is."""
+    prob = W.obstacle8(4, 6)
+    g = Geometry(prob)
+    u, v, w = _random_faces(prob, 17)
+    us, vs, ws = PJ.split_faces(prob, u, v, w)
+    flux = 0.0
+    for b in range(g.nb):
+        if g.nbr[b][1] < 0:
+            flux += (us[b][:, :, -1] * g.dcy[b][None, :] * g.dz).sum()
+        if g.nbr[b][0] < 0:
+            flux -= (us[b][:, :, 0] * g.dcy[b][None, :] * g.dz).sum()
+        if g.nbr[b][3] < 0:
+            flux += (vs[b][:, -1, :] * g.dcx[b][None, :] * g.dz).sum()
+        if g.nbr[b][2] < 0:
+            flux -= (vs[b][:, 0, :] * g.dcx[b][None, :] * g.dz).sum()
+    div = PJ.divergence(prob, u, v, w)
+    assert abs(np.dot(g.volumes(), div) - flux) < 1e-10 * np.abs(div).sum() * g.volumes().max()
+    gdt = 0.37
+    u2, v2, w2, phi = PJ.project(prob, u, v, w, gdt)
+    d2 = PJ.divergence(prob, u2, v2, w2)
+    assert np.linalg.norm(d2) < 1e-11 * np.linalg.norm(div)
+    gu, gv, gw = PJ.gradient(prob, phi)
+    assert np.allclose(u2, u - gdt * gu) and np.allclose(w2, w - gdt * gw)
+    u3, v3, w3, phi3 = PJ.project(prob, u2, v2, w2, gdt)
+    assert np.abs(phi3).max() < 1e-9 * np.abs(phi).max()
+    assert np.allclose(u3, u2, atol=1e-9 * np.abs(u2).max())
