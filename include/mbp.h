@@ -304,6 +304,41 @@ int mbp_inverse_transform(mbp_plan* plan, const double* phat_dev, double* p_dev,
 int mbp_apply_operator(mbp_plan* plan, const double* p_dev, double* out_dev, void* stream);
 int mbp_modal_shift(const mbp_plan* plan, double* shift_host);
 
+/* ---- pressure projection (Eqs. (3)-(6)) --------------------------------- */
+/* The steps on either side of the Poisson solve in the paper's fractional
+ * step, on the staggered grid (Sec. 2: velocities on cell faces):
+ *     rhs = D u* / (gamma dt),  L_h Phi = rhs,  u = u* - gamma dt G Phi,
+ * after which D u = 0 to the solver's tolerance (the check of Sec. 4.1).  D
+ * is the finite-volume divergence, G the face gradient, D G = L_h: a Neumann
+ * face (prescribed normal velocity) keeps its velocity, a Dirichlet face
+ * (prescribed pressure) sees the mirrored ghost -Phi, joined and periodic
+ * faces couple the partner's cell.
+ * Face fields are packed float64 device buffers, block after block in plan
+ * order: u (nz, ny, nx + 1), v (nz, ny + 1, nx), w (nz, ny, nx) when z is
+ * periodic (face k - 1/2, cyclic) and (nz + 1, ny, nx) otherwise.  A face
+ * shared by two joined blocks is stored in both (the caller keeps the two
+ * copies equal; the update keeps them equal).
+ *   mbp_velocity_layout: element offsets of each block in u, v, w (nblocks +
+ *     1 int64 each; any may be NULL).
+ *   mbp_divergence: out_dev (a packed cell field) = scale * D(u, v, w).
+ *     Stream-ordered and asynchronous.
+ *   mbp_project: one projection: rhs_work_dev (a cell field, caller-owned
+ *     scratch) = D u / gamma_dt, Phi solved into phi_dev as mbp_solve does
+ *     (flags as there, MBP_PROJECT_RHS implied: a singular problem whose net
+ *     boundary flux is not zero is projected; MBP_WARM_START starts from the
+ *     previous Phi, as the paper's time loop does), then u, v, w -= gamma_dt G
+ *     Phi in place.  Returns the solve's status (info as mbp_solve's); the
+ *     velocity is corrected also when the solve stops at max_cycles.
+ *     Errors: MBP_ERR_INVALID (NULL pointer, gamma_dt <= 0, rtol <= 0,
+ *     phi_dev == rhs_work_dev, wrong device), MBP_ERR_BUSY, MBP_ERR_HIP and
+ *     the solve's codes. */
+int mbp_velocity_layout(const mbp_plan* plan, int64_t* u_off, int64_t* v_off, int64_t* w_off);
+int mbp_divergence(mbp_plan* plan, const double* u_dev, const double* v_dev, const double* w_dev,
+                   double scale, double* out_dev, void* stream);
+int mbp_project(mbp_plan* plan, double* u_dev, double* v_dev, double* w_dev, double gamma_dt,
+                double* phi_dev, double* rhs_work_dev, double rtol, int flags, void* stream,
+                mbp_solve_info* info);
+
 /* Kernel timing for roofline reports.  While enabled, the finest-level
  * fused smoothing launches of every solve on the plan are bracketed by HIP
  * events on the solve's stream.  mbp_profile_read waits for those events and

@@ -88,6 +88,9 @@ def _load():
         "mbp_inverse_transform": (I, [P, VP, VP, VP]),
         "mbp_apply_operator": (I, [P, VP, VP, VP]),
         "mbp_residual_norm": (I, [P, VP, VP, D, VP, VP]),
+        "mbp_velocity_layout": (I, [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+        "mbp_divergence": (I, [P, VP, VP, VP, D, VP, VP]),
+        "mbp_project": (I, [P, VP, VP, VP, D, VP, VP, D, I, VP, C.POINTER(SolveInfo)]),
         "mbp_residual_norm_noalloc": (I, [P, VP, VP, D, VP, VP]),
         "mbp_noalloc_scratch_bytes": (C.c_size_t, []),
         "mbp_modal_shift": (I, [P, C.POINTER(D)]),
@@ -121,7 +124,7 @@ EXPORTED = [
     "mbp_status_string", "mbp_version", "mbp_grid_tanh", "mbp_plan_check", "mbp_plan_create",
     "mbp_plan_layout", "mbp_solve", "mbp_solve_batch", "mbp_forward_transform",
     "mbp_inverse_transform", "mbp_apply_operator", "mbp_residual_norm", "mbp_residual_norm_noalloc",
-    "mbp_noalloc_scratch_bytes", "mbp_modal_shift", "mbp_plan_destroy",
+    "mbp_noalloc_scratch_bytes", "mbp_velocity_layout", "mbp_divergence", "mbp_project", "mbp_modal_shift", "mbp_plan_destroy",
     "mbp_server_create", "mbp_server_submit", "mbp_server_poll", "mbp_server_wait",
     "mbp_server_destroy", "mbp_profile_enable", "mbp_profile_read", "mbp_batch_schedule",
     "mbp_plan_autotune", "mbp_plan_set_helmholtz",
@@ -299,6 +302,32 @@ class Plan:
         _check(lib.mbp_residual_norm(self._h, _ptr(rhs, self.ncells), _ptr(p, self.ncells), float(rhs_shift),
                                      _ptr(out, 2), _stream(stream)), "mbp_residual_norm")
         return out
+
+    def velocity_sizes(self):
+        """Element counts of the packed face fields u, v, w."""
+        nb = self._desc.nblocks
+        uo, vo, wo = (C.c_int64 * (nb + 1))(), (C.c_int64 * (nb + 1))(), (C.c_int64 * (nb + 1))()
+        _check(lib.mbp_velocity_layout(self._h, uo, vo, wo), "mbp_velocity_layout")
+        return uo[nb], vo[nb], wo[nb]
+
+    def divergence(self, u, v, w, out, scale=1.0, stream=None):
+        nu, nv, nw = self.velocity_sizes()
+        _check(lib.mbp_divergence(self._h, _ptr(u, nu), _ptr(v, nv), _ptr(w, nw), float(scale),
+                                  _ptr(out, self.ncells), _stream(stream)), "mbp_divergence")
+
+    def project(self, u, v, w, gamma_dt, phi, work, rtol=1e-10, flags=0, stream=None, raise_on_error=True) -> Info:
+        """u, v, w -= gamma_dt G Phi with L_h Phi = D u / gamma_dt (in place)."""
+        nu, nv, nw = self.velocity_sizes()
+        cpm = np.zeros(self.nz, dtype=np.int32)
+        si = SolveInfo()
+        si.cycles_per_mode = cpm.ctypes.data_as(C.POINTER(C.c_int32))
+        st = lib.mbp_project(self._h, _ptr(u, nu), _ptr(v, nv), _ptr(w, nw), float(gamma_dt),
+                             _ptr(phi, self.ncells), _ptr(work, self.ncells), float(rtol), int(flags),
+                             _stream(stream), C.byref(si))
+        if raise_on_error and st != OK:
+            raise MBPError(st, "mbp_project")
+        si.status = st if si.status == 0 else si.status
+        return Info(si, cpm)
 
     def modal_shift(self) -> np.ndarray:
         out = np.empty(self.nz, dtype=np.float64)

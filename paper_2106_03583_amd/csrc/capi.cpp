@@ -189,6 +189,36 @@ int mbp_residual_norm(mbp_plan* plan, const double* rhs_dev, const double* p_dev
     return hipGetLastError() == hipSuccess ? MBP_OK : MBP_ERR_HIP;
 }
 
+int mbp_velocity_layout(const mbp_plan* plan, int64_t* u_off, int64_t* v_off, int64_t* w_off) {
+    if (!plan) return MBP_ERR_INVALID;
+    velocity_offsets(plan, u_off, v_off, w_off);
+    return MBP_OK;
+}
+
+int mbp_divergence(mbp_plan* plan, const double* u_dev, const double* v_dev, const double* w_dev, double scale,
+                   double* out_dev, void* stream) {
+    if (!plan || !u_dev || !v_dev || !w_dev || !out_dev) return MBP_ERR_INVALID;
+    launch_divergence(plan, u_dev, v_dev, w_dev, scale, out_dev, static_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? MBP_OK : MBP_ERR_HIP;
+}
+
+int mbp_project(mbp_plan* plan, double* u_dev, double* v_dev, double* w_dev, double gamma_dt, double* phi_dev,
+                double* rhs_work_dev, double rtol, int flags, void* stream, mbp_solve_info* info) {
+    if (!plan || !u_dev || !v_dev || !w_dev || !phi_dev || !rhs_work_dev || !(gamma_dt > 0.0) ||
+        !std::isfinite(gamma_dt) || !(rtol > 0.0) || phi_dev == rhs_work_dev)
+        return MBP_ERR_INVALID;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) return MBP_ERR_INVALID;
+    if (!plan->busy.claim()) return MBP_ERR_BUSY;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    launch_divergence(plan, u_dev, v_dev, w_dev, 1.0 / gamma_dt, rhs_work_dev, s);
+    int st = solve_one(plan, rhs_work_dev, phi_dev, rtol, flags | plan->opt.flags | MBP_PROJECT_RHS, s, info);
+    if (st == MBP_OK || st == MBP_ERR_NOT_CONVERGED) launch_gradient_update(plan, phi_dev, gamma_dt, u_dev, v_dev, w_dev, s);
+    plan->busy.release();
+    if (hipGetLastError() != hipSuccess) return MBP_ERR_HIP;
+    return st;
+}
+
 int mbp_modal_shift(const mbp_plan* plan, double* shift_host) {
     if (!plan || !shift_host) return MBP_ERR_INVALID;
     std::memcpy(shift_host, plan->shift.data(), plan->shift.size() * sizeof(double));

@@ -125,6 +125,7 @@ struct mbp_plan {
     void* d_ftiles_inv = nullptr;
     int64_t lds_limit = 64 * 1024;  // LDS bytes one workgroup may use
     int lvinfo = 0;               // int-pool offset: per level {plane, blk_off, tile_off, ntiles}
+    int proj_tab = 0;             // int-pool offset: per block {dcx, dcy, gx, gy, rows before, columns before}
     std::vector<int> mtile_off, mtile_cnt;  // fused-sweep strips per level (LDS strip form)
     std::vector<int> rtile_off, rtile_cnt;  // taller strips of the register-march form
     std::vector<char> use_rmarch;           // level runs its pre-smoothing as a register march
@@ -212,6 +213,12 @@ void launch_forward(const mbp_plan* P, const double* f, double* fhat, int* nonfi
                     hipStream_t s);
 void launch_inverse(const mbp_plan* P, const double* phat, double* p, hipStream_t s);
 void launch_apply3d(const mbp_plan* P, const double* p, double* out, hipStream_t s);
+// project.hip: staggered velocities (packed face fields) and the projection
+void velocity_offsets(const mbp_plan* P, int64_t* uo, int64_t* vo, int64_t* wo);
+void launch_divergence(const mbp_plan* P, const double* u, const double* v, const double* w, double scale,
+                       double* out, hipStream_t s);
+void launch_gradient_update(const mbp_plan* P, const double* phi, double gdt, double* u, double* v, double* w,
+                            hipStream_t s);
 // Final check: out[0] = ||f - shift - (L_h - alpha) p||_2, out[1] = ||f - shift||_2
 // (device doubles), per-workgroup partials in part (resnorm_scratch_doubles).
 size_t resnorm_scratch_doubles(const mbp_plan* P);

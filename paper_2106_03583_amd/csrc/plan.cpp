@@ -691,6 +691,47 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
         P->lvinfo = push_i(li);
     }
 
+    // ---- projection tables of the finest level (staggered velocities on the
+    //      faces): per block {dcx, dcy, gx, gy offsets, rows and columns of
+    //      the blocks before it}; gx / gy hold 1 / (centre distance) per face
+    //      (walls: 0 for Neumann, 1 / dc for Dirichlet with the mirrored
+    //      ghost -p, joined faces 2 / (dc + dc_partner)) ----
+    {
+        std::vector<int> pt;
+        int cny = 0, cnx = 0;
+        const Level& L = P->levels[0];
+        for (int b = 0; b < nb; ++b) {
+            int offs[4];
+            for (int axis = 0; axis < 2; ++axis) {
+                const std::vector<double>& F = axis == 0 ? L.xf[b] : L.yf[b];
+                const int n = int(F.size()) - 1;
+                std::vector<double> dc(n), gf(n + 1, 0.0);
+                for (int i = 0; i < n; ++i) dc[i] = F[i + 1] - F[i];
+                for (int i = 1; i < n; ++i) gf[i] = 1.0 / (0.5 * (F[i + 1] + F[i]) - 0.5 * (F[i] + F[i - 1]));
+                const int fm = axis == 0 ? XM : YM, fp = axis == 0 ? XP : YP;
+                for (int side = 0; side < 2; ++side) {
+                    const int f = side == 0 ? fm : fp;
+                    const int at = side == 0 ? 0 : n;
+                    const double dc0 = side == 0 ? dc[0] : dc[n - 1];
+                    const int k = g.nbr[b][f];
+                    if (k >= 0) {
+                        const std::vector<double>& Fk = axis == 0 ? L.xf[k] : L.yf[k];
+                        const double dk = side == 0 ? Fk[Fk.size() - 1] - Fk[Fk.size() - 2] : Fk[1] - Fk[0];
+                        gf[at] = 1.0 / (0.5 * (dc0 + dk));
+                    } else {
+                        gf[at] = g.bc[b][f] == MBP_DIRICHLET ? 1.0 / dc0 : 0.0;
+                    }
+                }
+                offs[axis] = push_d(dc);
+                offs[2 + axis] = push_d(gf);
+            }
+            pt.insert(pt.end(), {offs[0], offs[1], offs[2], offs[3], cny, cnx});
+            cny += L.ny[b];
+            cnx += L.nx[b];
+        }
+        P->proj_tab = push_i(pt);
+    }
+
     // ---- z transform tables (twiddles in extended precision) ----
     P->fft.n = nz;
     P->fft.m = nz / 2;
