@@ -135,6 +135,9 @@ int mg3_create(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* 
             L.xyc = hier[l + 1].first != L.xl ? 1 : 0;
             L.zc = hier[l + 1].second != L.nz ? 1 : 0;
         }
+        L.even_xy = 1;
+        for (int b = 0; b < X2.nb; ++b)
+            if ((X2.nx[b] & 1) || (X2.ny[b] & 1)) L.even_xy = 0;
     }
     return MBP_OK;
 }

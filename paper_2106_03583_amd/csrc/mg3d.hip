@@ -189,12 +189,26 @@ __device__ __forceinline__ int zplane(const Op3& o, int k) {
 
 }  // namespace
 
-template <bool NORM>
+// The coarse level a restricting march writes to.
+struct Rst3 {
+    const DBlock* Bc;
+    int nzc;
+    double* fc;
+};
+
+// MODE 0: the sweep; 1: the sweep and the partial sums of NORM above; 2: no
+// sweep, the residual restricted to the next level instead (x-y and z both
+// coarsened, even x-y block sizes: children 2I, 2I + 1 of coarse cell I lie
+// in the same tile; the pair of planes 2K, 2K + 1 is summed in registers,
+// the 2 x 2 x-y children through LDS).
+template <int MODE>
 __global__ void __launch_bounds__(256)
 k3_jacobi_zm(Op3 o, const int4* __restrict__ tiles, int ntiles, const double* __restrict__ pin,
              double* __restrict__ pout, const double* __restrict__ f, double fshift, double omega,
-             double* __restrict__ part) {
+             double* __restrict__ part, Rst3 rs) {
+    constexpr bool NORM = MODE == 1;
     __shared__ double sp[kTileY + 2][kTileX + 2];
+    __shared__ double sr[MODE == 2 ? kTileY : 1][MODE == 2 ? kTileX : 1];
     const int4 t = tiles[xcd_remap3(blockIdx.x, ntiles)];
     const DBlock b = o.B[t.x];
     const int k0 = blockIdx.y * kZChunk;
@@ -236,6 +250,15 @@ k3_jacobi_zm(Op3 o, const int4* __restrict__ tiles, int ntiles, const double* __
     load(k0 + 1, pp);
     loadf(k0, fc);
     double acc = 0.0, accp = 0.0;
+    double racc[R], rw[R];
+    if (MODE == 2) {
+        const double wx = in_i ? dp[b.rwx + i] : 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            racc[r] = 0.0;
+            rw[r] = act[r] ? 0.5 * wx * dp[b.rwy + j[r]] : 0.0;  // volume fraction: x, y and the z pair
+        }
+    }
     for (int k = k0; k < k1; ++k) {
         if (k + 1 < k1) {  // next plane's loads in flight during this plane's work
             load(k + 2, pn);
@@ -271,9 +294,25 @@ k3_jacobi_zm(Op3 o, const int4* __restrict__ tiles, int ntiles, const double* __
                 acc += res * res;
                 accp += pc[r] * pc[r];
             }
-            pout[base + k * kz + (long long)j[r] * b.nx + i] = pc[r] + omega * res / d;
+            if (MODE == 2) racc[r] += rw[r] * res;
+            else pout[base + k * kz + (long long)j[r] * b.nx + i] = pc[r] + omega * res / d;
         }
         __syncthreads();
+        if (MODE == 2 && (k & 1)) {  // planes 2K, 2K + 1 done: sum the x-y children
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                sr[ty + kRowsPerPass * r][tx] = racc[r];
+                racc[r] = 0.0;
+            }
+            __syncthreads();
+            const int ci = tid % (kTileX / 2), cj = tid / (kTileX / 2);  // 32 x 8 coarse cells
+            const DBlock bc = rs.Bc[t.x];
+            const int I = t.y / 2 + ci, J = t.z / 2 + cj;
+            if (I < bc.nx && J < bc.ny)
+                rs.fc[cell3(bc, rs.nzc, k >> 1, J, I)] = sr[2 * cj][2 * ci] + sr[2 * cj][2 * ci + 1] +
+                                                         sr[2 * cj + 1][2 * ci] + sr[2 * cj + 1][2 * ci + 1];
+            __syncthreads();
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             pm[r] = pc[r];
@@ -416,6 +455,101 @@ k3_prolong(const DBlock* __restrict__ Bf, const DBlock* __restrict__ Bc, const i
 }
 
 // ---------------------------------------------------------------------------
+// The same correction when both x-y and z coarsen, marching along z: a
+// workgroup owns one 64 x 16 fine tile and kPZChunk fine planes (pairs 2K,
+// 2K+1).  Each coarse plane the chunk needs is staged once into LDS (the
+// tile's coarse cells and their ring, through cvalue), and its bilinear
+// interpolant at the thread's four cells kept in registers; fine plane 2K
+// takes 1/4 of plane K-1 and 3/4 of plane K, plane 2K+1 3/4 of K and 1/4 of
+// K+1 (mirror or wrap beyond the z ends).
+// ---------------------------------------------------------------------------
+constexpr int kPZChunk = 16;             // fine planes per workgroup (even)
+constexpr int kPX = kTileX / 2 + 4;      // staged coarse columns (with ring and merge slack)
+constexpr int kPY = kTileY / 2 + 4;      // staged coarse rows
+
+__global__ void __launch_bounds__(256)
+k3_prolong_zm(const DBlock* __restrict__ Bf, const DBlock* __restrict__ Bc, const int4* __restrict__ tiles_f,
+              int ntiles_f, int nzf, int nzc, const double* __restrict__ dp, const int* __restrict__ ip,
+              const double* __restrict__ pc, double* __restrict__ pf, int zlo, int zhi) {
+    __shared__ double sc[kPY][kPX];
+    const int4 t = tiles_f[xcd_remap3(blockIdx.x, ntiles_f)];
+    const DBlock bf = Bf[t.x];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * kTileX + tx;
+    const int i = t.y + tx;
+    const bool in_i = i < bf.nx;
+    // coarse range of the tile (the lower-neighbour tables are monotone)
+    const int ilast = min(t.y + kTileX - 1, bf.nx - 1), jlast = min(t.z + kTileY - 1, bf.ny - 1);
+    const int cx0 = ip[bf.pcx + t.y], cy0 = ip[bf.pcy + t.z];
+    const int ncx = ip[bf.pcx + ilast] + 2 - cx0, ncy = ip[bf.pcy + jlast] + 2 - cy0;
+    constexpr int R = kTileY / kRowsPerPass;
+    int lx = 0;
+    double wx = 0.0;
+    if (in_i) {
+        lx = ip[bf.pcx + i] - cx0;
+        wx = dp[bf.pwx + i];
+    }
+    int ly[R];
+    double wy[R];
+    bool act[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = t.z + ty + kRowsPerPass * r;
+        act[r] = in_i && j < bf.ny;
+        ly[r] = act[r] ? ip[bf.pcy + j] - cy0 : 0;
+        wy[r] = act[r] ? dp[bf.pwy + j] : 0.0;
+    }
+    // bilinear values of coarse plane K (inside [0, nzc)) at the thread's cells
+    auto interp = [&](int K, double* e) {
+        __syncthreads();
+        for (int q = tid; q < ncx * ncy; q += kTileX * kRowsPerPass) {
+            const int a = q % ncx, b = q / ncx;
+            sc[b][a] = cvalue(pc, Bc, nzc, t.x, cx0 + a, cy0 + b, K);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!act[r]) {
+                e[r] = 0.0;
+                continue;
+            }
+            const double e00 = sc[ly[r]][lx], e10 = sc[ly[r]][lx + 1];
+            const double e01 = sc[ly[r] + 1][lx], e11 = sc[ly[r] + 1][lx + 1];
+            e[r] = wy[r] * (wx * e00 + (1.0 - wx) * e10) + (1.0 - wy[r]) * (wx * e01 + (1.0 - wx) * e11);
+        }
+    };
+    // beyond a non-periodic z end the coarse ghost is the end plane mirrored
+    // (Neumann +, Dirichlet -)
+    const double slo = zlo == MBP_DIRICHLET ? -1.0 : 1.0, shi = zhi == MBP_DIRICHLET ? -1.0 : 1.0;
+    const bool per = zlo == MBP_PERIODIC;
+    const int K0 = blockIdx.y * (kPZChunk / 2);
+    const long long base = (long long)nzf * bf.off, kz = (long long)bf.nx * bf.ny;
+    double em[R], ec[R], ep[R];
+    interp(K0, ec);
+    if (K0 > 0 || per) interp((K0 - 1 + nzc) % nzc, em);
+    else
+#pragma unroll
+        for (int r = 0; r < R; ++r) em[r] = slo * ec[r];
+    for (int K = K0; K < K0 + kPZChunk / 2; ++K) {
+        if (K + 1 < nzc || per) interp((K + 1) % nzc, ep);
+        else
+#pragma unroll
+            for (int r = 0; r < R; ++r) ep[r] = shi * ec[r];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!act[r]) continue;
+            const long long c = base + ((long long)t.z + ty + kRowsPerPass * r) * bf.nx + i;
+            pf[c + (2 * K) * kz] += 0.25 * em[r] + 0.75 * ec[r];
+            pf[c + (2 * K + 1) * kz] += 0.75 * ec[r] + 0.25 * ep[r];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            em[r] = ec[r];
+            ec[r] = ep[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Exact coarsest solve by separation.  Stage 1, one workgroup per z mode m:
 // fz = sum_k V[k][m] f_k (z eigenvectors), then the x-y solve
 // x_m = WL diag(1 / (mu + muz_m - alpha)) WR fz, with the null mode dropped.
@@ -544,9 +678,11 @@ long long m3_jacobi(const Mg3Plan& M, int l, const double* pin, double* pout, co
         return (long long)L.ntiles * L.nz;
     }
     const dim3 g(unsigned(L.ntiles), unsigned((L.nz + kZChunk - 1) / kZChunk));
-    if (part) hipLaunchKernelGGL(k3_jacobi_zm<true>, g, kBlk, 0, s, o, tl, L.ntiles, pin, pout, f, fshift, M.omega,
-                                 part);
-    else hipLaunchKernelGGL(k3_jacobi_zm<false>, g, kBlk, 0, s, o, tl, L.ntiles, pin, pout, f, fshift, M.omega, part);
+    const Rst3 none{nullptr, 0, nullptr};
+    if (part) hipLaunchKernelGGL(k3_jacobi_zm<1>, g, kBlk, 0, s, o, tl, L.ntiles, pin, pout, f, fshift, M.omega,
+                                 part, none);
+    else hipLaunchKernelGGL(k3_jacobi_zm<0>, g, kBlk, 0, s, o, tl, L.ntiles, pin, pout, f, fshift, M.omega, part,
+                            none);
     return (long long)g.x * g.y;
 }
 
@@ -573,8 +709,15 @@ void m3_total(const double* part, long long n, double scale, double* out, hipStr
 
 void m3_restrict(const Mg3Plan& M, int l, const double* p, const double* f, double fshift, double* fc,
                  hipStream_t s) {
+    const Mg3Level& F = M.lev[l];
     const Mg3Level& C = M.lev[l + 1];
     const Op3 o = op_of(M, l);
+    if (F.xyc && F.zc && F.even_xy && F.nz % kZChunk == 0) {  // marching form
+        const dim3 g(unsigned(F.ntiles), unsigned(F.nz / kZChunk));
+        hipLaunchKernelGGL(k3_jacobi_zm<2>, g, kBlk, 0, s, o, M.d_tiles + F.tile_off, F.ntiles, p, nullptr, f, fshift,
+                           M.omega, nullptr, Rst3{M.d_blk + C.blk_off, C.nz, fc});
+        return;
+    }
     hipLaunchKernelGGL(k3_restrict, grid_of(C), kBlk, 0, s, o, M.d_blk + C.blk_off, M.d_tiles + C.tile_off, C.ntiles,
                        C.nz, M.d_int, p, f, fshift, fc, M.lev[l].xyc, M.lev[l].zc);
 }
@@ -582,6 +725,12 @@ void m3_restrict(const Mg3Plan& M, int l, const double* p, const double* f, doub
 void m3_prolong(const Mg3Plan& M, int l, const double* pc, double* pf, hipStream_t s) {
     const Mg3Level& F = M.lev[l];
     const Mg3Level& C = M.lev[l + 1];
+    if (F.xyc && F.zc && F.nz % kPZChunk == 0) {
+        const dim3 g(unsigned(F.ntiles), unsigned(F.nz / kPZChunk));
+        hipLaunchKernelGGL(k3_prolong_zm, g, kBlk, 0, s, M.d_blk + F.blk_off, M.d_blk + C.blk_off,
+                           M.d_tiles + F.tile_off, F.ntiles, F.nz, C.nz, M.d_dbl, M.d_int, pc, pf, M.zlo, M.zhi);
+        return;
+    }
     hipLaunchKernelGGL(k3_prolong, grid_of(F), kBlk, 0, s, M.d_blk + F.blk_off, M.d_blk + C.blk_off,
                        M.d_tiles + F.tile_off, F.ntiles, F.nz, C.nz, M.d_dbl, M.d_int, pc, pf, F.xyc, F.zc,
                        M.zlo, M.zhi);

@@ -99,6 +99,7 @@ def _small():
         out.append(W.box(40, 36, 12, 40 / 64, 36 / 64, 12 / 64, xp, yp, zk, xfactor=1.3, yfactor=1.1,
                          name=f"box40x36x12_{xp}{yp}{zk}"))
     out.append(W.box(70, 52, 10, 70 / 64, 52 / 64, 10 / 64, "NN", "PP", "NN", name="box70x52x10_odd"))
+    out.append(W.box(15, 12, 8, 15 / 16, 12 / 16, 0.5, "PP", "NN", "PP", name="box15x12_oddring_x"))
     return out
 
 
@@ -106,6 +107,16 @@ def _small():
 def test_mg3d_small(torch_cuda, mbp, prob):
     print(f"mg3d small {prob.name}", flush=True)
     f = W.rhs(prob, 62)
+    _run(torch_cuda, mbp, prob, f, oracle.solve(prob, f))
+
+
+@pytest.mark.parametrize("zk", KINDS)
+def test_mg3d_z_marching_transfers(torch_cuda, mbp, zk):
+    """Isotropic boxes (x-y and z coarsen together over several levels, with
+    32 and 64 z cells) run the z-marching prolongation; every z pair."""
+    prob = W.box(64, 48, 32, 1.0, 0.75, 0.5, "DN", "PP", zk, xfactor=1.2, name=f"box64x48x32_{zk}")
+    print(f"mg3d z-march {prob.name}", flush=True)
+    f = W.rhs(prob, 66)
     _run(torch_cuda, mbp, prob, f, oracle.solve(prob, f))
 
 
