@@ -219,6 +219,49 @@ __device__ void stage(double2* z, int cs, int m, int W, int Ns, const double* __
     __syncthreads();
 }
 
+// One Stockham stage of any radix R (a prime above 31, for which no
+// unrolled butterfly exists): each output of butterfly (j = jn Ns + k) is
+// y_s = sum_r z[j + r m/R] w^{r (k + s Ns) m / (Ns R)}, w = e^{-2 pi i / m},
+// computed straight from LDS (R complex products per output).  The host
+// keeps W m <= MAXOUT * blockDim.x.
+template <int MAXOUT>
+__device__ void stage_generic(double2* z, int cs, int m, int W, int Ns, int R, const double* __restrict__ tw) {
+    const int nbf = m / R;
+    const int step = m / (Ns * R);
+    const int total = W * m;
+    double2 y[MAXOUT];
+    int dst[MAXOUT];
+#pragma unroll
+    for (int t = 0; t < MAXOUT; ++t) {
+        const int o = threadIdx.x + t * blockDim.x;
+        dst[t] = -1;
+        if (o >= total) continue;
+        const int w = o / m, rest = o - w * m;
+        const int s = rest / nbf, j = rest - s * nbf;
+        const int jn = j / Ns, k = j - jn * Ns;
+        const double2* col = z + w * cs;
+        const int inc = int(((long long)(k + s * Ns) * step) % m);
+        int ti = 0;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int r = 0; r < R; ++r) {
+            const double2 pr = cmul(col[j + r * nbf], ld2(tw, ti));
+            acc.x += pr.x;
+            acc.y += pr.y;
+            ti += inc;
+            if (ti >= m) ti -= m;
+        }
+        y[t] = acc;
+        dst[t] = w * cs + jn * Ns * R + k + s * Ns;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < MAXOUT; ++t)
+        if (dst[t] >= 0) z[dst[t]] = y[t];
+    __syncthreads();
+}
+
+constexpr int kGenericOut = 16;  // outputs per thread of the any-radix stage
+
 template <int R>
 __device__ void stage_dispatch(double2* z, int cs, int m, int W, int Ns, const double* tw) {
     const int total = W * (m / R);
@@ -237,8 +280,9 @@ __device__ void stage_dispatch(double2* z, int cs, int m, int W, int Ns, const d
 }
 
 // Radix classes: 0 = powers of two only, 1 = with 3 / 5 / 7, 2 = any prime
-// up to 31.  Each class is its own kernel so the power-of-two transforms do
-// not carry the register footprint of the long odd butterflies.
+// up to 31, 3 = also primes above 31 (the any-radix stage).  Each class is
+// its own kernel so the power-of-two transforms do not carry the register
+// footprint of the long odd butterflies.
 template <int CLASS>
 __device__ void fft_columns(double2* z, int cs, const FFTArgs& a) {
     int Ns = 1;
@@ -264,7 +308,10 @@ __device__ void fft_columns(double2* z, int cs, const FFTArgs& a) {
                                     case 23: stage_dispatch<23>(z, cs, a.m, a.W, Ns, a.tw); break;
                                     case 29: stage_dispatch<29>(z, cs, a.m, a.W, Ns, a.tw); break;
                                     case 31: stage_dispatch<31>(z, cs, a.m, a.W, Ns, a.tw); break;
-                                    default: break;  // rejected on the host
+                                    default:
+                                        if constexpr (CLASS >= 3)
+                                            stage_generic<kGenericOut>(z, cs, a.m, a.W, Ns, R, a.tw);
+                                        break;
                                 }
                             }
                             break;
@@ -503,6 +550,8 @@ static int fft_width_for(const mbp_plan* P, int64_t lds) {
     for (int R : P->fft.radices) {
         const int per = R > 8 ? 1 : (R == 2 ? 8 : R == 4 ? 4 : 2);  // butterflies per thread
         while (W > 1 && W * (m / R) > per * 256) W >>= 1;
+        if (R > 31)  // the any-radix stage holds W m / 256 outputs per thread
+            while (W > 1 && W * m > kGenericOut * 256) W >>= 1;
     }
     return W;
 }
@@ -575,7 +624,8 @@ static int radix_class(const mbp_plan* P) {
     int c = 0;
     for (int R : P->fft.radices) {
         if (R == 3 || R == 5 || R == 7) c = std::max(c, 1);
-        else if (R > 8) c = 2;
+        else if (R > 31) c = 3;
+        else if (R > 8) c = std::max(c, 2);
     }
     return c;
 }
@@ -597,7 +647,8 @@ static void run_r2r(const mbp_plan* P, const void* tiles, int dir, const double*
     switch (radix_class(P)) {
         case 0: launch_r2r<0>(P, a, tiles, dir, in, out, nonfinite, s); break;
         case 1: launch_r2r<1>(P, a, tiles, dir, in, out, nonfinite, s); break;
-        default: launch_r2r<2>(P, a, tiles, dir, in, out, nonfinite, s); break;
+        case 2: launch_r2r<2>(P, a, tiles, dir, in, out, nonfinite, s); break;
+        default: launch_r2r<3>(P, a, tiles, dir, in, out, nonfinite, s); break;
     }
 }
 

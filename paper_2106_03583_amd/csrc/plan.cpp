@@ -103,8 +103,6 @@ bool validate(const mbp_block_desc* blocks, int nb, const mbp_synth_desc* z, Geo
         g.ny[i] = int(ny);
         if (!increasing(b.xf, int(nx) + 1) || !increasing(b.yf, int(ny) + 1))
             return fail(err, "face coordinates must be finite and increasing");
-        if ((b.bc[XM] == MBP_PERIODIC && (nx & 1)) || (b.bc[YM] == MBP_PERIODIC && (ny & 1)))
-            return fail(err, "a periodic direction needs an even cell count");
         g.xf[i].assign(b.xf, b.xf + nx + 1);
         g.yf[i].assign(b.yf, b.yf + ny + 1);
         for (int f = 0; f < 4; ++f) {
@@ -736,11 +734,7 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
     P->fft.n = nz;
     P->fft.m = nz / 2;
     P->fft.radices = fft_radices(P->fft.m);
-    for (int R : P->fft.radices)
-        if (R > 31 || R == 9) {
-            if (err) *err = "nz/2 has a prime factor above 31";
-            return MBP_ERR_INVALID;
-        }
+
     {
         const long double PI = 3.14159265358979323846264338327950288L;
         const int n = nz, m = nz / 2;

@@ -48,12 +48,14 @@ def two_block(nz, zpair, nx1=12, nx2=7, ny=9):
     return W.Problem([A, B], nz, 1.3, W.PAIRS[zpair], name=f"two_block_{zpair}_{nz}")
 
 
-# nz covers every radix (2..31 through n/2 = 1..31), and the workgroup shapes
+# nz covers every radix (2..31 through n/2 = 1..31, and the any-radix stage
+# for the primes 37, 83 and 509 of n/2 = 37, 74, 83, 509), and the workgroup shapes
 # of the power-of-two lengths: 64-column tiles (32, 64), 16 columns with four
 # radix-2 butterflies per thread (256), 8 columns in 80 KB (512, 1024), and
 # 4 columns with eight radix-2 butterflies per thread (2048).
 @pytest.mark.parametrize("kind", KINDS)
-@pytest.mark.parametrize("nz", [2, 4, 6, 8, 10, 14, 22, 26, 32, 48, 62, 64, 96, 160, 256, 512, 1024, 2048])
+@pytest.mark.parametrize("nz", [2, 4, 6, 8, 10, 14, 22, 26, 32, 48, 62, 64, 96, 160, 256, 512, 1024, 2048,
+                                74, 148, 166, 1018])
 def test_transforms(torch_cuda, mbp, kind, nz):
     torch = torch_cuda
     prob = two_block(nz, kind)
@@ -323,5 +325,47 @@ def test_obstacle8_small(torch_cuda, mbp, precision):
     res = oracle.rel_residual(prob, got, f)
     err = oracle.rel_error(got, ref)
     print(f"  obstacle8 {precision}: {info} residual={res:.2e} error={err:.2e}", flush=True)
+    assert info.status == 0 and res <= 1e-10 and err <= 1e-9
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("prob", [W.box(15, 12, 8, 15 / 16, 12 / 16, 0.5, "PP", "NN", "PP", name="box15x12_oddring_x"),
+                                  W.box(40, 27, 6, 40 / 32, 27 / 32, 0.25, "DN", "PP", "NN", xfactor=1.3,
+                                        name="box40x27_oddring_y")],
+                         ids=lambda p: p.name)
+def test_odd_periodic_finest_ring(torch_cuda, mbp, prob, precision):
+    """An odd number of cells around a periodic wrap on the finest grid: the
+    last column (row) takes the two extra smoothing colours."""
+    torch = torch_cuda
+    f = W.rhs(prob, 92)
+    ref = oracle.solve(prob, f)
+    fproj = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
+    plan = mbp.Plan(prob, precision=precision)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.PROJECT_RHS | mbp.RETIRE)
+    got = host(p)
+    res = oracle.rel_residual(prob, got, fproj)
+    err = oracle.rel_error(got, ref)
+    print(f"  {prob.name} {precision}: {info} residual={res:.2e} error={err:.2e}", flush=True)
+    assert info.status == 0 and res <= 1e-10 and err <= 1e-9
+    plan.close()
+
+
+@pytest.mark.parametrize("zk", ["PP", "NN", "DD", "ND", "DN"])
+def test_solve_prime_half_length(torch_cuda, mbp, zk):
+    """nz = 74: the half-length FFT of 37 points runs the any-radix stage."""
+    torch = torch_cuda
+    prob = two_block(74, zk)
+    f = W.rhs(prob, 93)
+    ref = oracle.solve(prob, f)
+    fproj = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
+    plan = mbp.Plan(prob)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.PROJECT_RHS | mbp.RETIRE)
+    got = host(p)
+    res = oracle.rel_residual(prob, got, fproj)
+    err = oracle.rel_error(got, ref)
+    print(f"  {prob.name}: {info} residual={res:.2e} error={err:.2e}", flush=True)
     assert info.status == 0 and res <= 1e-10 and err <= 1e-9
     plan.close()

@@ -91,10 +91,13 @@ def test_plan_check_rejects(mbp):
     lone = W.Problem([W.Block(b.lo, b.hi, b.xf, b.yf, (W.CONNECT, W.DIRICHLET, W.NEUMANN, W.NEUMANN))], 8, 0.5,
                      base.zbc)
     assert mbp.plan_check_status(lone) == mbp.ERR_INVALID
-    # an odd cell count around a periodic wrap of the finest grid is refused
-    # (red-black ordering needs an even ring; odd coarse rings are handled)
+    # an odd cell count around a periodic wrap is accepted (its last column
+    # is relaxed in two extra colours on every level)
     odd = W.box(15, 12, 8, 1.0, 0.75, 0.5, "PP", "NN", "PP")
-    assert mbp.plan_check_status(odd) == mbp.ERR_INVALID
+    assert mbp.plan_check_status(odd) == mbp.OK
+    # any even nz: a half length with a prime factor above 31 (37, 509) plans
+    assert mbp.plan_check_status(_with(base, nz=74)) == mbp.OK
+    assert mbp.plan_check_status(_with(base, nz=1018)) == mbp.OK
 
 
 def test_plan_check_rejects_overlap_and_nonconforming(mbp):
