@@ -121,6 +121,7 @@ struct mbp_plan {
     mbp::FFTPlan fft;
     int fft_tw = 0, fft_twn = 0, fft_post = 0, fft_pre4 = 0, fft_post4 = 0;  // double-pool offsets
     int fft_ntiles = 0;
+    int fft_stream_nt = 0, fft_grid = 0;  // streaming transform: threads per workgroup, grid (0 = per-tile kernel)
     void* d_ftiles_fwd = nullptr;
     void* d_ftiles_inv = nullptr;
     int64_t lds_limit = 64 * 1024;  // LDS bytes one workgroup may use
@@ -205,6 +206,7 @@ int grid_tanh(int n, double lmin, double lmax, int type, double factor, double* 
 // fft.hip (host helpers)
 int fft_columns_per_wg(const mbp_plan* P);
 int fft_col_stride(const mbp_plan* P);
+int fft_stream_setup(mbp_plan* P);
 void fft_build_tiles(const mbp_plan* P, std::vector<unsigned char>& fwd, std::vector<unsigned char>& inv,
                      int* ntiles);
 

@@ -137,6 +137,7 @@ size_t plan_device_bytes(const mbp_plan* P) {
 int plan_device_init(mbp_plan* P, void* ext_mem, size_t ext_bytes, void* ext_pinned) {
     std::vector<unsigned char> ftf, fti, mt;
     fft_build_tiles(P, ftf, fti, &P->fft_ntiles);
+    if (const int st = fft_stream_setup(P)) return st;
     plan_march_tables(P, mt);
     Layout L = layout(P, ftf.size(), mt.size(), partial_count(P));
     void* mem = ext_mem;

@@ -50,8 +50,8 @@ def two_block(nz, zpair, nx1=12, nx2=7, ny=9):
 
 # nz covers every radix (2..31 through n/2 = 1..31, and the any-radix stage
 # for the primes 37, 83 and 509 of n/2 = 37, 74, 83, 509), and the workgroup shapes
-# of the power-of-two lengths: 64-column tiles (32, 64), 16 columns with four
-# radix-2 butterflies per thread (256), 8 columns in 80 KB (512, 1024), and
+# of the power-of-two lengths: 64-column tiles of the per-tile kernel (32, 64),
+# the streaming kernel's 64-, 32- and 16-column tiles (256, 512, 1024), and
 # 4 columns with eight radix-2 butterflies per thread (2048).
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("nz", [2, 4, 6, 8, 10, 14, 22, 26, 32, 48, 62, 64, 96, 160, 256, 512, 1024, 2048,
@@ -77,6 +77,32 @@ def test_transforms(torch_cuda, mbp, kind, nz):
     phm = ph.reshape(nz, -1)
     expect = np.concatenate([(T @ phm[:, g.off2[i]:g.off2[i + 1]]).ravel() for i in range(g.nb)])
     assert np.abs(host(p) - expect).max() <= 1e-12 * np.abs(expect).max() * max(1.0, np.sqrt(nz))
+    plan.close()
+
+
+# The streaming kernel's workgroups loop over tiles: planes of 25,344 columns
+# give 396 to 1,584 tiles (several per workgroup), ragged at both blocks' ends.
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("nz", [256, 512, 1024])
+def test_transforms_streaming(torch_cuda, mbp, kind, nz):
+    torch = torch_cuda
+    prob = two_block(nz, kind, 161, 95, 99)
+    print(f"transform (streaming) {kind} nz={nz}", flush=True)
+    plan = mbp.Plan(prob)
+    g = oracle.Geometry(prob)
+    T = oracle.basis(kind, nz)
+    f = W.rhs(prob, 7 + nz)
+    fh = torch.empty(plan.ncells, dtype=torch.float64, device="cuda")
+    plan.forward(dev(torch, f), fh)
+    got = host(fh).reshape(nz, -1)
+    ref = oracle.modal_rhs(prob, f, range(nz))
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max() * np.sqrt(nz)
+    ph = np.random.default_rng(nz).standard_normal(plan.ncells)
+    p = torch.empty(plan.ncells, dtype=torch.float64, device="cuda")
+    plan.inverse(dev(torch, ph), p)
+    phm = ph.reshape(nz, -1)
+    expect = np.concatenate([(T @ phm[:, g.off2[i]:g.off2[i + 1]]).ravel() for i in range(g.nb)])
+    assert np.abs(host(p) - expect).max() <= 1e-12 * np.abs(expect).max() * np.sqrt(nz)
     plan.close()
 
 
