@@ -713,6 +713,7 @@ __global__ void __launch_bounds__(NT) k_r2r_stream(FFTArgs a, const FTile* __res
             t2[i] = ld2(a.post, i);
         }
     }
+    __syncthreads();  // the first tile's placement already reads the tables
 
     const int G = gridDim.x;
     int v = blockIdx.x;

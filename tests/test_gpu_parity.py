@@ -81,12 +81,18 @@ def test_transforms(torch_cuda, mbp, kind, nz):
 
 
 # The streaming kernel's workgroups loop over tiles: planes of 25,344 columns
-# give 396 to 1,584 tiles (several per workgroup), ragged at both blocks' ends.
+# give 396 to 1,584 tiles (several per workgroup), ragged at both blocks' ends;
+# a 64 x 192 box at nz = 256 gives 192 tiles, one per workgroup (each
+# workgroup's first tile reads the tables it has just staged in LDS).
 @pytest.mark.parametrize("kind", KINDS)
-@pytest.mark.parametrize("nz", [256, 512, 1024])
+@pytest.mark.parametrize("nz", [256, 512, 1024, "box256"])
 def test_transforms_streaming(torch_cuda, mbp, kind, nz):
     torch = torch_cuda
-    prob = two_block(nz, kind, 161, 95, 99)
+    if nz == "box256":
+        prob = W.box(64, 192, 256, 0.5, 1.5, 2.0, "DD", "DN", kind, name=f"box64x192x256_{kind}")
+        nz = 256
+    else:
+        prob = two_block(nz, kind, 161, 95, 99)
     print(f"transform (streaming) {kind} nz={nz}", flush=True)
     plan = mbp.Plan(prob)
     g = oracle.Geometry(prob)

@@ -143,4 +143,3 @@ def test_workload_generators():
     assert len(c5) == 50
     t = [r.arrival_s for r in c5]
     assert all(b >= a for a, b in zip(t, t[1:]))
-
