@@ -273,7 +273,7 @@ void launch_add_correction(const mbp_plan* P, double* p, const float* e32, const
                            const int* nact, int nitems, hipStream_t s);
 void launch_plane_norm(const mbp_plan* P, const double* f, double* out, hipStream_t s);
 void launch_update_active(const mbp_plan* P, double rtol2, double etol2, int retire, int maxc,
-                          hipStream_t s);
+                          hipStream_t s, double* out = nullptr);
 void launch_zero(double* p, size_t n, hipStream_t s);
 void launch_zero32(float* p, size_t n, hipStream_t s);
 void launch_singular_fix(const mbp_plan* P, double* plane, double* out_mean, hipStream_t s);
@@ -307,7 +307,8 @@ struct SolveCtx {
 void ctx_init(SolveCtx& c, mbp_plan* P, const double* rhs, double* p, double rtol, int flags);
 void ctx_prologue(SolveCtx& c, hipStream_t s);  // ends with an async readback of the checks
 void ctx_check(SolveCtx& c);                    // after that readback synchronised
-void ctx_test(SolveCtx& c, hipStream_t s);      // residual norms + convergence update
+void ctx_test(SolveCtx& c, hipStream_t s, double* state_out = nullptr);  // residual norms + convergence
+                                                                        // update (state copied to state_out)
 void ctx_vcycle(SolveCtx& c, hipStream_t s);    // one V-cycle of the active modes
 void ctx_state_readback(SolveCtx& c, hipStream_t s);
 void ctx_state_apply(SolveCtx& c);              // after that readback synchronised

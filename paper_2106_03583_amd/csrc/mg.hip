@@ -465,6 +465,7 @@ struct UpdJob {
     int* cyc;
     double* scal;
     int* state;
+    double* out;  // optional (host-visible): scal[0..1], state[0..3], nact after the update
 };
 
 __device__ __forceinline__ void update_body(const UpdJob& J) {
@@ -499,18 +500,36 @@ __device__ __forceinline__ void update_body(const UpdJob& J) {
     }
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
     if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = m;
+    // modes still to run, in list order: a ballot prefix per wave, the wave
+    // totals in LDS (retiring form: compacted into act, which every thread
+    // has finished reading at the barrier below)
+    __shared__ int wsum[16];
+    __shared__ int kept;
+    if (threadIdx.x == 0) kept = 0;
     __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = int(blockDim.x >> 6);
+    for (int r0 = 0; r0 < n; r0 += blockDim.x) {
+        const int it = r0 + threadIdx.x;
+        const bool k = it < n && keep[it] >= 0;
+        const unsigned long long mask = __ballot(k);
+        if (lane == 0) wsum[wv] = __popcll(mask);
+        __syncthreads();
+        int off = kept;
+        for (int v = 0; v < wv; ++v) off += wsum[v];
+        if (k && retire) act[off + __popcll(mask & ((1ull << lane) - 1))] = keep[it];
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int v = 0; v < nw; ++v) kept += wsum[v];
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
         double g = 0.0;
-        for (int w = 0; w < int(blockDim.x >> 6); ++w) g = fmax(g, mx[w]);
+        for (int w = 0; w < nw; ++w) g = fmax(g, mx[w]);
         scal[0] = g;
-        int c = 0;
+        int c = kept;
         if (!retire) {  // lockstep: done when every mode passes both tests
-            for (int it = 0; it < n; ++it) c += keep[it] >= 0 ? 1 : 0;
             scal[1] = double(c);
         } else {
-            for (int it = 0; it < n; ++it)
-                if (keep[it] >= 0) act[c++] = keep[it];
             if (stop && c > 0) {
                 state[2] = 1;
                 c = 0;
@@ -519,6 +538,13 @@ __device__ __forceinline__ void update_body(const UpdJob& J) {
         }
         if (stop && !retire && c > 0) state[2] = 1;
         state[1] = cycle + 1;
+        if (J.out) {
+            J.out[0] = scal[0];
+            J.out[1] = scal[1];
+            int* oi = reinterpret_cast<int*>(J.out + 2);
+            for (int i = 0; i < 4; ++i) oi[i] = state[i];
+            oi[4] = *nact;
+        }
     }
 }
 
@@ -1208,9 +1234,9 @@ void launch_plane_norm(const mbp_plan* P, const double* f, double* out, hipStrea
 }
 
 void launch_update_active(const mbp_plan* P, double rtol2, double etol2, int retire, int maxc,
-                          hipStream_t s) {
+                          hipStream_t s, double* out) {
     const UpdJob J{P->g.nz, P->d_rnorm, P->d_fnorm, P->d_pnorm, P->d_sabs, rtol2, etol2,
-                   retire, maxc, P->d_act, P->d_nact, P->d_cyc, P->d_scal, P->d_flag};
+                   retire, maxc, P->d_act, P->d_nact, P->d_cyc, P->d_scal, P->d_flag, out};
     hipLaunchKernelGGL(k_update, dim3(1), dim3(1024), 0, s, J);
 }
 

@@ -286,6 +286,9 @@ namespace {
 constexpr int kPinScal = 0;     // doubles 0..7: d_scal
 constexpr int kPinSum = 8;      // double: singular-plane area sum
 constexpr int kPinInts = 32;    // ints (byte offset 256): flag[0..3], nact
+constexpr int kPinSlots = 64;   // doubles from byte 512: state slots of the pipelined loop
+constexpr int kSlotDoubles = 8; //   each scal[0..1], then ints flag[0..3], nact
+constexpr int kSlots = 3;
 }  // namespace
 
 void ctx_init(SolveCtx& c, mbp_plan* P, const double* rhs, double* p, double rtol, int flags) {
@@ -345,7 +348,7 @@ void ctx_check(SolveCtx& c) {
 
 // Convergence test of the current iterate (Sec. 3's per-mode systems each
 // stop on their own when retiring).
-void ctx_test(SolveCtx& c, hipStream_t s) {
+void ctx_test(SolveCtx& c, hipStream_t s, double* state_out) {
     mbp_plan* P = c.P;
     const bool zero = c.cycles == 0 && !c.warm;  // p = 0: the residual is f itself
     if (c.mixed)
@@ -357,7 +360,7 @@ void ctx_test(SolveCtx& c, hipStream_t s) {
         launch_finish(P, c.fused_parts, P->d_rnorm, P->d_act, P->d_nact, c.nitems, s);
     else
         launch_residual_norm(P, P->phat, P->fhat, P->d_rnorm, P->d_act, P->d_nact, c.nitems, s);
-    launch_update_active(P, c.rtol2, c.etol2, c.retire ? 1 : 0, P->opt.max_cycles, s);
+    launch_update_active(P, c.rtol2, c.etol2, c.retire ? 1 : 0, P->opt.max_cycles, s, state_out);
 }
 
 void ctx_vcycle(SolveCtx& c, hipStream_t s) {
@@ -386,16 +389,15 @@ void ctx_state_readback(SolveCtx& c, hipStream_t s) {
 
 // After the readback synchronised: stop when every mode retired (retiring
 // form) or every mode passed (lockstep), or when the cycle budget ran out.
-void ctx_state_apply(SolveCtx& c) {
-    mbp_plan* P = c.P;
-    const int* hi = pin_i(P);
+// hi: flag[0..3], nact; scal1: the lockstep count of unconverged modes.
+static void state_apply(SolveCtx& c, const int* hi, double scal1) {
     const bool hitmax = hi[2] != 0;
     bool converged;
     if (c.retire) {
         c.nitems = hi[4];
         converged = c.nitems == 0 && !hitmax;
     } else {
-        converged = pin_d(P)[kPinScal + 1] == 0.0;
+        converged = scal1 == 0.0;
     }
     if (converged) {
         c.done = true;
@@ -404,6 +406,8 @@ void ctx_state_apply(SolveCtx& c) {
         c.done = true;
     }
 }
+
+void ctx_state_apply(SolveCtx& c) { state_apply(c, pin_i(c.P), pin_d(c.P)[kPinScal + 1]); }
 
 void ctx_epilogue(SolveCtx& c, hipStream_t s) {
     mbp_plan* P = c.P;
@@ -460,6 +464,36 @@ int solve_one(mbp_plan* P, const double* rhs, double* p, double rtol, int flags,
         if (!c.done && c.full_lds) {
             launch_lds_full(P, P->phat, P->fhat, P->d_act, P->d_nact, P->g.nz, P->opt.max_cycles, c.rtol2,
                             c.etol2, P->d_cyc, P->d_rnorm, P->d_fnorm, s);
+        } else if (c.retire) {
+            // Pipelined: the next V-cycle and test are queued before the host
+            // reads the state of the previous test, so the device never waits
+            // for the host.  Once every mode has retired the queued work runs
+            // on an empty active list (no-op launches).
+            double* slots = pin_d(P) + kPinSlots;
+            double* dslots = nullptr;
+            if (hipHostGetDevicePointer(reinterpret_cast<void**>(&dslots), slots, 0) != hipSuccess) {
+                st = MBP_ERR_HIP;
+            } else {
+                hipEvent_t sev[kSlots];
+                for (auto& e : sev) (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+                auto test = [&](int k) {
+                    ctx_test(c, s, dslots + (k % kSlots) * kSlotDoubles);
+                    (void)hipEventRecord(sev[k % kSlots], s);
+                };
+                test(0);
+                for (int k = 0;; ++k) {
+                    ctx_vcycle(c, s);
+                    test(k + 1);
+                    if (hipEventSynchronize(sev[k % kSlots]) != hipSuccess) {
+                        st = MBP_ERR_HIP;
+                        break;
+                    }
+                    const double* sl = slots + (k % kSlots) * kSlotDoubles;
+                    state_apply(c, reinterpret_cast<const int*>(sl + 2), sl[1]);
+                    if (c.done) break;
+                }
+                for (auto& e : sev) (void)hipEventDestroy(e);
+            }
         } else {
             while (!c.done) {
                 ctx_test(c, s);
