@@ -715,11 +715,14 @@ struct LdsArgs {
     const double* cwl;   // coarsest eigen tables
     const double* cwr;
     const double* cmu;
+    double cmumax;       // max |cmu| (host)
     int nc;
     int dpb, dpn, ipb, ipn;  // pool ranges of the tables of levels L.. (copied into LDS)
     int fglob;           // level L's rhs is read from device memory, not copied into LDS
     const double* cdp;   // in the kernel: the copies, indexed like the pools
     const int* cip;
+    int nthr;            // in the kernel: threads of the workgroup, held in a register
+                         // (blockDim.x is a memory load that each loop would repeat)
 };
 
 template <typename T>
@@ -731,6 +734,7 @@ struct LdsView {
     double* red;         // reduction scratch (16 doubles)
     double* tdp;         // copy of the levels' coefficient / transfer tables
     int* tip;            //   and index tables
+    DBlock* tblk;        //   and block descriptors
 };
 
 template <typename T>
@@ -740,31 +744,65 @@ __device__ __forceinline__ T* lds_p(const LdsArgs& a, const LdsView<T>& v, int l
     return v.base + o;
 }
 
+// On the small levels (at most two cells per thread) the three phases below
+// spread the cells of all blocks over the workgroup at once (cell h of the
+// level's list is found by a scan of the per-block counts): a block's cells
+// then do not wait for the previous block's, which would put one latency
+// chain per block in every phase.  Larger levels go block by block, with the
+// block's descriptor in scalar registers.
+
+// Cells of one colour in block b (red-black blocks only).
+__device__ __forceinline__ int colour_cells(const DBlock& b) { return ((b.nx + 1) >> 1) * b.ny; }
+
 template <typename T>
 __device__ void lds_smooth(const LdsArgs& a, T* p, const T* f, const DBlock* B, T sig, int colour) {
     bool any_odd = false;
+    int total = 0;
     for (int bi = 0; bi < a.nb; ++bi) {
-        const DBlock b = wave_uniform(B[bi]);
-        any_odd |= b.oddwrap != 0;
-        if (b.oddwrap == 0) {
+        any_odd |= B[bi].oddwrap != 0;
+        if (B[bi].oddwrap == 0) total += colour_cells(B[bi]);
+    }
+    if (total > 2 * a.nthr) {
+        for (int bi = 0; bi < a.nb; ++bi) {
+            const DBlock b = wave_uniform(B[bi]);
+            if (b.oddwrap != 0) continue;
             const int hx = (b.nx + 1) >> 1;
             const int cnt = hx * b.ny;
-            for (int h = threadIdx.x; h < cnt; h += blockDim.x) {
+            for (int h = threadIdx.x; h < cnt; h += a.nthr) {
                 const int j = h / hx;
                 const int i = 2 * (h - j * hx) + ((colour + j + b.par) & 1);
-                if (i >= b.nx) continue;
-                p[b.off + j * b.nx + i] = gs_value(p, f, B, b, a.cdp, i, j, sig);
+                if (i < b.nx) p[b.off + j * b.nx + i] = gs_value(p, f, B, b, a.cdp, i, j, sig);
             }
-        } else {
+        }
+    } else {
+        for (int h = threadIdx.x; h < total; h += a.nthr) {
+            int bi = 0, r = h;
+            for (;; ++bi) {
+                if (B[bi].oddwrap != 0) continue;
+                const int c = colour_cells(B[bi]);
+                if (r < c) break;
+                r -= c;
+            }
+            const DBlock& b = B[bi];
+            const int hx = (b.nx + 1) >> 1;
+            const int j = r / hx;
+            const int i = 2 * (r - j * hx) + ((colour + j + b.par) & 1);
+            if (i < b.nx) p[b.off + j * b.nx + i] = gs_value(p, f, B, b, a.cdp, i, j, sig);
+        }
+    }
+    if (any_odd) {  // blocks with an odd periodic wrap: per block, by colour
+        for (int bi = 0; bi < a.nb; ++bi) {
+            const DBlock b = wave_uniform(B[bi]);
+            if (b.oddwrap == 0) continue;
             const int cnt = b.nx * b.ny;
-            for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+            for (int c = threadIdx.x; c < cnt; c += a.nthr) {
                 const int j = c / b.nx, i = c - j * b.nx;
                 if (colour_of(b, i, j) != colour) continue;
                 p[b.off + c] = gs_value(p, f, B, b, a.cdp, i, j, sig);
             }
         }
-        // cells of one colour are never neighbours, also across blocks
     }
+    // cells of one colour are never neighbours, also across blocks
     __syncthreads();
     if (any_odd && colour == 1) {  // the two extra colours of odd periodic wraps
         for (int extra = 2; extra < 4; ++extra) {
@@ -772,7 +810,7 @@ __device__ void lds_smooth(const LdsArgs& a, T* p, const T* f, const DBlock* B, 
                 const DBlock b = wave_uniform(B[bi]);
                 if (b.oddwrap == 0) continue;
                 const int cnt = b.nx * b.ny;
-                for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+                for (int c = threadIdx.x; c < cnt; c += a.nthr) {
                     const int j = c / b.nx, i = c - j * b.nx;
                     if (colour_of(b, i, j) != extra) continue;
                     p[b.off + c] = gs_value(p, f, B, b, a.cdp, i, j, sig);
@@ -783,17 +821,37 @@ __device__ void lds_smooth(const LdsArgs& a, T* p, const T* f, const DBlock* B, 
     }
 }
 
+// Cell h of the concatenated cells of the level's blocks: block index and
+// index inside the block (the block offsets are the packed plane offsets).
+__device__ __forceinline__ int block_of(const DBlock* B, int nb, int h) {
+    int bi = 0;
+    while (bi + 1 < nb && h >= B[bi + 1].off) ++bi;
+    return bi;
+}
+
 template <typename T>
 __device__ void lds_restrict(const LdsArgs& a, const T* pf, const T* ff, T* pc, T* fc,
                              const DBlock* Bf, const DBlock* Bc, T sig) {
-    for (int bi = 0; bi < a.nb; ++bi) {
-        const DBlock bc = wave_uniform(Bc[bi]);
-        const DBlock bf = wave_uniform(Bf[bi]);
-        const int cnt = bc.nx * bc.ny;
-        for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+    const int total = Bc[a.nb - 1].off + Bc[a.nb - 1].nx * Bc[a.nb - 1].ny;
+    if (total > 2 * a.nthr) {
+        for (int bi = 0; bi < a.nb; ++bi) {
+            const DBlock bc = wave_uniform(Bc[bi]);
+            const DBlock bf = wave_uniform(Bf[bi]);
+            const int cnt = bc.nx * bc.ny;
+            for (int c = threadIdx.x; c < cnt; c += a.nthr) {
+                const int J = c / bc.nx, I = c - J * bc.nx;
+                fc[bc.off + c] = restrict_at(pf, ff, Bf, bf, a.cdp, a.cip, I, J, sig);
+                pc[bc.off + c] = T(0);
+            }
+        }
+    } else {
+        for (int h = threadIdx.x; h < total; h += a.nthr) {
+            const int bi = block_of(Bc, a.nb, h);
+            const DBlock& bc = Bc[bi];
+            const int c = h - bc.off;
             const int J = c / bc.nx, I = c - J * bc.nx;
-            fc[bc.off + c] = restrict_at(pf, ff, Bf, bf, a.cdp, a.cip, I, J, sig);
-            pc[bc.off + c] = T(0);
+            fc[h] = restrict_at(pf, ff, Bf, Bf[bi], a.cdp, a.cip, I, J, sig);
+            pc[h] = T(0);
         }
     }
     __syncthreads();
@@ -801,12 +859,23 @@ __device__ void lds_restrict(const LdsArgs& a, const T* pf, const T* ff, T* pc, 
 
 template <typename T>
 __device__ void lds_prolong(const LdsArgs& a, const T* pc, T* pf, const DBlock* Bf, const DBlock* Bc) {
-    for (int bi = 0; bi < a.nb; ++bi) {
-        const DBlock bf = wave_uniform(Bf[bi]);
-        const int cnt = bf.nx * bf.ny;
-        for (int c = threadIdx.x; c < cnt; c += blockDim.x) {
+    const int total = Bf[a.nb - 1].off + Bf[a.nb - 1].nx * Bf[a.nb - 1].ny;
+    if (total > 2 * a.nthr) {
+        for (int bi = 0; bi < a.nb; ++bi) {
+            const DBlock bf = wave_uniform(Bf[bi]);
+            const int cnt = bf.nx * bf.ny;
+            for (int c = threadIdx.x; c < cnt; c += a.nthr) {
+                const int j = c / bf.nx, i = c - j * bf.nx;
+                pf[bf.off + c] += prolong_at(pc, Bc, bf, bi, a.cdp, a.cip, i, j);
+            }
+        }
+    } else {
+        for (int h = threadIdx.x; h < total; h += a.nthr) {
+            const int bi = block_of(Bf, a.nb, h);
+            const DBlock& bf = Bf[bi];
+            const int c = h - bf.off;
             const int j = c / bf.nx, i = c - j * bf.nx;
-            pf[bf.off + c] += prolong_at(pc, Bc, bf, bi, a.cdp, a.cip, i, j);
+            pf[h] += prolong_at(pc, Bc, bf, bi, a.cdp, a.cip, i, j);
         }
     }
     __syncthreads();
@@ -814,24 +883,42 @@ __device__ void lds_prolong(const LdsArgs& a, const T* pc, T* pf, const DBlock* 
 
 // Exact coarsest solve in float64: x = Wl diag(1/(mu + sigma)) Wr b, with the
 // null mode (mu + sigma = 0, singular plane) dropped.
+// Both products run kCoarseLanes lanes per row, each summing a strided part
+// of it, so a lane has only nc / kCoarseLanes dependent loads of the
+// (device-memory) eigenvector tables in its chain.
+constexpr int kCoarseLanes = 8;
+
 template <typename T>
 __device__ void lds_coarse(const LdsArgs& a, const LdsView<T>& v, T* p, const T* f, double sig) {
     const int nc = a.nc;
-    double mumax = 0.0;
-    for (int k = 0; k < nc; ++k) mumax = fmax(mumax, fabs(a.cmu[k]));
-    for (int k = threadIdx.x; k < nc; k += blockDim.x) {
+    const double mumax = a.cmumax;
+    const int g = threadIdx.x & (kCoarseLanes - 1);
+    const int rows = a.nthr / kCoarseLanes;
+    for (int k0 = 0; k0 < nc; k0 += rows) {
+        const int k = k0 + threadIdx.x / kCoarseLanes;
         double acc = 0.0;
-        const double* row = a.cwr + (long long)k * nc;
-        for (int j = 0; j < nc; ++j) acc += row[j] * double(f[j]);
-        const double d = a.cmu[k] + sig;
-        v.ctmp[k] = fabs(d) > 1e-11 * (mumax + fabs(sig)) ? acc / d : 0.0;
+        if (k < nc) {
+            const double* row = a.cwr + (long long)k * nc;
+#pragma unroll 4
+            for (int j = g; j < nc; j += kCoarseLanes) acc += row[j] * double(f[j]);
+        }
+        for (int o = 1; o < kCoarseLanes; o <<= 1) acc += __shfl_xor(acc, o);
+        if (k < nc && g == 0) {
+            const double d = a.cmu[k] + sig;
+            v.ctmp[k] = fabs(d) > 1e-11 * (mumax + fabs(sig)) ? acc / d : 0.0;
+        }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+    for (int i0 = 0; i0 < nc; i0 += rows) {
+        const int i = i0 + threadIdx.x / kCoarseLanes;
         double acc = 0.0;
-        const double* row = a.cwl + (long long)i * nc;
-        for (int k = 0; k < nc; ++k) acc += row[k] * v.ctmp[k];
-        p[i] = T(acc);
+        if (i < nc) {
+            const double* row = a.cwl + (long long)i * nc;
+#pragma unroll 4
+            for (int k = g; k < nc; k += kCoarseLanes) acc += row[k] * v.ctmp[k];
+        }
+        for (int o = 1; o < kCoarseLanes; o <<= 1) acc += __shfl_xor(acc, o);
+        if (i < nc && g == 0) p[i] = T(acc);
     }
     __syncthreads();
 }
@@ -882,18 +969,29 @@ __device__ LdsView<T> lds_view(const LdsArgs& a, unsigned char* raw) {
     v.red = v.ctmp + ((a.nc + 1) & ~1);
     v.tdp = v.red + 16;
     v.tip = reinterpret_cast<int*>(v.tdp + a.dpn);
+    v.tblk = reinterpret_cast<DBlock*>(v.tip + a.ipn);
     v.fL = v.base + a.ip[a.lvinfo + 4 * a.L];  // after level L's p (unless fglob)
     return v;
 }
 
-// Copy the level tables into LDS and point the stencil routines at the copies
-// (the pointers are rebased so that pool offsets index them directly).
+// Copy the level tables and block descriptors into LDS and point the stencil
+// routines at the copies (the pointers are rebased so that pool offsets and
+// block indices index them directly): a neighbour lookup across a joined
+// face then costs an LDS read, not a dependent device-memory load.
 template <typename T>
 __device__ __forceinline__ void lds_tables(LdsArgs& a, const LdsView<T>& v) {
-    for (int t = threadIdx.x; t < a.dpn; t += blockDim.x) v.tdp[t] = a.dp[a.dpb + t];
-    for (int t = threadIdx.x; t < a.ipn; t += blockDim.x) v.tip[t] = a.ip[a.ipb + t];
+    a.nthr = __builtin_amdgcn_readfirstlane(int(blockDim.x));
+    for (int t = threadIdx.x; t < a.dpn; t += a.nthr) v.tdp[t] = a.dp[a.dpb + t];
+    for (int t = threadIdx.x; t < a.ipn; t += a.nthr) v.tip[t] = a.ip[a.ipb + t];
+    const int blk0 = a.ip[a.lvinfo + 4 * a.L + 1];
+    constexpr int kWords = int(sizeof(DBlock) / sizeof(int));
+    const int words = (a.nlev - a.L) * a.nb * kWords;
+    const int* src = reinterpret_cast<const int*>(a.Ball + blk0);
+    int* dst = reinterpret_cast<int*>(v.tblk);
+    for (int t = threadIdx.x; t < words; t += a.nthr) dst[t] = src[t];
     a.cdp = v.tdp - a.dpb;
     a.cip = v.tip - a.ipb;
+    a.Ball = v.tblk - blk0;
 }
 
 // One V-cycle on levels L.. of every active mode: f_L in, p_L out (from 0).
@@ -922,17 +1020,17 @@ __device__ __forceinline__ void lds_vcycle_body(const LdsJob<T>& J, int item) {
         // the rhs is only read; the sweeps and the restriction take it from
         // device memory (just written by the level above, so cached)
         v.fL = const_cast<T*>(J.fL + q * planeL);
-        for (long long c = threadIdx.x; c < planeL; c += blockDim.x) p[c] = T(0);
+        for (long long c = threadIdx.x; c < planeL; c += a.nthr) p[c] = T(0);
     } else {
         T* f = v.fL;
-        for (long long c = threadIdx.x; c < planeL; c += blockDim.x) {
+        for (long long c = threadIdx.x; c < planeL; c += a.nthr) {
             f[c] = J.fL[q * planeL + c];
             p[c] = T(0);
         }
     }
     __syncthreads();
     lds_vcycle(a, v, J.shift[q]);
-    for (long long c = threadIdx.x; c < planeL; c += blockDim.x) J.pL[q * planeL + c] = p[c];
+    for (long long c = threadIdx.x; c < planeL; c += a.nthr) J.pL[q * planeL + c] = p[c];
 }
 
 template <typename T>
@@ -940,13 +1038,13 @@ __global__ void __launch_bounds__(1024) k_lds_vcycle(const LdsJob<T> J) {
     lds_vcycle_body<T>(J, blockIdx.x);
 }
 
-__device__ double lds_block_sum(double x, double* red) {
+__device__ double lds_block_sum(double x, double* red, int nthr) {
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
     __syncthreads();
     double s = 0.0;
-    for (int w = 0; w < int(blockDim.x >> 6); ++w) s += red[w];
+    for (int w = 0; w < (nthr >> 6); ++w) s += red[w];
     __syncthreads();
     return s;  // every thread holds the same sum
 }
@@ -970,13 +1068,13 @@ k_lds_full(LdsArgs a, double* __restrict__ p0, const double* __restrict__ f0, lo
     double* f = p + plane;
     const DBlock* B = a.Ball + a.ip[a.lvinfo + 1];
     double fs = 0.0;
-    for (long long c = threadIdx.x; c < plane; c += blockDim.x) {
+    for (long long c = threadIdx.x; c < plane; c += a.nthr) {
         const double x = f0[q * plane + c];
         f[c] = x;
         p[c] = p0[q * plane + c];
         fs += x * x;
     }
-    const double fn = lds_block_sum(fs, v.red);
+    const double fn = lds_block_sum(fs, v.red, a.nthr);
     const double sig = shift[q];
     int c = 0;
     double rn = 0.0;
@@ -986,20 +1084,20 @@ k_lds_full(LdsArgs a, double* __restrict__ p0, const double* __restrict__ f0, lo
         for (int bi = 0; bi < a.nb; ++bi) {
             const DBlock b = B[bi];
             const int cnt = b.nx * b.ny;
-            for (int k = threadIdx.x; k < cnt; k += blockDim.x) {
+            for (int k = threadIdx.x; k < cnt; k += a.nthr) {
                 const int j = k / b.nx, i = k - j * b.nx;
                 const double r = f[b.off + k] - apply_at(p, B, b, a.cdp, i, j, sig);
                 rs += r * r;
                 ps += p[b.off + k] * p[b.off + k];
             }
         }
-        rn = lds_block_sum(rs, v.red);
-        const double pn = lds_block_sum(ps, v.red);
+        rn = lds_block_sum(rs, v.red, a.nthr);
+        const double pn = lds_block_sum(ps, v.red, a.nthr);
         const bool err_ok = etol2 < 0.0 || 4.0 * rn <= etol2 * sa * sa * pn;
         if ((rn <= rtol2 * fn && err_ok) || c >= maxc) break;
         lds_vcycle(a, v, sig);
     }
-    for (long long k = threadIdx.x; k < plane; k += blockDim.x) p0[q * plane + k] = p[k];
+    for (long long k = threadIdx.x; k < plane; k += a.nthr) p0[q * plane + k] = p[k];
     if (threadIdx.x == 0) {
         cyc[q] = c;
         rnorm[q] = rn;
@@ -1027,6 +1125,8 @@ static LdsArgs lds_args(const mbp_plan* P, int L) {
     a.cwl = P->d_cwl;
     a.cwr = P->d_cwr;
     a.cmu = P->d_cmu;
+    a.cmumax = 0.0;
+    for (double mu : P->coarse_mu) a.cmumax = std::max(a.cmumax, std::fabs(mu));
     a.nc = P->coarse_n;
     a.dpb = P->levels[L].dp_begin;
     a.dpn = P->dp_levels_end - a.dpb;

@@ -639,7 +639,8 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
             int64_t e = 0;
             for (int l = L0; l < P->nlev; ++l) e += 2 * P->levels[l].plane;
             const int64_t tables = int64_t(P->dp_levels_end - P->levels[L0].dp_begin) * 8 +
-                                   int64_t(P->ip_levels_end - P->levels[L0].ip_begin) * 4;
+                                   int64_t(P->ip_levels_end - P->levels[L0].ip_begin) * 4 +
+                                   int64_t(P->nlev - L0) * nb * int64_t(sizeof(DBlock));
             return e * elem + int64_t(P->coarse_n) * 8 + 1024 + tables;
         };
         P->lds_level = P->nlev - 1;
