@@ -171,6 +171,23 @@ def cpu_baseline_separable(probs_fs, unit: str, budget_s: float = 25.0) -> dict:
                        f"BLAS threads {threads} of os.cpu_count() = {ncpu}; CPU {model or 'unknown'}")}
 
 
+def cpu_baseline_alg1(prob, f) -> dict:
+    """The oracle's Algorithm 1 route (forward transform, one sparse LU per
+    distinct modal shift, inverse transform) on the whole problem, the
+    per-shift solves spread over a process pool of os.cpu_count() workers
+    (at most 16)."""
+    import oracle
+    model, threads, ncpu = _cpu_info()
+    workers = max(1, min(16, ncpu or 1))
+    t0 = time.perf_counter()
+    oracle.solve_alg1(prob, f, workers=workers)
+    t = time.perf_counter() - t0
+    return {"value": prob.ncells / t, "unit": "grid points/s", "cores": workers, "kind": "oracle",
+            "sample": (f"FP64 oracle, Algorithm 1 route (sparse LU per modal shift), full run: "
+                       f"{prob.ncells} cells in {t:.1f} s wall; {workers} worker processes of "
+                       f"os.cpu_count() = {ncpu}; CPU {model or 'unknown'}")}
+
+
 # ---------------------------------------------------------------------------
 # Single problems
 # ---------------------------------------------------------------------------
@@ -703,18 +720,28 @@ def main(argv=None):
         largs = argparse.Namespace(**{**vars(args), "precision": "fp64", "lockstep": False})
         lmain, lvar = bench_single(largs, torch, mbp, lp, lf, with_variants=True)
         lmg = bench_mg3d(largs, torch, mbp, lp, lf, lmain["ms_per_solve"])
+        lcpu = None
+        if not args.no_cpu:
+            log("lshape: cpu baseline (oracle, Algorithm 1 route in a process pool)")
+            lcpu = cpu_baseline_alg1(lp, lf)
         del lf
         sub["lshape"] = {"config": {"workload": lp.name, "cells": lp.ncells, "nz": lp.nz, "blocks": 3},
-                         "fp64": _strip(lmain), **{k: _strip(v) for k, v in lvar.items()}, "mg3d": lmg}
+                         "fp64": _strip(lmain), **{k: _strip(v) for k, v in lvar.items()}, "mg3d": lmg,
+                         "cpu_baseline": lcpu}
         # eight blocks around a square obstacle (the paper's third geometry)
         op = W.obstacle8(64, 576)
         of = W.rhs(op, 6, "normal")
         oargs = argparse.Namespace(**{**vars(args), "precision": "fp64", "lockstep": False})
         omain, ovar = bench_single(oargs, torch, mbp, op, of, with_variants=True)
         omg = bench_mg3d(oargs, torch, mbp, op, of, omain["ms_per_solve"])
+        ocpu = None
+        if not args.no_cpu:
+            log("obstacle8: cpu baseline (oracle, Algorithm 1 route in a process pool)")
+            ocpu = cpu_baseline_alg1(op, of)
         del of
         sub["obstacle8"] = {"config": {"workload": op.name, "cells": op.ncells, "nz": op.nz, "blocks": 8},
-                            "fp64": _strip(omain), **{k: _strip(v) for k, v in ovar.items()}, "mg3d": omg}
+                            "fp64": _strip(omain), **{k: _strip(v) for k, v in ovar.items()}, "mg3d": omg,
+                            "cpu_baseline": ocpu}
         sub["batch64"] = bench_batch(args, torch, mbp, not args.no_cpu)
         sub["serve"] = bench_serve(args, torch, mbp, not args.no_cpu)
 
