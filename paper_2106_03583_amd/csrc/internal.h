@@ -53,6 +53,7 @@ struct Level {
     int tile_off = 0;             // first tile in the tile table
     int64_t lds_off = 0;          // element offset of this level in the LDS image
     bool oddwrap = false;         // some block needs the two extra smoothing colours
+    int cx = 1, cy = 1;           // the next coarser level halves x / y (semicoarsening: one of them)
     int dp_begin = 0, ip_begin = 0;  // first entries of this level's tables in the pools
 };
 

@@ -138,6 +138,7 @@ int mg3_create(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* 
         L.even_xy = 1;
         for (int b = 0; b < X2.nb; ++b)
             if ((X2.nx[b] & 1) || (X2.ny[b] & 1)) L.even_xy = 0;
+        L.xy22 = X2.cx && X2.cy ? 1 : 0;
     }
     return MBP_OK;
 }

@@ -13,6 +13,7 @@ struct Mg3Level {
     int xyc = 0;          // the next coarser 3D level coarsens x-y (else x-y is kept)
     int zc = 0;           // the next coarser 3D level halves z (else z is kept)
     int even_xy = 0;      // every block has even x and y counts (x-y children in pairs)
+    int xy22 = 1;         // an x-y coarsening step from here halves both x and y (not semicoarsened)
     int blk_off = 0;      // first DBlock of the x-y level in the block table
     int tile_off = 0;     // first x-y tile of the level
     int ntiles = 0;

@@ -712,7 +712,7 @@ void m3_restrict(const Mg3Plan& M, int l, const double* p, const double* f, doub
     const Mg3Level& F = M.lev[l];
     const Mg3Level& C = M.lev[l + 1];
     const Op3 o = op_of(M, l);
-    if (F.xyc && F.zc && F.even_xy && F.nz % kZChunk == 0) {  // marching form
+    if (F.xyc && F.zc && F.xy22 && F.even_xy && F.nz % kZChunk == 0) {  // marching form
         const dim3 g(unsigned(F.ntiles), unsigned(F.nz / kZChunk));
         hipLaunchKernelGGL(k3_jacobi_zm<2>, g, kBlk, 0, s, o, M.d_tiles + F.tile_off, F.ntiles, p, nullptr, f, fshift,
                            M.omega, nullptr, Rst3{M.d_blk + C.blk_off, C.nz, fc});
@@ -725,7 +725,7 @@ void m3_restrict(const Mg3Plan& M, int l, const double* p, const double* f, doub
 void m3_prolong(const Mg3Plan& M, int l, const double* pc, double* pf, hipStream_t s) {
     const Mg3Level& F = M.lev[l];
     const Mg3Level& C = M.lev[l + 1];
-    if (F.xyc && F.zc && F.nz % kPZChunk == 0) {
+    if (F.xyc && F.zc && F.xy22 && F.nz % kPZChunk == 0) {  // staged tile: x-y halved
         const dim3 g(unsigned(F.ntiles), unsigned(F.nz / kPZChunk));
         hipLaunchKernelGGL(k3_prolong_zm, g, kBlk, 0, s, M.d_blk + F.blk_off, M.d_blk + C.blk_off,
                            M.d_tiles + F.tile_off, F.ntiles, F.nz, C.nz, M.d_dbl, M.d_int, pc, pf, M.zlo, M.zhi);

@@ -327,8 +327,13 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
         P->lambda[q] = double(lam);
     }
 
-    // ---- multigrid levels: full coarsening while every block has >= 4 cells
-    //      per direction; odd counts merge their last three cells ----
+    // ---- multigrid levels.  Each step coarsens the direction(s) with the
+    //      smaller mean cell width, as PFMG picks its semicoarsening direction
+    //      (Sec. 3.3.1): x alone when the mean x width is below the mean y
+    //      width over sqrt(2), y alone in the opposite case, both otherwise; the
+    //      hierarchy ends when a direction to be coarsened has a block with
+    //      fewer than 4 cells along it.  Odd counts merge their last three
+    //      cells ----
     P->levels.clear();
     {
         Level L;
@@ -340,11 +345,35 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
         P->levels.push_back(L);
     }
     while (P->levels.size() < 24) {
-        const Level& F = P->levels.back();
-        bool ok = true;
-        for (int b = 0; b < nb; ++b)
-            if (F.nx[b] < 4 || F.ny[b] < 4) ok = false;
-        if (!ok) break;
+        Level& F = P->levels.back();
+        bool canx = true, cany = true;
+        double wx = 0.0, wy = 0.0;
+        int64_t cellsx = 0, cellsy = 0;
+        for (int b = 0; b < nb; ++b) {
+            if (F.nx[b] < 4) canx = false;
+            if (F.ny[b] < 4) cany = false;
+            wx += F.xf[b].back() - F.xf[b].front();
+            wy += F.yf[b].back() - F.yf[b].front();
+            cellsx += F.nx[b];
+            cellsy += F.ny[b];
+        }
+        const double hx = wx / double(cellsx), hy = wy / double(cellsy);
+        // halving the smaller width alone brings the ratio closer to 1 once
+        // it exceeds sqrt(2)
+        const double r2 = 0.70710678118654752440;
+        bool cx, cy;
+        if (hx < r2 * hy) {  // x strongly coupled: x alone
+            cx = canx;
+            cy = false;
+        } else if (hy < r2 * hx) {
+            cx = false;
+            cy = cany;
+        } else {
+            cx = cy = canx && cany;
+        }
+        if (!cx && !cy) break;
+        F.cx = cx ? 1 : 0;
+        F.cy = cy ? 1 : 0;
         Level C;
         C.nb = nb;
         C.nx.resize(nb);
@@ -352,8 +381,8 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
         C.xf.resize(nb);
         C.yf.resize(nb);
         for (int b = 0; b < nb; ++b) {
-            C.xf[b] = coarsen_faces(F.xf[b]);
-            C.yf[b] = coarsen_faces(F.yf[b]);
+            C.xf[b] = cx ? coarsen_faces(F.xf[b]) : F.xf[b];
+            C.yf[b] = cy ? coarsen_faces(F.yf[b]) : F.yf[b];
             C.nx[b] = int(C.xf[b].size()) - 1;
             C.ny[b] = int(C.yf[b].size()) - 1;
         }
@@ -489,12 +518,16 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
                     const std::vector<double>& F = axis == 0 ? L.xf[b] : L.yf[b];
                     const std::vector<double>& G = axis == 0 ? C.xf[b] : C.yf[b];
                     int n = int(F.size()) - 1, nc = int(G.size()) - 1;
+                    // a direction the next level keeps (semicoarsening) maps cell
+                    // i to itself: one child, weight 1; the prolongation
+                    // tables below then give weight 1 to the coincident centre
+                    const int ratio = nc == n ? 1 : 2;
                     std::vector<int> rs(nc + 1);
-                    for (int I = 0; I < nc; ++I) rs[I] = 2 * I;
+                    for (int I = 0; I < nc; ++I) rs[I] = ratio * I;
                     rs[nc] = n;
                     std::vector<double> rw(n);
                     for (int i = 0; i < n; ++i) {
-                        int I = std::min(i / 2, nc - 1);
+                        int I = std::min(i / ratio, nc - 1);
                         rw[i] = (F[i + 1] - F[i]) / (G[I + 1] - G[I]);
                     }
                     // prolongation: coarse centres with a ghost centre beyond each face

@@ -104,7 +104,10 @@ void plan_march_tables(mbp_plan* P, std::vector<unsigned char>& bytes) {
     bytes.clear();
     int off = 0;
     for (int l = 0; l < P->nlev; ++l) {
-        P->march_ok[l] = march_level_ok(P, l) ? 1 : 0;
+        // the fused transfers take 2 x 2 children (restriction) and two fine
+        // rows per coarse row (correction): not above a semicoarsened step
+        const bool full_step = l + 1 >= P->nlev || (P->levels[l].cx && P->levels[l].cy);
+        P->march_ok[l] = full_step && march_level_ok(P, l) ? 1 : 0;
         if (!P->march_ok[l]) continue;
         for (int set = 0; set < 2; ++set) {
             std::vector<unsigned char> b;

@@ -401,3 +401,47 @@ def test_solve_prime_half_length(torch_cuda, mbp, zk):
     print(f"  {prob.name}: {info} residual={res:.2e} error={err:.2e}", flush=True)
     assert info.status == 0 and res <= 1e-10 and err <= 1e-9
     plan.close()
+
+
+def _aniso_problems():
+    D, N, C = W.DIRICHLET, W.NEUMANN, W.CONNECT
+    # two joined blocks of 1 x 4 cells (dx = 1/128, dy = 1/32)
+    A = W.Block((1, 1), (128, 32), W.faces(128, 0.0, 1.0), W.faces(32, 0.0, 1.0), (D, C, N, N))
+    B = W.Block((129, 1), (192, 32), W.faces(64, 1.0, 1.5), W.faces(32, 0.0, 1.0), (C, N, N, D))
+    joined = W.Problem([A, B], 8, 0.5, W.PAIRS["DN"], name="two_block_aspect4")
+    return [
+        W.box(256, 64, 8, 1.0, 1.0, 0.25, "DD", "NN", "PP", name="box256x64_aspect4"),
+        W.box(64, 256, 6, 1.0, 0.25, 0.1, "NN", "DD", "NN", yfactor=1.2, name="box64x256_aspect16"),
+        W.box(64, 128, 8, 0.125, 1.0, 0.5, "PP", "ND", "DD", name="box64x128_aspect4_periodic"),
+        joined,
+        two_block(6, "PP", 100, 36, 44),
+    ]
+
+
+# Anisotropic cells: the hierarchy halves only the direction of the smaller
+# mean width (PFMG's semicoarsening rule) until the cells are near square;
+# point red-black smoothing then keeps its rate (cycles stay <= 30).  The
+# last layout mixes a uniform block of 0.01-wide cells with a stretched one
+# (cell aspect 1.3 to 2.9 across the plane): one global direction per level
+# cannot match every cell there, so it keeps a looser bound (it needed 48
+# cycles with full coarsening).
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("prob", _aniso_problems(), ids=lambda p: p.name)
+def test_anisotropic_semicoarsening(torch_cuda, mbp, prob, precision):
+    torch = torch_cuda
+    print(f"anisotropic {prob.name} {precision}", flush=True)
+    f = W.rhs(prob, 31)
+    ref = oracle.solve(prob, f)
+    fproj = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
+    plan = mbp.Plan(prob, precision=precision)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.PROJECT_RHS | mbp.RETIRE)
+    got = host(p)
+    res = oracle.rel_residual(prob, got, fproj)
+    err = oracle.rel_error(got, ref)
+    print(f"  {info} residual={res:.2e} error={err:.2e}", flush=True)
+    assert info.status == 0
+    assert res <= 1e-10
+    assert err <= 1e-9
+    assert info.cycles <= (40 if prob.name == "two_block_PP_6" else 30)
+    plan.close()
