@@ -15,6 +15,8 @@
 // A workgroup runs several modes of its strip in turn, issuing the loads of
 // the next mode before relaxing the current one.
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "internal.h"
@@ -1087,9 +1089,55 @@ static int modes_per_wg(int ntiles, int nitems, int target) {
     return int(std::max(1LL, std::min<long long>(kMaxModes, per)));
 }
 
+// Workgroups of a strip kernel resident on the chip at once (occupancy x CUs,
+// taken once per kernel on the current device).
+static int chip_slots(const void* kernel) {
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, int> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({dev, kernel});
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        per_cu = 1;
+        ncu = 256;
+    }
+    const int slots = std::max(1, per_cu) * std::max(1, ncu);
+    cache[{dev, kernel}] = slots;
+    return slots;
+}
+
+// Modes per workgroup of a single-problem launch: the count for which the
+// rounds of workgroups the chip runs (the last one often nearly empty) times
+// the time of one workgroup (per modes plus its strip set-up, about two
+// modes' worth) is smallest; ties go to the count the workgroup target gives
+// or, failing that, to the larger count.
+static int modes_per_wg_balanced(int ntiles, int nitems, int target, int slots) {
+    const int pref = modes_per_wg(ntiles, nitems, target);
+    int best = pref;
+    long long best_cost = -1;
+    for (int per = 1; per <= kMaxModes; ++per) {
+        if (per > nitems) break;
+        const long long wgs = (long long)ntiles * ((nitems + per - 1) / per);
+        const long long rounds = (wgs + slots - 1) / slots;
+        const long long cost = rounds * (per + 2);
+        if (best_cost < 0 || cost < best_cost || (cost == best_cost && best != pref && (per == pref || per > best))) {
+            best_cost = cost;
+            best = per;
+        }
+    }
+    return best;
+}
+
 template <typename T, bool PRO, bool RES, bool NRM>
 static void launch_march(MArgs<T> a, int nitems, hipStream_t s) {
-    a.per = modes_per_wg(a.ntiles, nitems, a.wg_target);
+    const void* fn = PRO ? reinterpret_cast<const void*>(k_tile_corr<T, NRM>)
+                         : reinterpret_cast<const void*>(k_tile<T, RES, NRM>);
+    a.per = modes_per_wg_balanced(a.ntiles, nitems, a.wg_target, chip_slots(fn));
     const int groups = (nitems + a.per - 1) / a.per;
     if constexpr (PRO)
         hipLaunchKernelGGL((k_tile_corr<T, NRM>), dim3(a.ntiles, groups), dim3(256), 0, s, a);
