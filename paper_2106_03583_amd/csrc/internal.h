@@ -53,7 +53,8 @@ struct Level {
     int tile_off = 0;             // first tile in the tile table
     int64_t lds_off = 0;          // element offset of this level in the LDS image
     bool oddwrap = false;         // some block needs the two extra smoothing colours
-    int cx = 1, cy = 1;           // the next coarser level halves x / y (semicoarsening: one of them)
+    int cx = 1, cy = 1;           // the next coarser level halves x / y in every block (the transfer
+                                  // tables carry each block's own step)
     int dp_begin = 0, ip_begin = 0;  // first entries of this level's tables in the pools
 };
 
@@ -193,8 +194,12 @@ struct mbp_plan {
 namespace mbp {
 
 // plan.cpp
+// uniform_levels: every block takes each coarsening step (the hierarchy ends
+// when one block cannot), instead of each class of blocks sharing cells
+// across joined faces stepping on its own
 int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* z,
-                           const mbp_options* opt, int64_t lds_limit, mbp_plan* P, std::string* err);
+                           const mbp_options* opt, int64_t lds_limit, mbp_plan* P, std::string* err,
+                           bool uniform_levels = false);
 int build_plan_host(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* z,
                     const mbp_options* opt, mbp_plan* P, std::string* err);
 void options_default(mbp_options* o);

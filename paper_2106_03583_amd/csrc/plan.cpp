@@ -272,7 +272,8 @@ int build_plan_host(const mbp_block_desc* blocks, int nblocks, const mbp_synth_d
 }
 
 int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* z,
-                           const mbp_options* opt, int64_t lds_limit, mbp_plan* P, std::string* err) {
+                           const mbp_options* opt, int64_t lds_limit, mbp_plan* P, std::string* err,
+                           bool uniform_levels) {
     P->lds_limit = lds_limit;
     if (!validate(blocks, nblocks, z, P->g, err)) return MBP_ERR_INVALID;
     Geometry& g = P->g;
@@ -330,10 +331,36 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
     // ---- multigrid levels.  Each step coarsens the direction(s) with the
     //      smaller mean cell width, as PFMG picks its semicoarsening direction
     //      (Sec. 3.3.1): x alone when the mean x width is below the mean y
-    //      width over sqrt(2), y alone in the opposite case, both otherwise; the
-    //      hierarchy ends when a direction to be coarsened has a block with
-    //      fewer than 4 cells along it.  Odd counts merge their last three
+    //      width over sqrt(2), y alone in the opposite case, both otherwise.
+    //      Blocks joined across a y face share their x cells, so they halve x
+    //      together; blocks joined across an x face halve y together.  Each
+    //      such class halves a direction while its blocks have at least 4
+    //      cells along it; a thinner class then merges its 2 or 3 cells into
+    //      one while other classes go on halving, where that direction is its
+    //      cells' strongly coupled one.  A thin block thus does not hold back
+    //      the rest of the plane; the hierarchy ends when no class can halve
+    //      the chosen direction(s).  Odd counts merge their last three
     //      cells ----
+    std::vector<int> xcls(nb), ycls(nb);
+    {
+        auto find = [](std::vector<int>& u, int a) {
+            while (u[a] != a) a = u[a] = u[u[a]];
+            return a;
+        };
+        for (int b = 0; b < nb; ++b) xcls[b] = ycls[b] = b;
+        for (int b = 0; b < nb; ++b)
+            for (int f = 0; f < 4; ++f) {
+                const int k = g.nbr[b][f];
+                if (k < 0) continue;
+                std::vector<int>& u = f < 2 ? ycls : xcls;  // x faces tie y cells, y faces x cells
+                const int ra = find(u, b), rb = find(u, k);
+                if (ra != rb) u[std::max(ra, rb)] = std::min(ra, rb);
+            }
+        for (int b = 0; b < nb; ++b) {
+            xcls[b] = find(xcls, b);
+            ycls[b] = find(ycls, b);
+        }
+    }
     P->levels.clear();
     {
         Level L;
@@ -346,12 +373,19 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
     }
     while (P->levels.size() < 24) {
         Level& F = P->levels.back();
-        bool canx = true, cany = true;
         double wx = 0.0, wy = 0.0;
         int64_t cellsx = 0, cellsy = 0;
+        // per class (indexed by its representative): every block has at
+        // least 4 cells along the direction (halve), or 2-3 (merge into one
+        // cell, taken only while another class halves that direction, so a
+        // thin block follows its neighbours one step further)
+        std::vector<char> canx(nb, 1), cany(nb, 1), mrgx(nb, 1), mrgy(nb, 1);
         for (int b = 0; b < nb; ++b) {
-            if (F.nx[b] < 4) canx = false;
-            if (F.ny[b] < 4) cany = false;
+            if (F.nx[b] < 4) canx[xcls[b]] = 0;
+            if (F.ny[b] < 4) cany[ycls[b]] = 0;
+            // (a periodic wrap keeps at least two cells)
+            if (F.nx[b] < 2 || g.bc[b][XM] == MBP_PERIODIC || g.bc[b][XP] == MBP_PERIODIC) mrgx[xcls[b]] = 0;
+            if (F.ny[b] < 2 || g.bc[b][YM] == MBP_PERIODIC || g.bc[b][YP] == MBP_PERIODIC) mrgy[ycls[b]] = 0;
             wx += F.xf[b].back() - F.xf[b].front();
             wy += F.yf[b].back() - F.yf[b].front();
             cellsx += F.nx[b];
@@ -361,19 +395,38 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
         // halving the smaller width alone brings the ratio closer to 1 once
         // it exceeds sqrt(2)
         const double r2 = 0.70710678118654752440;
-        bool cx, cy;
-        if (hx < r2 * hy) {  // x strongly coupled: x alone
-            cx = canx;
-            cy = false;
-        } else if (hy < r2 * hx) {
-            cx = false;
-            cy = cany;
-        } else {
-            cx = cy = canx && cany;
+        const bool dirx = !(hy < r2 * hx), diry = !(hx < r2 * hy);
+        bool halvex = false, halvey = false;
+        for (int b = 0; b < nb; ++b) {
+            halvex = halvex || (dirx && canx[xcls[b]]);
+            halvey = halvey || (diry && cany[ycls[b]]);
         }
-        if (!cx && !cy) break;
-        F.cx = cx ? 1 : 0;
-        F.cy = cy ? 1 : 0;
+        // a merge must leave the block's cells no more anisotropic than
+        // they would be without it: the merged direction has to be the
+        // block's strongly coupled one (width below the other direction's
+        // next-level width over sqrt(2)), as the direction rule itself asks
+        for (int b = 0; b < nb; ++b) {
+            const double wxb = (F.xf[b].back() - F.xf[b].front()) / F.nx[b];
+            const double wyb = (F.yf[b].back() - F.yf[b].front()) / F.ny[b];
+            const double wxn = (dirx && canx[xcls[b]]) ? 2.0 * wxb : wxb;
+            const double wyn = (diry && cany[ycls[b]]) ? 2.0 * wyb : wyb;
+            if (!(wxb < r2 * wyn)) mrgx[xcls[b]] = 0;
+            if (!(wyb < r2 * wxn)) mrgy[ycls[b]] = 0;
+        }
+        std::vector<char> bx(nb), by(nb);
+        bool any = false, allx = true, ally = true;
+        for (int b = 0; b < nb; ++b) {
+            const bool hxb = dirx && canx[xcls[b]], hyb = diry && cany[ycls[b]];
+            bx[b] = hxb || (!uniform_levels && halvex && !canx[xcls[b]] && mrgx[xcls[b]]);
+            by[b] = hyb || (!uniform_levels && halvey && !cany[ycls[b]] && mrgy[ycls[b]]);
+            any = any || bx[b] || by[b];
+            allx = allx && hxb;
+            ally = ally && hyb;
+        }
+        if (!any) break;
+        if (uniform_levels && ((dirx && !allx) || (diry && !ally))) break;
+        F.cx = allx ? 1 : 0;
+        F.cy = ally ? 1 : 0;
         Level C;
         C.nb = nb;
         C.nx.resize(nb);
@@ -381,8 +434,8 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
         C.xf.resize(nb);
         C.yf.resize(nb);
         for (int b = 0; b < nb; ++b) {
-            C.xf[b] = cx ? coarsen_faces(F.xf[b]) : F.xf[b];
-            C.yf[b] = cy ? coarsen_faces(F.yf[b]) : F.yf[b];
+            C.xf[b] = bx[b] ? coarsen_faces(F.xf[b]) : F.xf[b];
+            C.yf[b] = by[b] ? coarsen_faces(F.yf[b]) : F.yf[b];
             C.nx[b] = int(C.xf[b].size()) - 1;
             C.ny[b] = int(C.yf[b].size()) - 1;
         }
@@ -403,7 +456,7 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
     P->ncells = P->plane0 * nz;
     P->coarse_n = int(P->levels.back().plane);
     if (P->coarse_n > 2048) {
-        if (err) *err = "coarsest plane exceeds 2048 cells (block sizes too disparate)";
+        if (err) *err = "coarsest plane exceeds 2048 cells (cells too anisotropic to coarsen further)";
         return MBP_ERR_INVALID;
     }
     P->block_off.resize(nb + 1);

@@ -425,6 +425,37 @@ def _aniso_problems():
 # (cell aspect 1.3 to 2.9 across the plane): one global direction per level
 # cannot match every cell there, so it keeps a looser bound (it needed 48
 # cycles with full coarsening).
+# Blocks of disparate sizes (a 4- or 6-cell-wide block beside a 256- or
+# 512-cell one, a 4-cell block of half-width cells between two wide ones, an
+# 8 x 8 block below an 8 x 200 one): each class of blocks that share cells
+# across joined faces coarsens on its own, so the wide blocks go on
+# coarsening after the thin one has stopped, and the thin one merges its last
+# cells into one where that keeps its cells near square.  Three of these
+# planes were refused before (coarsest plane above 2048 cells).
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kind,zpair", [("thin_wide", "PP"), ("stacked", "NN"), ("sandwich", "DN"),
+                                        ("large", "DD")])
+def test_disparate_blocks(torch_cuda, mbp, kind, zpair, precision):
+    torch = torch_cuda
+    prob = W.disparate(kind, 8, zpair)
+    print(f"disparate {prob.name} {precision}", flush=True)
+    f = W.rhs(prob, 37)
+    ref = oracle.solve(prob, f)
+    fproj = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
+    plan = mbp.Plan(prob, precision=precision)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.PROJECT_RHS | mbp.RETIRE)
+    got = host(p)
+    res = oracle.rel_residual(prob, got, fproj)
+    err = oracle.rel_error(got, ref)
+    print(f"  {info} residual={res:.2e} error={err:.2e}", flush=True)
+    assert info.status == 0
+    assert res <= 1e-10
+    assert err <= 1e-9
+    assert info.cycles <= 30
+    plan.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("prob", _aniso_problems(), ids=lambda p: p.name)
 def test_anisotropic_semicoarsening(torch_cuda, mbp, prob, precision):

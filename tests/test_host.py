@@ -113,6 +113,16 @@ def test_plan_check_rejects_overlap_and_nonconforming(mbp):
     assert mbp.plan_check_status(W.Problem([A, D], 4, 1.0, W.PAIRS["PP"])) == mbp.OK
 
 
+@pytest.mark.parametrize("kind", ["thin_wide", "stacked", "sandwich", "large"])
+def test_plan_check_disparate_blocks(mbp, kind):
+    """A block too thin to follow its neighbours down the hierarchy stops
+    coarsening on its own (its class of blocks sharing cells across joined
+    faces), so the coarsest plane stays small instead of being refused."""
+    s = mbp.plan_check(W.disparate(kind))
+    assert s["coarse_cells"] <= 64
+    assert s["nlevels"] >= 4
+
+
 def test_plan_check_singular_flag(mbp):
     assert mbp.plan_check(W.box(8, 8, 4, 1, 1, 1, "NN", "NN", "PP"))["singular"]
     assert mbp.plan_check(W.box(8, 8, 4, 1, 1, 1, "PP", "PP", "NN"))["singular"]

@@ -181,6 +181,36 @@ def obstacle8(n: int = 64, nz: int = 576, lz_per_h: float = 9.0) -> Problem:
     return Problem(blocks=blocks, nz=nz, lz=lz, zbc=PAIRS["PP"], name=f"obstacle8_{n}perH_nz{nz}")
 
 
+def disparate(kind: str, nz: int = 8, zpair: str = "PP") -> Problem:
+    """Blocks of very different sizes joined along whole faces, square cells
+    of width 1/64 unless stated.  These are the layouts where one thin block
+    cannot follow its neighbours down the multigrid hierarchy.
+      "thin_wide":   a 4 x 64 block left of a 256 x 64 block (x faces joined);
+      "stacked":     an 8 x 8 block below an 8 x 200 block (y faces joined);
+      "sandwich":    128 x 96, 4 x 96 and 64 x 96 blocks side by side, the
+                     middle one with cells half as wide;
+      "large":       a 6 x 128 block left of a 512 x 128 block."""
+    D, N, C = DIRICHLET, NEUMANN, CONNECT
+    h = 1.0 / 64.0
+    if kind == "thin_wide":
+        blocks = [Block((1, 1), (4, 64), faces(4, 0.0, 4 * h), faces(64, 0.0, 1.0), (D, C, N, N)),
+                  Block((5, 1), (260, 64), faces(256, 4 * h, 260 * h), faces(64, 0.0, 1.0), (C, N, N, D))]
+    elif kind == "stacked":
+        blocks = [Block((1, 1), (8, 8), faces(8, 0.0, 8 * h), faces(8, 0.0, 8 * h), (D, N, N, C)),
+                  Block((1, 9), (8, 208), faces(8, 0.0, 8 * h), faces(200, 8 * h, 208 * h), (N, N, C, N))]
+    elif kind == "sandwich":
+        blocks = [Block((1, 1), (128, 96), faces(128, 0.0, 2.0), faces(96, 0.0, 1.5), (D, C, N, N)),
+                  Block((129, 1), (132, 96), faces(4, 2.0, 2.0 + 2 * h), faces(96, 0.0, 1.5), (C, C, N, N)),
+                  Block((133, 1), (196, 96), faces(64, 2.0 + 2 * h, 3.0 + 2 * h), faces(96, 0.0, 1.5),
+                        (C, N, D, N))]
+    elif kind == "large":
+        blocks = [Block((1, 1), (6, 128), faces(6, 0.0, 6 * h), faces(128, 0.0, 2.0), (N, C, N, N)),
+                  Block((7, 1), (518, 128), faces(512, 6 * h, 518 * h), faces(128, 0.0, 2.0), (C, D, N, N))]
+    else:
+        raise ValueError(kind)
+    return Problem(blocks=blocks, nz=nz, lz=0.5, zbc=PAIRS[zpair], name=f"disparate_{kind}_{zpair}_{nz}")
+
+
 def config2() -> Problem:
     return lshape(256, 512, 1.5, 2.0)
 
