@@ -476,3 +476,45 @@ def test_anisotropic_semicoarsening(torch_cuda, mbp, prob, precision):
     assert err <= 1e-9
     assert info.cycles <= 30
     plan.close()
+
+
+# The fused correcting sweep sums the squared residual of the red cells only
+# (the black cells were relaxed last, so their residual is zero up to
+# rounding).  Pin that shortcut on mid-cycle iterates: stop a lockstep FP64
+# solve after k V-cycles and compare the reported largest ratio
+# ||rhat_q|| / ||fhat_q|| with the same ratio taken by the oracle over every
+# cell of every mode of the returned field (Eq. (9) per mode, unweighted sums
+# over the plane as the solver's test uses).
+@pytest.mark.parametrize("prob", [W.box(192, 160, 16, 1.2, 1.0, 0.5, "DD", "NN", "NN", name="box192x160_DD_NN_NN"),
+                                  W.lshape(64, 16, 1.5, 1.0)], ids=lambda p: p.name)
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_fused_norm_mid_cycle(torch_cuda, mbp, prob, k):
+    import scipy.sparse as sp
+    from oracle.solve import _geom
+    from oracle.operator import assemble_2d
+    from oracle.transforms import eigenvalues
+    torch = torch_cuda
+    print(f"fused norm {prob.name} k={k}", flush=True)
+    f = W.rhs(prob, 71)
+    singular = oracle.is_singular(prob)
+    fproj = oracle.project_compatible(prob, f) if singular else f
+    plan = mbp.Plan(prob, max_cycles=k)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, rtol=1e-14, flags=mbp.PROJECT_RHS if singular else 0,
+                      raise_on_error=False)
+    assert info.status == mbp.ERR_NOT_CONVERGED and info.cycles == k, info
+    plan.close()
+    g = _geom(prob)
+    qs = range(prob.nz)
+    ph = oracle.modal_rhs(prob, host(p), qs)  # the same contraction applied to the field
+    fh = oracle.modal_rhs(prob, fproj, qs)
+    A2 = assemble_2d(g)
+    lam = eigenvalues(g.zkind, g.nz) / (g.dz * g.dz)
+    ratios = []
+    for q in qs:
+        r = fh[q] - (A2 @ ph[q] + lam[q] * ph[q])
+        ratios.append(np.linalg.norm(r) / np.linalg.norm(fh[q]))
+    worst = max(ratios)
+    print(f"  {info} oracle max ratio {worst:.6e}", flush=True)
+    assert worst > 1e-8  # a genuine mid-cycle iterate
+    assert abs(info.rel_residual - worst) <= 1e-6 * worst
