@@ -281,6 +281,8 @@ void launch_plane_norm(const mbp_plan* P, const double* f, double* out, hipStrea
 void launch_update_active(const mbp_plan* P, double rtol2, double etol2, int retire, int maxc,
                           hipStream_t s, double* out = nullptr);
 void launch_zero(double* p, size_t n, hipStream_t s);
+void launch_zero_unrelaxed(const mbp_plan* P, double* p, hipStream_t s);  // modes with cyc == 0
+bool vcycle_zero_start_reads_none(const mbp_plan* P);
 void launch_zero32(float* p, size_t n, hipStream_t s);
 void launch_singular_fix(const mbp_plan* P, double* plane, double* out_mean, hipStream_t s);
 
@@ -309,6 +311,8 @@ struct SolveCtx {
     int fused_parts = 0;  // partials left by the last V-cycle (0: explicit residual)
     int cycles = 0;       // V-cycles launched so far
     bool done = false;
+    bool lazy_zero = false;  // p is not zeroed up front: the planes of modes no V-cycle
+                             // relaxed are zeroed before the inverse transform
 };
 void ctx_init(SolveCtx& c, mbp_plan* P, const double* rhs, double* p, double rtol, int flags);
 void ctx_prologue(SolveCtx& c, hipStream_t s);  // ends with an async readback of the checks

@@ -560,9 +560,23 @@ __global__ void k_fill_int(int* p, int n, int v) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
 }
 
-__global__ void k_iota(int* act, int n, int* nact) {
-    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) act[i] = i;
+__global__ void k_iota(int* act, int n, int* nact, int* cyc) {
+    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) {
+        act[i] = i;
+        cyc[i] = 0;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) *nact = n;
+}
+
+// Zero the planes of the modes that no V-cycle relaxed (cyc[q] == 0: they
+// passed the test before the first cycle); the others were all written.
+__global__ void k_zero_unrelaxed(double* __restrict__ p, long long plane, const int* __restrict__ cyc) {
+    const int q = blockIdx.y;
+    if (cyc[q] != 0) return;
+    double* pq = p + q * plane;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < plane;
+         i += (long long)gridDim.x * blockDim.x)
+        pq[i] = 0.0;
 }
 
 // sum(a x) over one plane (single workgroup, fixed order).
@@ -1341,7 +1355,23 @@ void launch_update_active(const mbp_plan* P, double rtol2, double etol2, int ret
 }
 
 void launch_reset_active(const mbp_plan* P, hipStream_t s) {
-    hipLaunchKernelGGL(k_iota, dim3(1), dim3(1024), 0, s, P->d_act, P->g.nz, P->d_nact);
+    hipLaunchKernelGGL(k_iota, dim3(1), dim3(1024), 0, s, P->d_act, P->g.nz, P->d_nact, P->d_cyc);
+}
+
+void launch_zero_unrelaxed(const mbp_plan* P, double* p, hipStream_t s) {
+    const int chunks = int(std::min<long long>(64, (P->plane0 + 1023) / 1024));
+    hipLaunchKernelGGL(k_zero_unrelaxed, dim3(chunks, P->g.nz), dim3(256), 0, s, p, (long long)P->plane0,
+                       P->d_cyc);
+}
+
+// The first V-cycle from a zero iterate reads no finest-level p: its first
+// sweep is a fused strip sweep that takes the old iterate as zero (the
+// residual test before it uses f itself).  The V-cycle then writes p of
+// every active mode.
+bool vcycle_zero_start_reads_none(const mbp_plan* P) {
+    const int nu1 = P->opt.nu1, nu2 = P->opt.nu2;
+    const bool fused_ok = ((nu1 + nu2) % 2 == 0) && nu1 >= 1 && nu2 >= 1;
+    return P->lds_level > 0 && fused_ok && !P->march_ok.empty() && P->march_ok[0] && P->phatB != nullptr;
 }
 
 void launch_fill_int(int* p, int n, int v, hipStream_t s) {

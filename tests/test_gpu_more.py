@@ -150,3 +150,31 @@ def test_batch_per_problem_form(torch_cuda, mbp):
     fs, got, singles, infos, sched = _run_batch(torch_cuda, mbp, probs, 800)
     assert sched is not None and sched[0] > 0, sched
     _check_all(probs, fs, got, singles, infos)
+
+
+# Modes that pass the test before the first V-cycle are never relaxed; their
+# modal solution must be zero even when the plan's buffers still hold a
+# previous solve (the retiring FP64 solve does not zero the whole modal field
+# up front, only these planes at the end).  A zero right-hand side makes every
+# mode pass at once; the solve after it must be unaffected.
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_unrelaxed_modes_zero(torch_cuda, mbp, precision):
+    torch = torch_cuda
+    prob = W.box(128, 96, 16, 1.0, 0.75, 0.5, "DD", "NN", "NN", name="box128x96_DD_NN_NN")
+    plan = mbp.Plan(prob, precision=precision)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    f1 = W.rhs(prob, 81)
+    assert plan.solve(dev(torch, f1), p, rtol=1e-10, flags=mbp.RETIRE).status == 0
+    p.fill_(7.0)
+    info0 = plan.solve(dev(torch, np.zeros_like(f1)), p, rtol=1e-10, flags=mbp.RETIRE)
+    assert info0.status == 0 and info0.cycles == 0, info0
+    assert float(p.abs().max()) == 0.0
+    f2 = W.rhs(prob, 82)
+    p.fill_(7.0)
+    info2 = plan.solve(dev(torch, f2), p, rtol=1e-10, flags=mbp.RETIRE)
+    got = host(p)
+    res = oracle.rel_residual(prob, got, f2)
+    err = oracle.rel_error(got, oracle.solve(prob, f2))
+    print(f"  {precision}: {info2} residual={res:.2e} error={err:.2e}", flush=True)
+    assert info2.status == 0 and res <= 1e-10 and err <= 1e-9
+    plan.close()
