@@ -75,7 +75,11 @@ def _vcycle_bytes_per_point(w: float, nu1: int = 1, nu2: int = 1) -> float:
     return ((nu1 + nu2) * 3.0 + 4.5) * w * 4.0 / 3.0
 
 
-def _mode_cycle_bytes(precision: str, inner: int = 2) -> float:
+MIXED_INNER = 4  # FP32 V-cycles per refinement step (the library's default)
+SERVE_INNER = 2  # the same inside a server (its default)
+
+
+def _mode_cycle_bytes(precision: str, inner: int = MIXED_INNER) -> float:
     """Method bytes per plane point and convergence step of one mode.
     FP64: one V-cycle.  Mixed: FP64 residual to FP32 (read p, f; write r:
     20 B), `inner` FP32 V-cycles, FP64 accumulation (read e, p; write p: 20 B)."""
@@ -87,9 +91,9 @@ def _mode_cycle_bytes(precision: str, inner: int = 2) -> float:
 TRANSFORM_BYTES = 32.0  # forward + inverse z transform, FP64 read + write
 
 
-def _solve_bytes(prob, cycles_per_mode, precision) -> float:
+def _solve_bytes(prob, cycles_per_mode, precision, inner: int = MIXED_INNER) -> float:
     plane = prob.ncells // prob.nz
-    return prob.ncells * TRANSFORM_BYTES + float(np.sum(cycles_per_mode)) * plane * _mode_cycle_bytes(precision)
+    return prob.ncells * TRANSFORM_BYTES + float(np.sum(cycles_per_mode)) * plane * _mode_cycle_bytes(precision, inner)
 
 
 # ---------------------------------------------------------------------------
@@ -480,8 +484,9 @@ def bench_batch(args, torch, mbp, with_cpu=True):
                      "achieved": round(bytes_step / t_fast / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(bytes_step / t_fast / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_step": bytes_step,
-                     "bytes_model": "32 B/cell transforms + per mode and refinement step 20 + 2 x 56 + 20 B "
-                                    "per plane point (FP64 residual, two FP32 V-cycles, FP64 accumulation)"},
+                     "bytes_model": f"32 B/cell transforms + per mode and refinement step 20 + {MIXED_INNER} x 56 + "
+                                    f"20 B per plane point (FP64 residual, {MIXED_INNER} FP32 V-cycles, FP64 "
+                                    "accumulation)"},
     }
     if with_cpu:
         log("batch64: cpu baseline (oracle, separable route)")
@@ -544,7 +549,7 @@ def bench_serve(args, torch, mbp, with_cpu=True):
     # method bytes of the capacity run: each request's transforms and mode cycles
     nbytes = 0.0
     for p, (_, inf, _) in zip(probs, res_cap):
-        nbytes += _solve_bytes(p, inf.cycles_per_mode, "mixed")
+        nbytes += _solve_bytes(p, inf.cycles_per_mode, "mixed", SERVE_INNER)
     del rhs, outs
     torch.cuda.empty_cache()
     rec = {
@@ -571,8 +576,8 @@ def bench_serve(args, torch, mbp, with_cpu=True):
                      "achieved": round(nbytes / t_cap / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(nbytes / t_cap / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_model": "per request: 32 B/cell transforms + per mode and refinement step "
-                                    "20 + 2 x 56 + 20 B per plane point (FP64 residual, two FP32 V-cycles, "
-                                    "FP64 accumulation)"},
+                                    f"20 + {SERVE_INNER} x 56 + 20 B per plane point (FP64 residual, "
+                                    f"{SERVE_INNER} FP32 V-cycles, FP64 accumulation)"},
     }
     if with_cpu:
         log("serve: cpu baseline (oracle, separable route)")

@@ -116,7 +116,7 @@ typedef struct {
  *              negative = off                                    [0]
  *   inner      MBP_MIXED: FP32 V-cycles per FP64 refinement step
  *              (residual in FP64, correction solved in FP32, added in
- *              FP64); 0 = default                                [2]
+ *              FP64); 0 = default                [4; 2 in a server]
  *   march      pre-smoothing form of the fused levels: 0 LDS strip
  *              tiles, 1 register march (mbp_plan_autotune may change
  *              it per level)                                     [0]

@@ -19,7 +19,7 @@ void options_default(mbp_options* o) {
     o->max_cycles = 60;
     o->flags = 0;
     o->etol = 0.0;
-    o->inner = 2;
+    o->inner = 4;
     o->march = 0;
     o->smoother = MBP_SMOOTHER_DEFAULT;
     o->helmholtz = 0.0;
@@ -288,7 +288,7 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
             if (err) *err = "bad smoothing counts or max_cycles";
             return MBP_ERR_INVALID;
         }
-        if (P->opt.inner == 0) P->opt.inner = 2;
+        if (P->opt.inner == 0) P->opt.inner = 4;
         if (P->opt.inner < 1 || P->opt.inner > 8) {
             if (err) *err = "bad inner cycle count";
             return MBP_ERR_INVALID;

@@ -373,6 +373,10 @@ int mbp_server_create(size_t hbm_budget, int slots, const mbp_options* opt, mbp_
     S->slots = slots;
     if (opt) S->opt = *opt;
     else options_default(&S->opt);
+    // served requests are solved one per slot, most of them small: there two
+    // FP32 V-cycles per refinement step measured faster than the four that
+    // single and batched solves default to (finer retirement per step)
+    if (S->opt.inner == 0 || !opt) S->opt.inner = 2;
     int lds = 65536;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds = 65536;
     S->lds_limit = lds;
