@@ -174,10 +174,10 @@ typedef struct {
 typedef struct mbp_plan mbp_plan;
 typedef struct mbp_server mbp_server;
 
-/* Static text for a status code. */
+/* Static text for a status code (library plumbing; no passage of the paper). */
 const char* mbp_status_string(int status);
 
-/* ABI version (major*100 + minor). */
+/* ABI version (major*100 + minor; library plumbing). */
 int mbp_version(void);
 
 /* Face coordinates of a hyperbolic-tangent clustered 1D grid (Sec. 3.1,
@@ -188,14 +188,17 @@ int mbp_version(void);
 int mbp_grid_tanh(int n, double lmin, double lmax, int type, double factor, double* faces_out);
 
 /* Validate a problem and describe the plan it would build, on the host only
- * (no HIP call, no allocation on the device).  Same errors as
- * mbp_plan_create's validation; out may be NULL. */
+ * (no HIP call, no allocation on the device): the checks of the problem
+ * statement of Sec. 3.1 and Table 2 (blocks, faces, conditions) and the
+ * Sec. 3.3.1 multigrid hierarchy.  Same errors as mbp_plan_create's
+ * validation; out may be NULL. */
 int mbp_plan_check(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* z,
                    const mbp_options* opt, mbp_plan_summary* out);
 
-/* Build a plan on the current HIP device: validation, connectivity, grid
- * metrics per multigrid level, modal shifts lambda_q / dz^2, transform
- * tables, the coarsest-level eigen-decomposition, device workspace.
+/* Build a plan on the current HIP device (the set-up of Algorithm 1 for the
+ * problem of Sec. 3.1 / Table 2): validation, connectivity, grid metrics per
+ * multigrid level, modal shifts lambda_q / dz^2 (Table 1, Eq. (9)),
+ * transform tables, the coarsest-level eigen-decomposition, device workspace.
  * Blocking.  The plan owns its device memory.  Errors: MBP_ERR_INVALID
  * (odd or < 2 nz, invalid pair, non-congruent or partial interface, a face
  * with two neighbours, overlapping blocks, bad faces), MBP_ERR_NOMEM,
@@ -211,9 +214,9 @@ int mbp_plan_create(const mbp_block_desc* blocks, int nblocks, const mbp_synth_d
  * (NULL plan, alpha < 0 or not finite), MBP_ERR_BUSY, MBP_ERR_HIP. */
 int mbp_plan_set_helmholtz(mbp_plan* plan, double alpha);
 
-/* Layout query.  block_offsets (nblocks+1 int64, may be NULL): element
- * offsets of each block in the packed field; workspace_bytes and singular
- * may be NULL. */
+/* Layout query (the packed field layout is this library's own; no passage).
+ * block_offsets (nblocks+1 int64, may be NULL): element offsets of each
+ * block in the packed field; workspace_bytes and singular may be NULL. */
 int mbp_plan_layout(const mbp_plan* plan, int64_t* block_offsets, size_t* workspace_bytes,
                     int* singular);
 
@@ -254,7 +257,8 @@ int mbp_solve(mbp_plan* plan, const double* rhs_dev, double* p_dev, double rtol,
 int mbp_solve_batch(mbp_plan* const* plans, const double* const* rhs_dev, double* const* p_dev,
                     int count, double rtol, int flags, void* stream, mbp_solve_info* infos);
 
-/* Schedule the batch autotuner chose for this plan set: MBP_OK with the
+/* Schedule the batch autotuner chose for this plan set (the batched form is
+ * this library's; the paper solves one problem at a time): MBP_OK with the
  * stream count and cycles per replay, or MBP_PENDING if none is cached.
  * streams is 0 when every replay of the last batch of this plan set ran in
  * the grouped form. */
@@ -378,8 +382,8 @@ typedef struct {
 } mbp_tuning;
 int mbp_plan_autotune(mbp_plan* plan, const double* rhs_dev, void* stream, mbp_tuning* out);
 
-/* Release the plan's device memory.  The caller ensures no work is in
- * flight on it.  NULL is ignored. */
+/* Release the plan's device memory (library plumbing).  The caller ensures
+ * no work is in flight on it.  NULL is ignored. */
 void mbp_plan_destroy(mbp_plan* plan);
 
 /* ---- 3D multigrid without the z synthesis ----------------------------- */
@@ -426,7 +430,9 @@ int mbp3_solve(mbp3_plan* plan, const double* rhs_dev, double* p_dev, double rto
 void mbp3_plan_destroy(mbp3_plan* plan);
 
 /* ---- serving loop ------------------------------------------------------- */
-/* A server admits solve requests of any size and conditions, keeps plans
+/* The serving form is this library's own (the paper runs one problem per
+ * job); each request is the solve of Algorithm 1.
+ * A server admits solve requests of any size and conditions, keeps plans
  * (hierarchies, tables, workspaces) resident in an LRU cache keyed by the
  * descriptor, and runs up to `slots` requests concurrently on their own HIP
  * streams: a request that arrives while others run starts as soon as a slot
