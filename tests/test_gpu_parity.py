@@ -420,14 +420,15 @@ def _aniso_problems():
 
 # Blocks of disparate sizes (a 4- or 6-cell-wide block beside a 256- or
 # 512-cell one, a 4-cell block of half-width cells between two wide ones, an
-# 8 x 8 block below an 8 x 200 one): each class of blocks that share cells
+# 8 x 8 block below an 8 x 200 one, a 1- or 2-cell sliver between two 64 x 64
+# blocks on the finest grid): each class of blocks that share cells
 # across joined faces coarsens on its own, so the wide blocks go on
 # coarsening after the thin one has stopped, and the thin one merges its last
 # cells into one where that keeps its cells near square.  Three of these
 # planes were refused before (coarsest plane above 2048 cells).
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("kind,zpair", [("thin_wide", "PP"), ("stacked", "NN"), ("sandwich", "DN"),
-                                        ("large", "DD")])
+                                        ("large", "DD"), ("sliver1", "NN"), ("sliver2", "ND")])
 def test_disparate_blocks(torch_cuda, mbp, kind, zpair, precision):
     torch = torch_cuda
     prob = W.disparate(kind, 8, zpair)

@@ -113,7 +113,7 @@ def test_plan_check_rejects_overlap_and_nonconforming(mbp):
     assert mbp.plan_check_status(W.Problem([A, D], 4, 1.0, W.PAIRS["PP"])) == mbp.OK
 
 
-@pytest.mark.parametrize("kind", ["thin_wide", "stacked", "sandwich", "large"])
+@pytest.mark.parametrize("kind", ["thin_wide", "stacked", "sandwich", "large", "sliver1", "sliver2"])
 def test_plan_check_disparate_blocks(mbp, kind):
     """A block too thin to follow its neighbours down the hierarchy stops
     coarsening on its own (its class of blocks sharing cells across joined

@@ -189,7 +189,9 @@ def disparate(kind: str, nz: int = 8, zpair: str = "PP") -> Problem:
       "stacked":     an 8 x 8 block below an 8 x 200 block (y faces joined);
       "sandwich":    128 x 96, 4 x 96 and 64 x 96 blocks side by side, the
                      middle one with cells half as wide;
-      "large":       a 6 x 128 block left of a 512 x 128 block."""
+      "large":       a 6 x 128 block left of a 512 x 128 block;
+      "sliver1", "sliver2": a 1- or 2-cell-wide block between two 64 x 64
+                     blocks (x faces joined)."""
     D, N, C = DIRICHLET, NEUMANN, CONNECT
     h = 1.0 / 64.0
     if kind == "thin_wide":
@@ -206,6 +208,12 @@ def disparate(kind: str, nz: int = 8, zpair: str = "PP") -> Problem:
     elif kind == "large":
         blocks = [Block((1, 1), (6, 128), faces(6, 0.0, 6 * h), faces(128, 0.0, 2.0), (N, C, N, N)),
                   Block((7, 1), (518, 128), faces(512, 6 * h, 518 * h), faces(128, 0.0, 2.0), (C, D, N, N))]
+    elif kind in ("sliver1", "sliver2"):
+        w = 1 if kind == "sliver1" else 2
+        blocks = [Block((1, 1), (64, 64), faces(64, 0.0, 1.0), faces(64, 0.0, 1.0), (D, C, N, N)),
+                  Block((65, 1), (64 + w, 64), faces(w, 1.0, 1.0 + w * h), faces(64, 0.0, 1.0), (C, C, N, N)),
+                  Block((65 + w, 1), (128 + w, 64), faces(64, 1.0 + w * h, 2.0 + w * h), faces(64, 0.0, 1.0),
+                        (C, N, N, D))]
     else:
         raise ValueError(kind)
     return Problem(blocks=blocks, nz=nz, lz=0.5, zbc=PAIRS[zpair], name=f"disparate_{kind}_{zpair}_{nz}")
