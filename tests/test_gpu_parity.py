@@ -519,3 +519,36 @@ def test_fused_norm_mid_cycle(torch_cuda, mbp, prob, k):
     print(f"  {info} oracle max ratio {worst:.6e}", flush=True)
     assert worst > 1e-8  # a genuine mid-cycle iterate
     assert abs(info.rel_residual - worst) <= 1e-6 * worst
+
+
+# The smallest problems: two z cells (every Table 1 pair), planes of 2 x 2 to
+# 8 x 6 cells (one multigrid level, or a hierarchy that ends after one step,
+# so the whole solve runs in one workgroup's LDS), singular ones included.
+def _tiny_problems():
+    out = []
+    for i, zk in enumerate(KINDS):
+        xp, yp = KINDS[(i + 1) % 5], KINDS[(i + 3) % 5]
+        out.append(W.box(8, 6, 2, 1.0, 0.75, 0.25, xp, yp, zk, name=f"box8x6x2_{xp}_{yp}_{zk}"))
+    out.append(W.box(2, 2, 2, 1.0, 1.0, 1.0, "NN", "NN", "PP", name="box2x2x2_NN_NN_PP"))
+    out.append(W.box(3, 5, 4, 0.3, 0.5, 0.4, "DD", "PP", "NN", name="box3x5x4_DD_PP_NN"))
+    out.append(W.box(4, 4, 2, 1.0, 1.0, 0.5, "NN", "NN", "NN", name="box4x4x2_NN_NN_NN"))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("prob", _tiny_problems(), ids=lambda p: p.name)
+def test_tiny_problems(torch_cuda, mbp, prob, precision):
+    torch = torch_cuda
+    print(f"tiny {prob.name} {precision}", flush=True)
+    f = W.rhs(prob, 91)
+    ref = oracle.solve(prob, f)
+    fproj = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
+    plan = mbp.Plan(prob, precision=precision)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.PROJECT_RHS | mbp.RETIRE)
+    got = host(p)
+    res = oracle.rel_residual(prob, got, fproj)
+    err = oracle.rel_error(got, ref)
+    print(f"  {info} residual={res:.2e} error={err:.2e}", flush=True)
+    assert info.status == 0 and res <= 1e-10 and err <= 1e-9
+    plan.close()
