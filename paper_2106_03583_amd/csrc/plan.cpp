@@ -361,86 +361,103 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
             ycls[b] = find(ycls, b);
         }
     }
-    P->levels.clear();
-    {
-        Level L;
-        L.nb = nb;
-        L.nx = g.nx;
-        L.ny = g.ny;
-        L.xf = g.xf;
-        L.yf = g.yf;
-        P->levels.push_back(L);
-    }
-    while (P->levels.size() < 24) {
-        Level& F = P->levels.back();
-        double wx = 0.0, wy = 0.0;
-        int64_t cellsx = 0, cellsy = 0;
-        // per class (indexed by its representative): every block has at
-        // least 4 cells along the direction (halve), or 2-3 (merge into one
-        // cell, taken only while another class halves that direction, so a
-        // thin block follows its neighbours one step further)
-        std::vector<char> canx(nb, 1), cany(nb, 1), mrgx(nb, 1), mrgy(nb, 1);
-        for (int b = 0; b < nb; ++b) {
-            if (F.nx[b] < 4) canx[xcls[b]] = 0;
-            if (F.ny[b] < 4) cany[ycls[b]] = 0;
-            // (a periodic wrap keeps at least two cells)
-            if (F.nx[b] < 2 || g.bc[b][XM] == MBP_PERIODIC || g.bc[b][XP] == MBP_PERIODIC) mrgx[xcls[b]] = 0;
-            if (F.ny[b] < 2 || g.bc[b][YM] == MBP_PERIODIC || g.bc[b][YP] == MBP_PERIODIC) mrgy[ycls[b]] = 0;
-            wx += F.xf[b].back() - F.xf[b].front();
-            wy += F.yf[b].back() - F.yf[b].front();
-            cellsx += F.nx[b];
-            cellsy += F.ny[b];
+    auto build_levels = [&](bool uniform) {
+        P->levels.clear();
+        {
+            Level L;
+            L.nb = nb;
+            L.nx = g.nx;
+            L.ny = g.ny;
+            L.xf = g.xf;
+            L.yf = g.yf;
+            P->levels.push_back(L);
         }
-        const double hx = wx / double(cellsx), hy = wy / double(cellsy);
-        // halving the smaller width alone brings the ratio closer to 1 once
-        // it exceeds sqrt(2)
-        const double r2 = 0.70710678118654752440;
-        const bool dirx = !(hy < r2 * hx), diry = !(hx < r2 * hy);
-        bool halvex = false, halvey = false;
-        for (int b = 0; b < nb; ++b) {
-            halvex = halvex || (dirx && canx[xcls[b]]);
-            halvey = halvey || (diry && cany[ycls[b]]);
+        while (P->levels.size() < 24) {
+            Level& F = P->levels.back();
+            double wx = 0.0, wy = 0.0;
+            int64_t cellsx = 0, cellsy = 0;
+            // per class (indexed by its representative): every block has at
+            // least 4 cells along the direction (halve), or 2-3 (merge into one
+            // cell, taken only while another class halves that direction, so a
+            // thin block follows its neighbours one step further)
+            std::vector<char> canx(nb, 1), cany(nb, 1), mrgx(nb, 1), mrgy(nb, 1);
+            for (int b = 0; b < nb; ++b) {
+                if (F.nx[b] < 4) canx[xcls[b]] = 0;
+                if (F.ny[b] < 4) cany[ycls[b]] = 0;
+                // (a periodic wrap keeps at least two cells)
+                if (F.nx[b] < 2 || g.bc[b][XM] == MBP_PERIODIC || g.bc[b][XP] == MBP_PERIODIC) mrgx[xcls[b]] = 0;
+                if (F.ny[b] < 2 || g.bc[b][YM] == MBP_PERIODIC || g.bc[b][YP] == MBP_PERIODIC) mrgy[ycls[b]] = 0;
+                wx += F.xf[b].back() - F.xf[b].front();
+                wy += F.yf[b].back() - F.yf[b].front();
+                cellsx += F.nx[b];
+                cellsy += F.ny[b];
+            }
+            const double hx = wx / double(cellsx), hy = wy / double(cellsy);
+            // halving the smaller width alone brings the ratio closer to 1 once
+            // it exceeds sqrt(2)
+            const double r2 = 0.70710678118654752440;
+            const bool dirx = !(hy < r2 * hx), diry = !(hx < r2 * hy);
+            bool halvex = false, halvey = false;
+            for (int b = 0; b < nb; ++b) {
+                halvex = halvex || (dirx && canx[xcls[b]]);
+                halvey = halvey || (diry && cany[ycls[b]]);
+            }
+            // a merge must leave the block's cells no more anisotropic than
+            // they would be without it: the merged direction has to be the
+            // block's strongly coupled one (width below the other direction's
+            // next-level width over sqrt(2)), as the direction rule itself asks
+            for (int b = 0; b < nb; ++b) {
+                const double wxb = (F.xf[b].back() - F.xf[b].front()) / F.nx[b];
+                const double wyb = (F.yf[b].back() - F.yf[b].front()) / F.ny[b];
+                const double wxn = (dirx && canx[xcls[b]]) ? 2.0 * wxb : wxb;
+                const double wyn = (diry && cany[ycls[b]]) ? 2.0 * wyb : wyb;
+                if (!(wxb < r2 * wyn)) mrgx[xcls[b]] = 0;
+                if (!(wyb < r2 * wxn)) mrgy[ycls[b]] = 0;
+            }
+            std::vector<char> bx(nb), by(nb);
+            bool any = false, allx = true, ally = true;
+            for (int b = 0; b < nb; ++b) {
+                const bool hxb = dirx && canx[xcls[b]], hyb = diry && cany[ycls[b]];
+                bx[b] = hxb || (!uniform && halvex && !canx[xcls[b]] && mrgx[xcls[b]]);
+                by[b] = hyb || (!uniform && halvey && !cany[ycls[b]] && mrgy[ycls[b]]);
+                any = any || bx[b] || by[b];
+                allx = allx && hxb;
+                ally = ally && hyb;
+            }
+            if (!any) break;
+            if (uniform && ((dirx && !allx) || (diry && !ally))) break;
+            F.cx = allx ? 1 : 0;
+            F.cy = ally ? 1 : 0;
+            Level C;
+            C.nb = nb;
+            C.nx.resize(nb);
+            C.ny.resize(nb);
+            C.xf.resize(nb);
+            C.yf.resize(nb);
+            for (int b = 0; b < nb; ++b) {
+                C.xf[b] = bx[b] ? coarsen_faces(F.xf[b]) : F.xf[b];
+                C.yf[b] = by[b] ? coarsen_faces(F.yf[b]) : F.yf[b];
+                C.nx[b] = int(C.xf[b].size()) - 1;
+                C.ny[b] = int(C.yf[b].size()) - 1;
+            }
+            P->levels.push_back(C);
         }
-        // a merge must leave the block's cells no more anisotropic than
-        // they would be without it: the merged direction has to be the
-        // block's strongly coupled one (width below the other direction's
-        // next-level width over sqrt(2)), as the direction rule itself asks
-        for (int b = 0; b < nb; ++b) {
-            const double wxb = (F.xf[b].back() - F.xf[b].front()) / F.nx[b];
-            const double wyb = (F.yf[b].back() - F.yf[b].front()) / F.ny[b];
-            const double wxn = (dirx && canx[xcls[b]]) ? 2.0 * wxb : wxb;
-            const double wyn = (diry && cany[ycls[b]]) ? 2.0 * wyb : wyb;
-            if (!(wxb < r2 * wyn)) mrgx[xcls[b]] = 0;
-            if (!(wyb < r2 * wxn)) mrgy[ycls[b]] = 0;
-        }
-        std::vector<char> bx(nb), by(nb);
-        bool any = false, allx = true, ally = true;
-        for (int b = 0; b < nb; ++b) {
-            const bool hxb = dirx && canx[xcls[b]], hyb = diry && cany[ycls[b]];
-            bx[b] = hxb || (!uniform_levels && halvex && !canx[xcls[b]] && mrgx[xcls[b]]);
-            by[b] = hyb || (!uniform_levels && halvey && !cany[ycls[b]] && mrgy[ycls[b]]);
-            any = any || bx[b] || by[b];
-            allx = allx && hxb;
-            ally = ally && hyb;
-        }
-        if (!any) break;
-        if (uniform_levels && ((dirx && !allx) || (diry && !ally))) break;
-        F.cx = allx ? 1 : 0;
-        F.cy = ally ? 1 : 0;
-        Level C;
-        C.nb = nb;
-        C.nx.resize(nb);
-        C.ny.resize(nb);
-        C.xf.resize(nb);
-        C.yf.resize(nb);
-        for (int b = 0; b < nb; ++b) {
-            C.xf[b] = bx[b] ? coarsen_faces(F.xf[b]) : F.xf[b];
-            C.yf[b] = by[b] ? coarsen_faces(F.yf[b]) : F.yf[b];
-            C.nx[b] = int(C.xf[b].size()) - 1;
-            C.ny[b] = int(C.yf[b].size()) - 1;
-        }
-        P->levels.push_back(C);
-    }
+    };
+    // Every block takes each step (the hierarchy ends when one block cannot)
+    // unless that leaves more than 256 coarsest cells: then each class of
+    // blocks steps on its own.  Per-class steps converge slower on layouts
+    // whose thin blocks stay one or two cells wide while their neighbours
+    // coarsen (a one-cell L-shaped pair even diverged where uniform steps
+    // left 73 coarsest cells), while a large coarsest plane costs the plan
+    // an O(n^3) eigen-decomposition (seconds at a few hundred cells, minutes
+    // near 2048).
+    auto coarsest = [&]() {
+        int64_t cells = 0;
+        for (int b = 0; b < nb; ++b) cells += int64_t(P->levels.back().nx[b]) * P->levels.back().ny[b];
+        return cells;
+    };
+    build_levels(true);
+    if (!uniform_levels && coarsest() > 256) build_levels(false);
     P->nlev = int(P->levels.size());
     for (Level& L : P->levels) {
         L.off.resize(nb + 1);
@@ -663,12 +680,15 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
                         if (w == 0.0) return;
                         int bb = b;
                         if (ii < 0 || ii >= d.nx || jj < 0 || jj >= d.ny) {
+                            // the partner's last / first column or row; the
+                            // tests read the original index (the partner may
+                            // be longer along the crossed direction)
                             bb = g.nbr[b][f];
                             const DBlock& e = P->hblk[L.blk_off + bb];
                             if (ii < 0) ii = e.nx - 1;
-                            if (ii >= d.nx) ii = 0;
+                            else if (ii >= d.nx) ii = 0;
                             if (jj < 0) jj = e.ny - 1;
-                            if (jj >= d.ny) jj = 0;
+                            else if (jj >= d.ny) jj = 0;
                         }
                         const DBlock& e = P->hblk[L.blk_off + bb];
                         A[size_t(c) * nc + (e.off + jj * e.nx + ii)] += w;
@@ -679,11 +699,22 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
                     addnb(YP, cy[d.ny + j], i, j + 1);
                 }
         }
-        // S = diag(a)^(1/2) A diag(a)^(-1/2) is symmetric
+        // S = diag(a)^(1/2) A diag(a)^(-1/2) is symmetric (the fluxes of the
+        // finite-volume operator); check it, so that a wrong coupling cannot
+        // hide behind the symmetrisation below
         std::vector<double> S(size_t(nc) * nc);
+        double smax = 0.0;
         for (int r = 0; r < nc; ++r)
-            for (int c = 0; c < nc; ++c)
+            for (int c = 0; c < nc; ++c) {
                 S[size_t(r) * nc + c] = std::sqrt(area[r]) * A[size_t(r) * nc + c] / std::sqrt(area[c]);
+                smax = std::max(smax, std::fabs(S[size_t(r) * nc + c]));
+            }
+        for (int r = 0; r < nc; ++r)
+            for (int c = r + 1; c < nc; ++c)
+                if (std::fabs(S[size_t(r) * nc + c] - S[size_t(c) * nc + r]) > 1e-10 * smax) {
+                    if (err) *err = "internal: coarsest-plane operator is not symmetric";
+                    return MBP_ERR_INVALID;
+                }
         for (int r = 0; r < nc; ++r)
             for (int c = r + 1; c < nc; ++c) {
                 double m = 0.5 * (S[size_t(r) * nc + c] + S[size_t(c) * nc + r]);

@@ -421,11 +421,13 @@ def _aniso_problems():
 # Blocks of disparate sizes (a 4- or 6-cell-wide block beside a 256- or
 # 512-cell one, a 4-cell block of half-width cells between two wide ones, an
 # 8 x 8 block below an 8 x 200 one, a 1- or 2-cell sliver between two 64 x 64
-# blocks on the finest grid): each class of blocks that share cells
-# across joined faces coarsens on its own, so the wide blocks go on
-# coarsening after the thin one has stopped, and the thin one merges its last
-# cells into one where that keeps its cells near square.  Three of these
-# planes were refused before (coarsest plane above 2048 cells).
+# blocks on the finest grid).  Where uniform steps would leave more than 256
+# coarsest cells, each class of blocks that share cells across joined faces
+# coarsens on its own, so the wide blocks go on coarsening after the thin one
+# has stopped, and the thin one merges its last cells into one where that
+# keeps its cells near square.  Five of these planes were refused before
+# (coarsest plane above 2048 cells).  The 1-cell sliver cannot merge: its
+# cells reach aspect 32 on the coarse levels, and it keeps a looser bound.
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("kind,zpair", [("thin_wide", "PP"), ("stacked", "NN"), ("sandwich", "DN"),
                                         ("large", "DD"), ("sliver1", "NN"), ("sliver2", "ND")])
@@ -446,7 +448,7 @@ def test_disparate_blocks(torch_cuda, mbp, kind, zpair, precision):
     assert info.status == 0
     assert res <= 1e-10
     assert err <= 1e-9
-    assert info.cycles <= 30
+    assert info.cycles <= (40 if kind == "sliver1" else 30)
     plan.close()
 
 
@@ -455,8 +457,7 @@ def test_disparate_blocks(torch_cuda, mbp, kind, zpair, precision):
 # point red-black smoothing then keeps its rate (cycles stay <= 30).  The
 # last layout mixes a uniform block of 0.01-wide cells with a stretched one
 # (cell aspect 1.3 to 2.9 across the plane); it needed 48 cycles with full
-# coarsening and 34 with one direction rule for the whole plane, and takes
-# 22 with each class of blocks coarsening on its own.
+# coarsening and takes about 24 with semicoarsening.
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("prob", _aniso_problems(), ids=lambda p: p.name)
 def test_anisotropic_semicoarsening(torch_cuda, mbp, prob, precision):
@@ -541,6 +542,30 @@ def test_tiny_problems(torch_cuda, mbp, prob, precision):
     torch = torch_cuda
     print(f"tiny {prob.name} {precision}", flush=True)
     f = W.rhs(prob, 91)
+    ref = oracle.solve(prob, f)
+    fproj = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
+    plan = mbp.Plan(prob, precision=precision)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.PROJECT_RHS | mbp.RETIRE)
+    got = host(p)
+    res = oracle.rel_residual(prob, got, fproj)
+    err = oracle.rel_error(got, ref)
+    print(f"  {info} residual={res:.2e} error={err:.2e}", flush=True)
+    assert info.status == 0 and res <= 1e-10 and err <= 1e-9
+    plan.close()
+
+
+# Seeded random layouts (rows, columns, L shapes and 2 x 2 grids of blocks 1
+# to 40 cells wide, mildly stretched, random walls and z pairs) against the
+# oracle: the per-class hierarchy, merges, halos across joined faces and
+# colour parities on layouts nobody picked by hand.
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("seed", range(40))
+def test_random_layouts(torch_cuda, mbp, seed, precision):
+    torch = torch_cuda
+    prob = W.random_layout(seed)
+    print(f"random {prob.name} {[(b.nx, b.ny) for b in prob.blocks]} nz={prob.nz} {precision}", flush=True)
+    f = W.rhs(prob, 100 + seed)
     ref = oracle.solve(prob, f)
     fproj = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
     plan = mbp.Plan(prob, precision=precision)

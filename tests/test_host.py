@@ -117,10 +117,19 @@ def test_plan_check_rejects_overlap_and_nonconforming(mbp):
 def test_plan_check_disparate_blocks(mbp, kind):
     """A block too thin to follow its neighbours down the hierarchy stops
     coarsening on its own (its class of blocks sharing cells across joined
-    faces), so the coarsest plane stays small instead of being refused."""
+    faces) where uniform steps would leave more than 2048 coarsest cells, so
+    such planes are not refused."""
     s = mbp.plan_check(W.disparate(kind))
-    assert s["coarse_cells"] <= 64
-    assert s["nlevels"] >= 4
+    assert s["coarse_cells"] <= 128
+    assert s["nlevels"] >= 3
+
+
+def test_plan_check_random_layouts(mbp):
+    """Every seeded random layout of the GPU sweep plans (its coarsest plane
+    within the 2048 cells of the exact solve)."""
+    for seed in range(40):
+        s = mbp.plan_check(W.random_layout(seed))
+        assert s["coarse_cells"] <= 2048, seed
 
 
 def test_plan_check_singular_flag(mbp):

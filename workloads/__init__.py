@@ -219,6 +219,66 @@ def disparate(kind: str, nz: int = 8, zpair: str = "PP") -> Problem:
     return Problem(blocks=blocks, nz=nz, lz=0.5, zbc=PAIRS[zpair], name=f"disparate_{kind}_{zpair}_{nz}")
 
 
+def random_layout(seed: int) -> Problem:
+    """A seeded multi-block layout for sweeps of the hierarchy and halo code:
+    a row of 2-4 blocks joined across x faces, a column of 2-4 joined across
+    y faces, an L of three blocks or a 2 x 2 grid of four.  Block widths are
+    1..40 cells of width 1/32 (thin blocks included), the shared faces of a
+    row or column are mildly tanh-stretched (factor up to 0.8), outer faces
+    are Dirichlet or Neumann at random, and z takes a random pair and an even
+    count up to 16."""
+    rng = np.random.default_rng(np.random.SeedSequence([7, seed]))
+    D, N, C = DIRICHLET, NEUMANN, CONNECT
+    h = 1.0 / 32.0
+    kind = int(rng.integers(0, 4))
+    wall = lambda: D if rng.random() < 0.5 else N  # noqa: E731
+
+    def stretched(n, lo):
+        return faces(n, lo, lo + n * h, 0, float(rng.uniform(0.0, 0.8)))
+
+    def widths(k):
+        return [int(rng.choice([1, 2, 3, 4, 5])) if rng.random() < 0.3 else int(rng.integers(6, 41))
+                for _ in range(k)]
+    blocks = []
+    if kind == 0:  # row: x faces joined, shared y faces
+        k = int(rng.integers(2, 5))
+        nxs, ny = widths(k), int(rng.integers(4, 41))
+        yf = stretched(ny, 0.0)
+        x0, i0 = 0.0, 1
+        for b, nx in enumerate(nxs):
+            bc = (wall() if b == 0 else C, wall() if b == k - 1 else C, wall(), wall())
+            blocks.append(Block((i0, 1), (i0 + nx - 1, ny), faces(nx, x0, x0 + nx * h), yf.copy(), bc))
+            x0 += nx * h
+            i0 += nx
+    elif kind == 1:  # column: y faces joined, shared x faces
+        k = int(rng.integers(2, 5))
+        nys, nx = widths(k), int(rng.integers(4, 41))
+        xf = stretched(nx, 0.0)
+        y0, j0 = 0.0, 1
+        for b, ny in enumerate(nys):
+            bc = (wall(), wall(), wall() if b == 0 else C, wall() if b == k - 1 else C)
+            blocks.append(Block((1, j0), (nx, j0 + ny - 1), xf.copy(), faces(ny, y0, y0 + ny * h), bc))
+            y0 += ny * h
+            j0 += ny
+    else:
+        na, nb = widths(2)
+        ma, mb = int(rng.integers(4, 41)), int(rng.integers(4, 41))
+        xa, xb = stretched(na, 0.0), faces(nb, na * h, (na + nb) * h)
+        ya, yb = stretched(ma, 0.0), faces(mb, ma * h, (ma + mb) * h)
+        if kind == 2:  # L: A, B right of A, C above A
+            blocks = [Block((1, 1), (na, ma), xa, ya, (wall(), C, wall(), C)),
+                      Block((na + 1, 1), (na + nb, ma), xb, ya.copy(), (C, wall(), wall(), wall())),
+                      Block((1, ma + 1), (na, ma + mb), xa.copy(), yb, (wall(), wall(), C, wall()))]
+        else:  # 2 x 2 grid
+            blocks = [Block((1, 1), (na, ma), xa, ya, (wall(), C, wall(), C)),
+                      Block((na + 1, 1), (na + nb, ma), xb, ya.copy(), (C, wall(), wall(), C)),
+                      Block((1, ma + 1), (na, ma + mb), xa.copy(), yb, (wall(), C, C, wall())),
+                      Block((na + 1, ma + 1), (na + nb, ma + mb), xb.copy(), yb.copy(), (C, wall(), C, wall()))]
+    zk = ["PP", "NN", "DD", "ND", "DN"][int(rng.integers(0, 5))]
+    nz = int(rng.choice([2, 4, 6, 8, 12, 16]))
+    return Problem(blocks=blocks, nz=nz, lz=nz * h, zbc=PAIRS[zk], name=f"random{seed}_{['row', 'col', 'L', 'grid'][kind]}_{zk}")
+
+
 def config2() -> Problem:
     return lshape(256, 512, 1.5, 2.0)
 
