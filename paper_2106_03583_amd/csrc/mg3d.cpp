@@ -106,11 +106,10 @@ int mg3_create(const mbp_block_desc* blocks, int nblocks, const mbp_synth_desc* 
     mbp_options o2 = o;
     o2.smoother = MBP_SMOOTHER_DEFAULT;
     std::string err;
-    // the x-y tables of the FFT path's plan; its LDS budget does not apply
-    // here.  Every block takes each x-y step: the 3D hierarchy appends x-y
-    // steps after z has stopped, and a step that coarsens only some blocks
-    // there leaves the smoother of a strongly z-coupled level unaided
-    int st = build_plan_host_limits(blocks, nblocks, z, &o2, int64_t(1) << 40, &X->host, &err, true);
+    // the x-y tables of the FFT path's plan (uniform x-y steps unless they
+    // leave more than 256 coarsest cells, as there); its LDS budget does not
+    // apply here
+    int st = build_plan_host_limits(blocks, nblocks, z, &o2, int64_t(1) << 40, &X->host, &err, false);
     if (st != MBP_OK) return st;
     X->host.opt.smoother = o.smoother;
     mbp_plan& H = X->host;

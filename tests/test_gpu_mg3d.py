@@ -159,3 +159,14 @@ def test_mg3d_errors(torch_cuda, mbp):
     plan.close()
     with pytest.raises(mbp.MBPError):
         mbp.Plan3D(prob, nu1=0)
+
+
+# The 3D multigrid on the seeded random layouts of the FFT path's sweep (the
+# same x-y hierarchy rule: uniform steps unless they leave more than 256
+# coarsest cells).
+@pytest.mark.parametrize("seed", range(0, 40, 2))
+def test_mg3d_random_layouts(torch_cuda, mbp, seed):
+    prob = W.random_layout(seed)
+    print(f"mg3d random {prob.name} {[(b.nx, b.ny) for b in prob.blocks]} nz={prob.nz}", flush=True)
+    f = W.rhs(prob, 300 + seed)
+    _run(torch_cuda, mbp, prob, f, oracle.solve(prob, f))

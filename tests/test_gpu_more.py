@@ -178,3 +178,12 @@ def test_unrelaxed_modes_zero(torch_cuda, mbp, precision):
     print(f"  {precision}: {info2} residual={res:.2e} error={err:.2e}", flush=True)
     assert info2.status == 0 and res <= 1e-10 and err <= 1e-9
     plan.close()
+
+
+# The batched form over the seeded random layouts (mixed precision, every
+# problem its own shape, many of them off the grouped form): each result
+# against the oracle and against the same plan's single solve.
+def test_batch_random_layouts(torch_cuda, mbp):
+    probs = [W.random_layout(seed) for seed in range(40)]
+    fs, got, singles, infos, sched = _run_batch(torch_cuda, mbp, probs, 900)
+    _check_all(probs, fs, got, singles, infos)
