@@ -556,11 +556,15 @@ def test_tiny_problems(torch_cuda, mbp, prob, precision):
 
 
 # Seeded random layouts (rows, columns, L shapes and 2 x 2 grids of blocks 1
-# to 40 cells wide, mildly stretched, random walls and z pairs) against the
-# oracle: the per-class hierarchy, merges, halos across joined faces and
-# colour parities on layouts nobody picked by hand.
+# to 40 cells wide, mildly stretched, random walls and z pairs; from seed 100
+# on, rows and columns may close into periodic rings of any length) against
+# the oracle: the hierarchy, merges, halos across joined faces, colour
+# parities and the coarsest operator on layouts nobody picked by hand.  The
+# cycle cap is raised: a block one cell thin between wide ones (per-class
+# steps) converges slowly (seed 116 takes 115 V-cycles in FP64), and
+# the test is about the answer.
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("seed", range(40))
+@pytest.mark.parametrize("seed", list(range(40)) + list(range(100, 140)))
 def test_random_layouts(torch_cuda, mbp, seed, precision):
     torch = torch_cuda
     prob = W.random_layout(seed)
@@ -568,7 +572,7 @@ def test_random_layouts(torch_cuda, mbp, seed, precision):
     f = W.rhs(prob, 100 + seed)
     ref = oracle.solve(prob, f)
     fproj = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
-    plan = mbp.Plan(prob, precision=precision)
+    plan = mbp.Plan(prob, precision=precision, max_cycles=300)
     p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
     info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.PROJECT_RHS | mbp.RETIRE)
     got = host(p)

@@ -226,9 +226,12 @@ def random_layout(seed: int) -> Problem:
     1..40 cells of width 1/32 (thin blocks included), the shared faces of a
     row or column are mildly tanh-stretched (factor up to 0.8), outer faces
     are Dirichlet or Neumann at random, and z takes a random pair and an even
-    count up to 16."""
+    count up to 16.  Seeds from 100 on close half of the rows and columns into
+    periodic rings (the two end faces joined cyclically; ring lengths may be
+    odd)."""
     rng = np.random.default_rng(np.random.SeedSequence([7, seed]))
-    D, N, C = DIRICHLET, NEUMANN, CONNECT
+    ring = seed >= 100 and rng.random() < 0.5
+    D, N, C, P = DIRICHLET, NEUMANN, CONNECT, PERIODIC
     h = 1.0 / 32.0
     kind = int(rng.integers(0, 4))
     wall = lambda: D if rng.random() < 0.5 else N  # noqa: E731
@@ -246,7 +249,8 @@ def random_layout(seed: int) -> Problem:
         yf = stretched(ny, 0.0)
         x0, i0 = 0.0, 1
         for b, nx in enumerate(nxs):
-            bc = (wall() if b == 0 else C, wall() if b == k - 1 else C, wall(), wall())
+            bc = (P if ring else wall()) if b == 0 else C, (P if ring else wall()) if b == k - 1 else C
+            bc = (bc[0], bc[1], wall(), wall())
             blocks.append(Block((i0, 1), (i0 + nx - 1, ny), faces(nx, x0, x0 + nx * h), yf.copy(), bc))
             x0 += nx * h
             i0 += nx
@@ -256,7 +260,8 @@ def random_layout(seed: int) -> Problem:
         xf = stretched(nx, 0.0)
         y0, j0 = 0.0, 1
         for b, ny in enumerate(nys):
-            bc = (wall(), wall(), wall() if b == 0 else C, wall() if b == k - 1 else C)
+            bc = (wall(), wall(), (P if ring else wall()) if b == 0 else C,
+                  (P if ring else wall()) if b == k - 1 else C)
             blocks.append(Block((1, j0), (nx, j0 + ny - 1), xf.copy(), faces(ny, y0, y0 + ny * h), bc))
             y0 += ny * h
             j0 += ny
