@@ -219,7 +219,7 @@ def disparate(kind: str, nz: int = 8, zpair: str = "PP") -> Problem:
     return Problem(blocks=blocks, nz=nz, lz=0.5, zbc=PAIRS[zpair], name=f"disparate_{kind}_{zpair}_{nz}")
 
 
-def random_layout(seed: int) -> Problem:
+def random_layout(seed: int, scale: int = 1) -> Problem:
     """A seeded multi-block layout for sweeps of the hierarchy and halo code:
     a row of 2-4 blocks joined across x faces, a column of 2-4 joined across
     y faces, an L of three blocks or a 2 x 2 grid of four.  Block widths are
@@ -228,11 +228,13 @@ def random_layout(seed: int) -> Problem:
     are Dirichlet or Neumann at random, and z takes a random pair and an even
     count up to 16.  Seeds from 100 on close half of the rows and columns into
     periodic rings (the two end faces joined cyclically; ring lengths may be
-    odd)."""
+    odd).  scale > 1 multiplies the wide blocks' cell counts (not the thin
+    ones') and divides the cell width, so the fused strip kernels see the
+    same kinds of layouts on planes of tens of thousands of cells."""
     rng = np.random.default_rng(np.random.SeedSequence([7, seed]))
     ring = seed >= 100 and rng.random() < 0.5
     D, N, C, P = DIRICHLET, NEUMANN, CONNECT, PERIODIC
-    h = 1.0 / 32.0
+    h = 1.0 / (32.0 * scale)
     kind = int(rng.integers(0, 4))
     wall = lambda: D if rng.random() < 0.5 else N  # noqa: E731
 
@@ -240,12 +242,12 @@ def random_layout(seed: int) -> Problem:
         return faces(n, lo, lo + n * h, 0, float(rng.uniform(0.0, 0.8)))
 
     def widths(k):
-        return [int(rng.choice([1, 2, 3, 4, 5])) if rng.random() < 0.3 else int(rng.integers(6, 41))
+        return [int(rng.choice([1, 2, 3, 4, 5])) if rng.random() < 0.3 else scale * int(rng.integers(6, 41))
                 for _ in range(k)]
     blocks = []
     if kind == 0:  # row: x faces joined, shared y faces
         k = int(rng.integers(2, 5))
-        nxs, ny = widths(k), int(rng.integers(4, 41))
+        nxs, ny = widths(k), scale * int(rng.integers(4, 41))
         yf = stretched(ny, 0.0)
         x0, i0 = 0.0, 1
         for b, nx in enumerate(nxs):
@@ -256,7 +258,7 @@ def random_layout(seed: int) -> Problem:
             i0 += nx
     elif kind == 1:  # column: y faces joined, shared x faces
         k = int(rng.integers(2, 5))
-        nys, nx = widths(k), int(rng.integers(4, 41))
+        nys, nx = widths(k), scale * int(rng.integers(4, 41))
         xf = stretched(nx, 0.0)
         y0, j0 = 0.0, 1
         for b, ny in enumerate(nys):
@@ -267,7 +269,7 @@ def random_layout(seed: int) -> Problem:
             j0 += ny
     else:
         na, nb = widths(2)
-        ma, mb = int(rng.integers(4, 41)), int(rng.integers(4, 41))
+        ma, mb = scale * int(rng.integers(4, 41)), scale * int(rng.integers(4, 41))
         xa, xb = stretched(na, 0.0), faces(nb, na * h, (na + nb) * h)
         ya, yb = stretched(ma, 0.0), faces(mb, ma * h, (ma + mb) * h)
         if kind == 2:  # L: A, B right of A, C above A
@@ -281,7 +283,9 @@ def random_layout(seed: int) -> Problem:
                       Block((na + 1, ma + 1), (na + nb, ma + mb), xb.copy(), yb.copy(), (C, wall(), C, wall()))]
     zk = ["PP", "NN", "DD", "ND", "DN"][int(rng.integers(0, 5))]
     nz = int(rng.choice([2, 4, 6, 8, 12, 16]))
-    return Problem(blocks=blocks, nz=nz, lz=nz * h, zbc=PAIRS[zk], name=f"random{seed}_{['row', 'col', 'L', 'grid'][kind]}_{zk}")
+    sc = "" if scale == 1 else f"x{scale}"
+    return Problem(blocks=blocks, nz=nz, lz=nz * h, zbc=PAIRS[zk],
+                   name=f"random{seed}{sc}_{['row', 'col', 'L', 'grid'][kind]}_{zk}")
 
 
 def config2() -> Problem:
