@@ -332,15 +332,16 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
     //      smaller mean cell width, as PFMG picks its semicoarsening direction
     //      (Sec. 3.3.1): x alone when the mean x width is below the mean y
     //      width over sqrt(2), y alone in the opposite case, both otherwise.
-    //      Blocks joined across a y face share their x cells, so they halve x
-    //      together; blocks joined across an x face halve y together.  Each
-    //      such class halves a direction while its blocks have at least 4
-    //      cells along it; a thinner class then merges its 2 or 3 cells into
-    //      one while other classes go on halving, where that direction is its
-    //      cells' strongly coupled one.  A thin block thus does not hold back
-    //      the rest of the plane; the hierarchy ends when no class can halve
-    //      the chosen direction(s).  Odd counts merge their last three
-    //      cells ----
+    //      Uniform steps (every block takes each step) unless they leave too
+    //      large a coarsest plane, see below.  Per-class steps: blocks joined
+    //      across a y face share their x cells, so they halve x together;
+    //      blocks joined across an x face halve y together.  Each such class
+    //      halves a direction while its blocks have at least 4 cells along
+    //      it; a thinner class then merges its 2 or 3 cells into one while
+    //      other classes go on halving, where that direction is its cells'
+    //      strongly coupled one.  A thin block thus does not hold back the
+    //      rest of the plane; the hierarchy ends when no class can halve the
+    //      chosen direction(s).  Odd counts merge their last three cells ----
     std::vector<int> xcls(nb), ycls(nb);
     {
         auto find = [](std::vector<int>& u, int a) {
@@ -447,10 +448,10 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
     // unless that leaves more than 256 coarsest cells: then each class of
     // blocks steps on its own.  Per-class steps converge slower on layouts
     // whose thin blocks stay one or two cells wide while their neighbours
-    // coarsen (a one-cell L-shaped pair even diverged where uniform steps
-    // left 73 coarsest cells), while a large coarsest plane costs the plan
-    // an O(n^3) eigen-decomposition (seconds at a few hundred cells, minutes
-    // near 2048).
+    // coarsen (20-40 V-cycles and more, where a direct solve of a few
+    // hundred coarsest cells needs none of that), while a large coarsest
+    // plane costs the plan an O(n^3) eigen-decomposition (seconds at a few
+    // hundred cells, minutes near 2048).
     auto coarsest = [&]() {
         int64_t cells = 0;
         for (int b = 0; b < nb; ++b) cells += int64_t(P->levels.back().nx[b]) * P->levels.back().ny[b];
