@@ -202,3 +202,25 @@ def test_server_two_waiters_one_ticket(torch_cuda, mbp):
     assert sorted(codes) == sorted([mbp.OK, mbp.ERR_INVALID]), codes
     _check(pr, o.cpu().numpy(), f, "two-waiters")
     srv.close()
+
+
+def test_server_random_layouts(torch_cuda, mbp):
+    """The serving loop over seeded random multi-block layouts (small plans,
+    many shapes, evictions under a tight budget), both precisions, every
+    result against the oracle."""
+    torch = torch_cuda
+    probs = [W.random_layout(seed) for seed in list(range(0, 40, 3)) + list(range(100, 120, 3))]
+    for precision in ["fp64", "mixed"]:
+        fs = [W.rhs(pr, 500 + i) for i, pr in enumerate(probs)]
+        rhs = [dev(torch, f) for f in fs]
+        outs = [torch.zeros_like(r) for r in rhs]
+        torch.cuda.synchronize()
+        budget = 3 * max(mbp.plan_check(pr)["workspace_bytes"] for pr in probs)
+        srv = mbp.Server(hbm_budget=budget, slots=4, precision=precision)
+        tickets = [srv.submit(pr, r, o, rtol=1e-10, flags=mbp.PROJECT_RHS) for pr, r, o in zip(probs, rhs, outs)]
+        for t in tickets:
+            st, info, ms = srv.wait(t)
+            assert st == 0, (st, info)
+        srv.close()
+        for pr, f, o in zip(probs, fs, outs):
+            _check(pr, o.cpu().numpy(), f, f"served {precision}")
