@@ -270,13 +270,15 @@ void march_post(const mbp_plan* P, int l, const T* pold, T* pnew, const T* f, co
                 const int* act, const int* nact, int nitems, hipStream_t s);
 void launch_residual_norm(const mbp_plan* P, const double* p, const double* f, double* rnorm,
                           const int* act, const int* nact, int nitems, hipStream_t s);
+// pzero: p is zero (the first refinement step), r = f without reading p
 void launch_residual_to32(const mbp_plan* P, const double* p, const double* f, float* r32,
                           float* e32, double* rnorm, const int* act, const int* nact, int nitems,
-                          hipStream_t s);
+                          hipStream_t s, bool pzero = false);
 // FP32 finest guess the refinement residual must zero (nullptr: none).
 float* fp32_guess_to_zero(const mbp_plan* P);
+// first: p is zero before the add (it is written, not read)
 void launch_add_correction(const mbp_plan* P, double* p, const float* e32, const int* act,
-                           const int* nact, int nitems, hipStream_t s);
+                           const int* nact, int nitems, hipStream_t s, bool first = false);
 void launch_plane_norm(const mbp_plan* P, const double* f, double* out, hipStream_t s);
 void launch_update_active(const mbp_plan* P, double rtol2, double etol2, int retire, int maxc,
                           hipStream_t s, double* out = nullptr);

@@ -252,6 +252,7 @@ struct ResJob {
     float* r32;
     float* e32;
     int per;             // items per workgroup
+    int pzero;           // p is zero (first refinement step): r = f, p is not read
 };
 
 // Items per residual workgroup: enough workgroups to fill the chip several
@@ -306,12 +307,13 @@ __device__ __forceinline__ void residual_body(const ResJob& J, int bx, int by) {
         const double* __restrict__ fq = J.f + q * J.plane + b.off;
         const double sig = J.shift[q];
         double pc[kResRows + 2], xm[kResRows], xp[kResRows], fv[kResRows];
+        const bool pz = J.pzero != 0;
 #pragma unroll
-        for (int k = 0; k < kResRows + 2; ++k) pc[k] = pq[jr[k] + ic];
+        for (int k = 0; k < kResRows + 2; ++k) pc[k] = pz ? 0.0 : pq[jr[k] + ic];
 #pragma unroll
         for (int k = 0; k < kResRows; ++k) {
-            xm[k] = pq[jr[k + 1] + im];
-            xp[k] = pq[jr[k + 1] + ip];
+            xm[k] = pz ? 0.0 : pq[jr[k + 1] + im];
+            xp[k] = pz ? 0.0 : pq[jr[k + 1] + ip];
             fv[k] = fq[jr[k + 1] + ic];
         }
         double acc = 0.0, pacc = 0.0;
@@ -323,8 +325,8 @@ __device__ __forceinline__ void residual_body(const ResJob& J, int bx, int by) {
             // cells on a joined or periodic face take their neighbours by the
             // face rules; on a wall the face coefficient is zero, so the
             // clamped (finite) value already contributes nothing
-            if ((i == 0 && b.nbr[XM] >= 0) || (i == b.nx - 1 && b.nbr[XP] >= 0) ||
-                (j == 0 && b.nbr[YM] >= 0) || (j == b.ny - 1 && b.nbr[YP] >= 0))
+            if (!pz && ((i == 0 && b.nbr[XM] >= 0) || (i == b.nx - 1 && b.nbr[XP] >= 0) ||
+                        (j == 0 && b.nbr[YM] >= 0) || (j == b.ny - 1 && b.nbr[YP] >= 0)))
                 neighbours(pl, B, b, i, j, vxm, vxp, vym, vyp);
             const double c = pc[k + 1];
             const double d = dx + dy[k] + sig;
@@ -432,6 +434,7 @@ struct AddJob {
     long long plane;
     const int* act;
     const int* nact;
+    int first;  // p is zero before the add: write e, do not read p
 };
 
 __device__ __forceinline__ void addcorr_body(const AddJob& J, int chunk, int item) {
@@ -441,7 +444,7 @@ __device__ __forceinline__ void addcorr_body(const AddJob& J, int chunk, int ite
 #pragma unroll
     for (int k = 0; k < kAddChunk / 256; ++k) {
         const long long c = c0 + k * 256;
-        if (c < J.plane) J.p[base + c] += double(J.e[base + c]);
+        if (c < J.plane) J.p[base + c] = (J.first ? 0.0 : J.p[base + c]) + double(J.e[base + c]);
     }
 }
 
@@ -1321,20 +1324,21 @@ void launch_residual_norm(const mbp_plan* P, const double* p, const double* f, d
 }
 
 void launch_residual_to32(const mbp_plan* P, const double* p, const double* f, float* r32, float* e32,
-                          double* rnorm, const int* act, const int* nact, int nitems, hipStream_t s) {
+                          double* rnorm, const int* act, const int* nact, int nitems, hipStream_t s,
+                          bool pzero) {
     const Level& L = P->levels[0];
     const int per = res_per(L.ntiles, nitems);
     const ResJob J{P->d_blk + L.blk_off, P->d_tiles + L.tile_off, L.ntiles, P->d_dbl, p, f,
-                   (long long)L.plane, P->d_shift, act, nact, P->d_part, r32, e32, per};
+                   (long long)L.plane, P->d_shift, act, nact, P->d_part, r32, e32, per, pzero ? 1 : 0};
     hipLaunchKernelGGL(k_residual<1>, dim3(L.ntiles, (nitems + per - 1) / per), dim3(kTileX, kRowsPerPass), 0, s, J);
     const FinJob F{P->d_part, L.ntiles, act, nact, rnorm, P->d_pnorm};
     hipLaunchKernelGGL(k_finish, dim3(nitems), dim3(256), 0, s, F);
 }
 
 void launch_add_correction(const mbp_plan* P, double* p, const float* e32, const int* act,
-                           const int* nact, int nitems, hipStream_t s) {
+                           const int* nact, int nitems, hipStream_t s, bool first) {
     const Level& L = P->levels[0];
-    const AddJob J{p, e32, (long long)L.plane, act, nact};
+    const AddJob J{p, e32, (long long)L.plane, act, nact, first ? 1 : 0};
     hipLaunchKernelGGL(k_addcorr, dim3(add_chunks(L.plane), nitems), dim3(256), 0, s, J);
 }
 

@@ -356,7 +356,7 @@ void ctx_test(SolveCtx& c, hipStream_t s, double* state_out) {
     const bool zero = c.cycles == 0 && !c.warm;  // p = 0: the residual is f itself
     if (c.mixed)
         launch_residual_to32(P, P->phat, P->fhat, P->f32[0], fp32_guess_to_zero(P), P->d_rnorm, P->d_act, P->d_nact,
-                             c.nitems, s);
+                             c.nitems, s, zero);
     else if (zero)
         launch_norm_from_rhs(P, c.nitems, s);
     else if (c.fused_parts > 0)
@@ -375,7 +375,7 @@ void ctx_vcycle(SolveCtx& c, hipStream_t s) {
         for (int k = 0; k < P->opt.inner; ++k)
             launch_vcycle<float>(P, P->p32[0], P->p32B[0], P->f32[0], P->d_act, P->d_nact, c.nitems, false,
                                  k == 0, s);
-        launch_add_correction(P, P->phat, P->p32[0], P->d_act, P->d_nact, c.nitems, s);
+        launch_add_correction(P, P->phat, P->p32[0], P->d_act, P->d_nact, c.nitems, s, zero);
     } else {
         c.fused_parts = launch_vcycle<double>(P, P->phat, P->phatB, P->fhat, P->d_act, P->d_nact, c.nitems,
                                               true, zero, s);
@@ -456,9 +456,10 @@ int solve_one(mbp_plan* P, const double* rhs, double* p, double rtol, int flags,
               mbp_solve_info* info) {
     SolveCtx c;
     ctx_init(c, P, rhs, p, rtol, flags);
-    // the retiring FP64 solve whose first sweep reads no iterate skips the
-    // up-front zero fill of the modal solution (one write of the whole field)
-    c.lazy_zero = c.retire && !c.warm && !c.mixed && !c.full_lds && vcycle_zero_start_reads_none(P);
+    // the retiring solve whose first step reads no iterate skips the up-front
+    // zero fill of the modal solution (one write of the whole field)
+    // (mixed: the first refinement step takes r = f and writes p = e)
+    c.lazy_zero = c.retire && !c.warm && !c.full_lds && (c.mixed || vcycle_zero_start_reads_none(P));
     hipEvent_t ev[4];
     for (auto& e : ev) (void)hipEventCreate(&e);
     (void)hipEventRecord(ev[0], s);
