@@ -632,3 +632,31 @@ def test_random_layouts_large(torch_cuda, mbp, seed, precision):
     print(f"  {info} residual={res:.2e} error={err:.2e}", flush=True)
     assert info.status == 0 and res <= 1e-10 and err <= 1e-9
     plan.close()
+
+
+# The other solve forms on random layouts: lockstep modes (no retirement)
+# and a warm start from a perturbed answer, in both precisions.
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("seed", list(range(0, 40, 5)) + [101, 106, 112])
+def test_random_layouts_lockstep_warm(torch_cuda, mbp, seed, precision):
+    torch = torch_cuda
+    prob = W.random_layout(seed)
+    print(f"random forms {prob.name} {precision}", flush=True)
+    f = W.rhs(prob, 600 + seed)
+    ref = oracle.solve(prob, f)
+    fproj = oracle.project_compatible(prob, f) if oracle.is_singular(prob) else f
+    plan = mbp.Plan(prob, precision=precision, max_cycles=300)
+    p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
+    info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.PROJECT_RHS)
+    got = host(p)
+    res, err = oracle.rel_residual(prob, got, fproj), oracle.rel_error(got, ref)
+    print(f"  lockstep {info} residual={res:.2e} error={err:.2e}", flush=True)
+    assert info.status == 0 and res <= 1e-10 and err <= 1e-9
+    guess = ref + 1e-3 * np.random.default_rng(seed).standard_normal(ref.size) * np.abs(ref).max()
+    p = dev(torch, guess)
+    info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.PROJECT_RHS | mbp.RETIRE | mbp.WARM_START)
+    got = host(p)
+    res, err = oracle.rel_residual(prob, got, fproj), oracle.rel_error(got, ref)
+    print(f"  warm {info} residual={res:.2e} error={err:.2e}", flush=True)
+    assert info.status == 0 and res <= 1e-10 and err <= 1e-9
+    plan.close()
