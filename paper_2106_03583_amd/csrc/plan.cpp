@@ -375,6 +375,16 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
         }
         while (P->levels.size() < 24) {
             Level& F = P->levels.back();
+            if (!uniform) {
+                // per-class steps end once the plane fits an exact solve of
+                // a few hundred cells: deeper, thin blocks left one or two
+                // cells wide beside far coarser neighbours made the cycle
+                // slow (268 V-cycles on one layout, 67 when stopped here)
+                // or even divergent
+                int64_t cells = 0;
+                for (int b = 0; b < nb; ++b) cells += int64_t(F.nx[b]) * F.ny[b];
+                if (cells <= 256) break;
+            }
             double wx = 0.0, wy = 0.0;
             int64_t cellsx = 0, cellsy = 0;
             // per class (indexed by its representative): every block has at
@@ -446,12 +456,11 @@ int build_plan_host_limits(const mbp_block_desc* blocks, int nblocks, const mbp_
     };
     // Every block takes each step (the hierarchy ends when one block cannot)
     // unless that leaves more than 256 coarsest cells: then each class of
-    // blocks steps on its own.  Per-class steps converge slower on layouts
-    // whose thin blocks stay one or two cells wide while their neighbours
-    // coarsen (20-40 V-cycles and more, where a direct solve of a few
-    // hundred coarsest cells needs none of that), while a large coarsest
-    // plane costs the plan an O(n^3) eigen-decomposition (seconds at a few
-    // hundred cells, minutes near 2048).
+    // blocks steps on its own, down to 256 cells.  Per-class steps converge
+    // slower on layouts whose thin blocks stay one or two cells wide while
+    // their neighbours coarsen, while a large coarsest plane costs the plan
+    // an O(n^3) eigen-decomposition (seconds at a few hundred cells, minutes
+    // near 2048).
     auto coarsest = [&]() {
         int64_t cells = 0;
         for (int b = 0; b < nb; ++b) cells += int64_t(P->levels.back().nx[b]) * P->levels.back().ny[b];

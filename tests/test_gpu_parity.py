@@ -424,10 +424,9 @@ def _aniso_problems():
 # blocks on the finest grid).  Where uniform steps would leave more than 256
 # coarsest cells, each class of blocks that share cells across joined faces
 # coarsens on its own, so the wide blocks go on coarsening after the thin one
-# has stopped, and the thin one merges its last cells into one where that
-# keeps its cells near square.  Five of these planes were refused before
-# (coarsest plane above 2048 cells).  The 1-cell sliver cannot merge: its
-# cells reach aspect 32 on the coarse levels, and it keeps a looser bound.
+# has stopped (down to 256 coarsest cells), and the thin one merges its last
+# cells into one where that keeps its cells near square.  Five of these
+# planes were refused before (coarsest plane above 2048 cells).
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("kind,zpair", [("thin_wide", "PP"), ("stacked", "NN"), ("sandwich", "DN"),
                                         ("large", "DD"), ("sliver1", "NN"), ("sliver2", "ND")])
@@ -448,7 +447,7 @@ def test_disparate_blocks(torch_cuda, mbp, kind, zpair, precision):
     assert info.status == 0
     assert res <= 1e-10
     assert err <= 1e-9
-    assert info.cycles <= (40 if kind == "sliver1" else 30)
+    assert info.cycles <= 30
     plan.close()
 
 
@@ -560,9 +559,8 @@ def test_tiny_problems(torch_cuda, mbp, prob, precision):
 # on, rows and columns may close into periodic rings of any length) against
 # the oracle: the hierarchy, merges, halos across joined faces, colour
 # parities and the coarsest operator on layouts nobody picked by hand.  The
-# cycle cap is raised: a block one cell thin between wide ones (per-class
-# steps) converges slowly (seed 116 takes 115 V-cycles in FP64), and
-# the test is about the answer.
+# cycle cap is raised: some near-singular planes converge slowly (see the
+# large sweep below), and the test is about the answer.
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("seed", list(range(40)) + list(range(100, 140)))
 def test_random_layouts(torch_cuda, mbp, seed, precision):
@@ -610,12 +608,9 @@ def test_random_layouts_helmholtz(torch_cuda, mbp, seed):
 # mode 0 are near-singular (a large all-Neumann block reached from a small
 # Dirichlet wall through a thin arm): rediscretised coarse operators miss
 # their smallest eigenvalue by a margin, and such modes need hundreds of
-# V-cycles; the cap is raised so that the test checks the answer.  Seed 116
-# (a 144 x 148 all-Neumann block reached through a 1-row and a 4-row block)
-# stalls at this size and is left out: a stated limitation of the
-# rediscretised hierarchy; at the small size it converges in 115 cycles.
+# V-cycles; the cap is raised so that the test checks the answer.
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("seed", list(range(40)) + [s for s in range(100, 120) if s != 116])
+@pytest.mark.parametrize("seed", list(range(40)) + list(range(100, 120)))
 def test_random_layouts_large(torch_cuda, mbp, seed, precision):
     torch = torch_cuda
     prob = W.random_layout(seed, 4)
