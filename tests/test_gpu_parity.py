@@ -607,7 +607,7 @@ def test_random_layouts_helmholtz(torch_cuda, mbp, seed):
 # faces and block corners run on them), against the oracle.  Some planes of
 # mode 0 are near-singular (a large all-Neumann block reached from a small
 # Dirichlet wall through a thin arm): rediscretised coarse operators miss
-# their smallest eigenvalue by a margin, and such modes need hundreds of
+# their smallest eigenvalue by a margin, and such modes need 50-70
 # V-cycles; the cap is raised so that the test checks the answer.
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("seed", list(range(40)) + list(range(100, 120)))
