@@ -106,7 +106,7 @@ typedef struct {
  *   precision  MBP_FP64 | MBP_MIXED                              [MBP_FP64]
  *   nu1, nu2   smoothing sweeps before / after the coarse-grid
  *              correction                                        [1, 1]
- *   max_cycles cap on V-cycles (or refinement steps)             [60]
+ *   max_cycles cap on V-cycles (or refinement steps)             [100]
  *   flags      default solve flags OR-ed into each solve          [0]
  *   etol       target of the estimated relative solution error of
  *              each mode, ||rhat_q|| / (mu_0 + |sigma_q|) <= etol ||phat_q||
@@ -123,8 +123,9 @@ typedef struct {
  *   smoother   MBP_SMOOTHER_DEFAULT | _RBGS (FFT path) | _JACOBI (mbp3_*)
  *                                                                [DEFAULT]
  *   helmholtz  alpha >= 0: solve (L_h - alpha) p = f, the Helmholtz
- *              systems of implicit diffusion "solved with the same method"
- *              (Sec. 2); every modal shift becomes lambda_q/dz^2 - alpha.
+ *              systems of implicit diffusion, which the paper solves
+ *              by the same method as the Poisson equation (Sec. 2);
+ *              every modal shift becomes lambda_q/dz^2 - alpha.
  *              With alpha > 0 no problem is singular.  Change it between
  *              solves with mbp_plan_set_helmholtz                  [0]
  * In the mixed form max_cycles and the reported cycles count refinement

@@ -180,7 +180,7 @@ class _Desc:
 SMOOTHER_DEFAULT, SMOOTHER_RBGS, SMOOTHER_JACOBI = 0, 1, 2
 
 
-def _options(precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0, etol=0.0, inner=0, march=0,
+def _options(precision="fp64", nu1=1, nu2=1, max_cycles=100, flags=0, etol=0.0, inner=0, march=0,
              smoother=SMOOTHER_DEFAULT, helmholtz=0.0) -> Options:
     prec = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}[precision]
     return Options(prec, nu1, nu2, max_cycles, flags, etol, inner, march, smoother, float(helmholtz))
@@ -241,7 +241,7 @@ class Info:
 
 
 class Plan:
-    def __init__(self, problem, precision="fp64", nu1=1, nu2=1, max_cycles=60, flags=0, etol=0.0, inner=0,
+    def __init__(self, problem, precision="fp64", nu1=1, nu2=1, max_cycles=100, flags=0, etol=0.0, inner=0,
                  march=0, smoother=SMOOTHER_DEFAULT, helmholtz=0.0):
         self.problem = problem
         self._desc = _Desc(problem)
@@ -444,7 +444,7 @@ def batch_schedule(plans: Sequence[Plan]):
 
 
 class Server:
-    def __init__(self, hbm_budget: int, slots: int = 4, precision="mixed", nu1=1, nu2=1, max_cycles=60,
+    def __init__(self, hbm_budget: int, slots: int = 4, precision="mixed", nu1=1, nu2=1, max_cycles=100,
                  flags=0, etol=0.0, inner=0):
         self._opt = _options(precision, nu1, nu2, max_cycles, flags, etol, inner)
         self._h = C.c_void_p()

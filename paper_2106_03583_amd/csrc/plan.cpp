@@ -16,7 +16,7 @@ void options_default(mbp_options* o) {
     o->precision = MBP_FP64;
     o->nu1 = 1;
     o->nu2 = 1;
-    o->max_cycles = 60;
+    o->max_cycles = 100;
     o->flags = 0;
     o->etol = 0.0;
     o->inner = 4;
