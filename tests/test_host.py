@@ -52,6 +52,30 @@ def test_grid_tanh_matches_generator(mbp, gtype, factor):
     assert a[0] == 0.25 and a[-1] == 1.75 and np.all(np.diff(a) > 0)
 
 
+# Properties the stretched-grid mapping must have whatever its exact form
+# (the paper names tanh clustering but prints no formula): exact end faces,
+# strictly increasing faces, the two-sided form symmetric about the middle and
+# finest at both walls, the one-sided forms mirror images of each other and
+# finest at their own wall, and the uniform grid as the stretching goes to 0
+# (the deviation falls like the square of the factor).
+@pytest.mark.parametrize("factor", [0.5, 1.5, 3.0])
+def test_grid_tanh_properties(mbp, factor):
+    n = 48
+    for gen in (lambda g, a: W.faces(n, 0.0, 1.0, g, a), lambda g, a: mbp.grid_tanh(n, 0.0, 1.0, g, a)):
+        two, lo, hi = gen(0, factor), gen(-1, factor), gen(1, factor)
+        for x in (two, lo, hi):
+            assert x[0] == 0.0 and x[-1] == 1.0 and np.all(np.diff(x) > 0)
+        d = np.diff(two)
+        assert np.allclose(two + two[::-1], 1.0, rtol=0, atol=1e-14)
+        assert d[0] < d[n // 2] and d[-1] < d[n // 2] and np.argmax(d) in (n // 2 - 1, n // 2)
+        assert np.allclose(lo, 1.0 - hi[::-1], rtol=0, atol=1e-14)
+        assert np.all(np.diff(np.diff(lo)) > 0) and np.all(np.diff(np.diff(hi)) < 0)
+        uni = np.linspace(0.0, 1.0, n + 1)
+        e1 = np.abs(gen(0, 1e-2) - uni).max()
+        e2 = np.abs(gen(0, 5e-3) - uni).max()
+        assert e1 < 1e-4 and 3.5 < e1 / e2 < 4.5
+
+
 def test_plan_check_layouts(mbp):
     s = mbp.plan_check(W.config2())
     assert s["ncells"] == 3 * 256 * 256 * 512
