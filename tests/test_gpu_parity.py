@@ -582,15 +582,16 @@ def test_random_layouts(torch_cuda, mbp, seed, precision):
 
 # The Helmholtz form (L_h - alpha) p = f on random layouts: alpha shifts every
 # plane away from singularity, including the all-Neumann ones.
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("seed", range(1, 40, 4))
-def test_random_layouts_helmholtz(torch_cuda, mbp, seed):
+def test_random_layouts_helmholtz(torch_cuda, mbp, seed, precision):
     torch = torch_cuda
     prob = W.random_layout(seed)
     alpha = 40.0 + 10.0 * (seed % 3)
-    print(f"random helmholtz {prob.name} alpha={alpha}", flush=True)
+    print(f"random helmholtz {prob.name} alpha={alpha} {precision}", flush=True)
     f = W.rhs(prob, 200 + seed)
     ref = oracle.solve(prob, f, alpha=alpha)
-    plan = mbp.Plan(prob, helmholtz=alpha)
+    plan = mbp.Plan(prob, precision=precision, helmholtz=alpha)
     p = torch.zeros(plan.ncells, dtype=torch.float64, device="cuda")
     info = plan.solve(dev(torch, f), p, rtol=1e-10, flags=mbp.RETIRE)
     got = host(p)
