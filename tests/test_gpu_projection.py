@@ -6,7 +6,8 @@ dt, direct solve, u = u* - gamma dt G Phi) to the solver's error, and leave a
 velocity whose divergence is at the solver's tolerance relative to D u*
 (the divergence-free check of Sec. 4.1).  Cases: joined blocks around an
 obstacle (Dirichlet outflow), the singular L-shape with walls that let no
-flow through, and a box with Dirichlet ends along z (nz + 1 z faces).
+flow through, boxes with Dirichlet ends along z (nz + 1 z faces), and seeded
+random multi-block layouts.
 """
 import numpy as np
 import pytest
@@ -68,7 +69,7 @@ def _cases():
         (W.lshape(24, 8, 1.5, 1.0), True),
         (W.box(48, 40, 10, 0.75, 0.625, 0.15, "DD", "NN", "DD", xfactor=1.2, name="box_DD_NN_DDz"), True),
         (W.box(40, 36, 8, 0.6, 0.5, 0.12, "PP", "ND", "NN", yfactor=1.4, name="box_PP_ND_NNz"), True),
-    ]
+    ] + [(W.random_layout(seed), True) for seed in (3, 11, 100, 102)]  # seeded layouts, two periodic rings
 
 
 @pytest.mark.parametrize("prob,closed", _cases(), ids=lambda c: getattr(c, "name", str(c)))
