@@ -3,8 +3,9 @@
 // on the host pass only).  It runs no HIP call: validation, connectivity,
 // congruence, the multigrid hierarchy, modal shifts (Eq. (9), with the
 // Helmholtz term), transform tables (Table 1), the Jacobi eigen-solver of the
-// coarsest plane and the tanh face mapping, over valid layouts and a set of
-// invalid descriptors that must be refused with a message.
+// coarsest plane and the tanh face mapping, over valid layouts (hand-built and
+// seeded random ones) and a set of invalid descriptors that must be refused
+// with a message.
 #include <cmath>
 #include <cstdio>
 #include <random>
@@ -127,6 +128,56 @@ void valid_layouts() {
     CHECK(build(r, 4, N, N, 0.0, &err) == MBP_OK, "odd ring: %s", err.c_str());
 }
 
+// Seeded random layouts: rows and columns of 2-4 joined blocks (some closed
+// into periodic rings), L shapes and 2 x 2 grids, with blocks from one cell
+// wide to 160 cells, stretched faces across the joins and random walls.  Every
+// one must plan, with its coarsest plane within the dense-solve limit.
+void random_layouts() {
+    std::mt19937 rng(2106);
+    auto uni = [&](int a, int b) { return std::uniform_int_distribution<int>(a, b)(rng); };
+    auto wall = [&]() { return uni(0, 1) ? D : N; };
+    const int zp[5][2] = {{P, P}, {N, N}, {D, D}, {N, D}, {D, N}};
+    const double h = 1.0 / 32;
+    std::string err;
+    for (int s = 0; s < 240; ++s) {
+        const int scale = (s % 3 == 2) ? 4 : 1;
+        auto width = [&]() { return uni(0, 9) < 3 ? uni(1, 5) : uni(6, 40) * scale; };
+        const int shape = s % 4;
+        const double fy = 0.2 * uni(0, 4);
+        Layout L;
+        if (shape < 2) {  // a row (joined in x) or a column (joined in y)
+            const int nb = uni(2, 4), cross = width();
+            const bool ring = uni(0, 3) == 0;
+            int at = 1;
+            double a0 = 0.0;
+            for (int b = 0; b < nb; ++b) {
+                const int len = width();
+                const double a1 = a0 + len * h;
+                const int lo = b == 0 ? (ring ? P : wall()) : C, hi = b == nb - 1 ? (ring ? P : wall()) : C;
+                if (shape == 0)
+                    L.add(at, 1, len, cross, a0, a1, 0.0, cross * h, lo, hi, wall(), wall(), fy);
+                else
+                    L.add(1, at, cross, len, 0.0, cross * h, a0, a1, wall(), wall(), lo, hi, fy);
+                at += len;
+                a0 = a1;
+            }
+        } else {  // an L (three blocks) or a 2 x 2 grid
+            const int w0 = width(), w1 = width(), h0 = width(), h1 = width();
+            const double x1 = w0 * h, x2 = (w0 + w1) * h, y1 = h0 * h, y2 = (h0 + h1) * h;
+            const bool grid = shape == 3;
+            L.add(1, 1, w0, h0, 0.0, x1, 0.0, y1, wall(), C, wall(), C, fy);
+            L.add(1 + w0, 1, w1, h0, x1, x2, 0.0, y1, C, wall(), wall(), grid ? C : wall(), fy);
+            L.add(1, 1 + h0, w0, h1, 0.0, x1, y1, y2, wall(), grid ? C : wall(), C, wall(), fy);
+            if (grid) L.add(1 + w0, 1 + h0, w1, h1, x1, x2, y1, y2, C, wall(), C, wall(), fy);
+        }
+        const int* z = zp[s % 5];
+        const int nz = 2 * uni(1, 8);
+        int nlev = 0;
+        const int st = build(L, nz, z[0], z[1], s % 7 == 0 ? 2.5 : 0.0, &err, &nlev);
+        CHECK(st == MBP_OK, "random layout %d (shape %d, %zu blocks): %s", s, shape, L.b.size(), err.c_str());
+    }
+}
+
 void invalid_layouts() {
     std::string err;
     Layout box;
@@ -229,6 +280,7 @@ void tanh_faces() {
 
 int main() {
     valid_layouts();
+    random_layouts();
     invalid_layouts();
     eigen();
     tanh_faces();
