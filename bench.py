@@ -51,6 +51,8 @@ def _workload(name: str):
         return W.config3(), W.CONFIG_SEEDS[3], W.CONFIG_DIST[3]
     if name == "cube32":
         return W.config1(), W.CONFIG_SEEDS[1], W.CONFIG_DIST[1]
+    if name == "obstacle8":  # the headline's obstacle sub-record: 64 cells per obstacle side, nz = 576
+        return W.obstacle8(64, 576), 6, "normal"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -656,7 +658,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "lshape", "box", "cube32", "batch64", "serve"])
+                    choices=["headline", "lshape", "box", "cube32", "obstacle8", "batch64", "serve"])
     ap.add_argument("--requests", type=int, default=1000, help="serve: requests in the stream")
     ap.add_argument("--slots", type=int, default=8, help="serve: concurrent requests")
     ap.add_argument("--server-gb", type=float, default=96.0, help="serve: plan memory budget (GiB)")
