@@ -68,6 +68,11 @@ class PlanSummary(C.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libmbp.so not built at {LIB_PATH}; run python paper_2106_03583_amd/build.py")
+    # torch carries its own HIP runtime under the same soname as the system
+    # one libmbp.so links against.  Loaded first, it is the one runtime of the
+    # process and libmbp.so binds to it; the other way round the process ends
+    # up with the system runtime under torch, and the library finds no device.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P, I, D, VP = C.c_void_p, C.c_int, C.c_double, C.c_void_p
     sig = {

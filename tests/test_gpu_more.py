@@ -187,3 +187,27 @@ def test_batch_random_layouts(torch_cuda, mbp):
     probs = [W.random_layout(seed) for seed in range(40)]
     fs, got, singles, infos, sched = _run_batch(torch_cuda, mbp, probs, 900)
     _check_all(probs, fs, got, singles, infos)
+
+
+# The package imported before torch (a fresh process, so nothing has loaded
+# a HIP runtime yet) must still find the device and solve: the package loads
+# torch's runtime ahead of its library.
+def test_import_before_torch(torch_cuda):
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_2106_03583_amd as m\n"
+        "import torch, numpy as np, workloads as W\n"
+        "prob = W.box(48, 40, 8, 1.0, 0.8, 0.5, 'DD', 'NN', 'PP', name='order')\n"
+        "f = W.rhs(prob, 3)\n"
+        "plan = m.Plan(prob)\n"
+        "p = torch.zeros(plan.ncells, dtype=torch.float64, device='cuda')\n"
+        "info = plan.solve(torch.from_numpy(f).cuda(), p, rtol=1e-10, flags=m.RETIRE)\n"
+        "print('status', info.status, 'residual', info.rel_residual, flush=True)\n"
+        "sys.exit(0 if info.status == 0 and info.rel_residual <= 1e-10 else 1)\n" % root)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240, cwd=root)
+    print(r.stdout, r.stderr[-2000:], flush=True)
+    assert r.returncode == 0, r.stdout + r.stderr[-2000:]
